@@ -1,0 +1,258 @@
+"""NumPy front end of the C reference oracle (test infrastructure only).
+
+Only the tests, the smoke check and the benchmark's CPU-baseline leg import
+this module.  It loads `liboracle.so`, built from `araullo_oracle.c` with gcc
+(`build()`), and marshals NumPy arrays; all arithmetic is in the C file.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from typing import Optional, Tuple
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "araullo_oracle.c")
+LIB = os.path.join(HERE, "liboracle.so")
+
+CFLAGS = ["-O2", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off", "-fno-fast-math",
+          "-fopenmp", "-Wall", "-Wno-unknown-pragmas"]
+
+
+def build(verbose: bool = False) -> str:
+    """Compile the oracle with gcc (always recompiles)."""
+    tmp = LIB + ".tmp"
+    cmd = ["gcc", *CFLAGS, SRC, "-o", tmp, "-lm"]
+    if verbose:
+        print(" ".join(cmd))
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, LIB)
+    return LIB
+
+
+_lib = None
+
+F32P = np.ctypeslib.ndpointer(np.float32, flags="C_CONTIGUOUS")
+F64P = np.ctypeslib.ndpointer(np.float64, flags="C_CONTIGUOUS")
+I32P = np.ctypeslib.ndpointer(np.int32, flags="C_CONTIGUOUS")
+I64P = np.ctypeslib.ndpointer(np.int64, flags="C_CONTIGUOUS")
+c_i32, c_i64, c_f32, c_f64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_float, ctypes.c_double
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+            build()
+        L = ctypes.CDLL(LIB)
+        L.orc_bin_constants.argtypes = [c_f32, c_i32, ctypes.POINTER(c_f32), ctypes.POINTER(c_f32),
+                                        ctypes.POINTER(c_f64)]
+        L.orc_window_bins.argtypes = [c_f64, c_i32, c_f64, c_f64, ctypes.POINTER(c_i32), ctypes.POINTER(c_i32)]
+        L.orc_window_bins.restype = c_i32
+        L.orc_roi_gather.argtypes = [F32P, c_i64, F32P, c_f32, ctypes.c_void_p, c_i64]
+        L.orc_roi_gather.restype = c_i64
+        L.orc_sdm_hist.argtypes = [F32P, c_i64, F32P, c_f32, c_i32, I32P]
+        L.orc_amplitudes.argtypes = [I32P, c_i32, F64P]
+        L.orc_signatures.argtypes = [F32P, c_i64, F32P, c_i64, c_f32, F32P, c_i32, c_i32, I32P, c_i32, F64P,
+                                     I32P, c_i32]
+        L.orc_sdm_debug.argtypes = [F32P, c_i64, c_f32, F32P, c_i32, c_i32, I32P, F64P]
+        L.orc_normalise.argtypes = [F32P, c_i64, c_i32, c_i32, F64P]
+        L.orc_index_topk.argtypes = [F64P, c_i64, F64P, c_i64, c_i64, c_i32, I32P, F64P, c_i32]
+        L.orc_ssd_pairs.argtypes = [F64P, F64P, c_i64, I64P, I64P, c_i64, F64P]
+        L.orc_disorientation_cubic.argtypes = [F64P, F64P, c_i64, F64P]
+        L.orc_cubic_group_out.argtypes = [F64P]
+        L.orc_rotated_nodes.argtypes = [F64P, c_i64, F32P, c_i32, I32P, c_i32]
+        L.orc_sf_amplitudes.argtypes = [F32P, c_i64, F64P, F32P, c_i32, F64P, c_i32, F64P]
+        L.orc_sf_score.argtypes = [F32P, c_i64, F64P, F32P, c_i32, F64P, c_i32, F64P]
+        L.orc_sf_score.restype = c_f64
+        L.orc_sf_grad_fd.argtypes = [F32P, c_i64, F64P, F32P, c_i32, F64P, c_i32, F64P, c_f64, F64P]
+        L.orc_sf_batch.argtypes = [F32P, I64P, c_i64, F64P, F32P, c_i32, F64P, c_i32, F64P, c_f64, F64P,
+                                   ctypes.c_void_p, c_i32]
+        _lib = L
+    return _lib
+
+
+def _f32(a):
+    return np.ascontiguousarray(a, dtype=np.float32)
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _i32(a):
+    return np.ascontiguousarray(a, dtype=np.int32)
+
+
+def default_threads() -> int:
+    return max(1, min(os.cpu_count() or 1, 16))
+
+
+# ---------------------------------------------------------------- signatures
+def bin_constants(radius: float, nbins: int) -> Tuple[float, float, float]:
+    s, c, w = c_f32(), c_f32(), c_f64()
+    lib().orc_bin_constants(radius, nbins, ctypes.byref(s), ctypes.byref(c), ctypes.byref(w))
+    return s.value, c.value, w.value
+
+
+def window_bins(radius: float, nbins: int, d_min: float, d_max: float) -> Tuple[int, int]:
+    lo, hi = c_i32(), c_i32()
+    rc = lib().orc_window_bins(radius, nbins, d_min, d_max, ctypes.byref(lo), ctypes.byref(hi))
+    if rc != 0:
+        raise ValueError(f"empty or out-of-range window for d in [{d_min}, {d_max}]")
+    return lo.value, hi.value
+
+
+def windows_for(radius: float, nbins: int, spacings) -> np.ndarray:
+    return np.array([window_bins(radius, nbins, float(a), float(b)) for a, b in np.asarray(spacings)],
+                    dtype=np.int32)
+
+
+def roi_gather(positions, centre, radius: float) -> np.ndarray:
+    p = _f32(positions)
+    c = _f32(centre).reshape(3)
+    n = lib().orc_roi_gather(p, len(p), c, radius, None, 0)
+    out = np.zeros((max(n, 1), 3), np.float32)
+    lib().orc_roi_gather(p, len(p), c, radius, out.ctypes.data, n)
+    return out[:n]
+
+
+def sdm_hist(rel, v, radius: float, nbins: int) -> np.ndarray:
+    rel = _f32(rel).reshape(-1, 3)
+    h = np.zeros(nbins, np.int32)
+    lib().orc_sdm_hist(rel, len(rel), _f32(v).reshape(3), radius, nbins, h)
+    return h
+
+
+def amplitudes(hist) -> np.ndarray:
+    h = _i32(hist)
+    a = np.zeros(len(h) // 2 + 1, np.float64)
+    lib().orc_amplitudes(h, len(h), a)
+    return a
+
+
+def signatures(positions, centres, radius: float, directions, nbins: int, windows,
+               threads: Optional[int] = None) -> Tuple[np.ndarray, np.ndarray]:
+    p, c, d, w = _f32(positions), _f32(centres).reshape(-1, 3), _f32(directions), _i32(windows).reshape(-1, 2)
+    n_roi, n_dir, n_win = len(c), len(d), len(w)
+    img = np.zeros((n_roi, n_win, n_dir), np.float64)
+    cnt = np.zeros(n_roi, np.int32)
+    lib().orc_signatures(p, len(p), c, n_roi, radius, d, n_dir, nbins, w, n_win, img, cnt,
+                         threads or default_threads())
+    return img, cnt
+
+
+def sdm_debug(rel, radius: float, directions, nbins: int) -> Tuple[np.ndarray, np.ndarray]:
+    rel = _f32(rel).reshape(-1, 3)
+    d = _f32(directions)
+    h = np.zeros((len(d), nbins), np.int32)
+    a = np.zeros((len(d), nbins // 2 + 1), np.float64)
+    lib().orc_sdm_debug(rel, len(rel), radius, d, len(d), nbins, h, a)
+    return h, a
+
+
+# ---------------------------------------------------------------- indexing
+def normalise(images) -> np.ndarray:
+    x = _f32(images)
+    n, n_win, n_dir = x.shape
+    out = np.zeros_like(x, dtype=np.float64)
+    lib().orc_normalise(x, n, n_win, n_dir, out)
+    return out
+
+
+def index_topk(S_hat, L_hat, k: int, threads: Optional[int] = None) -> Tuple[np.ndarray, np.ndarray]:
+    S = _f64(S_hat).reshape(len(S_hat), -1)
+    L = _f64(L_hat).reshape(len(L_hat), -1)
+    assert S.shape[1] == L.shape[1]
+    idx = np.zeros((len(S), k), np.int32)
+    sc = np.zeros((len(S), k), np.float64)
+    lib().orc_index_topk(S, len(S), L, len(L), S.shape[1], k, idx, sc, threads or default_threads())
+    return idx, sc
+
+
+def ssd_pairs(S_hat, L_hat, roi, libidx) -> np.ndarray:
+    S = _f64(S_hat).reshape(len(S_hat), -1)
+    L = _f64(L_hat).reshape(len(L_hat), -1)
+    r = np.ascontiguousarray(roi, np.int64)
+    l = np.ascontiguousarray(libidx, np.int64)
+    out = np.zeros(len(r), np.float64)
+    lib().orc_ssd_pairs(S, L, S.shape[1], r, l, len(r), out)
+    return out
+
+
+def disorientation_cubic(qa, qb) -> np.ndarray:
+    a = _f64(qa).reshape(-1, 4)
+    b = _f64(qb).reshape(-1, 4)
+    out = np.zeros(len(a), np.float64)
+    lib().orc_disorientation_cubic(a, b, len(a), out)
+    return out
+
+
+def cubic_group() -> np.ndarray:
+    out = np.zeros((24, 4), np.float64)
+    lib().orc_cubic_group_out(out)
+    return out
+
+
+def rotated_nodes(quats, directions, threads: Optional[int] = None) -> np.ndarray:
+    q = _f64(quats).reshape(-1, 4)
+    d = _f32(directions)
+    lut = np.zeros((len(q), len(d)), np.int32)
+    lib().orc_rotated_nodes(q, len(q), d, len(d), lut, threads or default_threads())
+    return lut
+
+
+def library_images(reference, phase_of, quats, directions, threads: Optional[int] = None) -> np.ndarray:
+    """Rotated reference images [n_lib][n_win][n_dir]: the value at node v of
+    entry l is reference[phase_of[l]][w][lut[l][v]] (nearest rotated node)."""
+    ref = np.asarray(reference)
+    lut = rotated_nodes(quats, directions, threads)
+    ph = np.asarray(phase_of, np.int64)
+    out = np.empty((len(lut), ref.shape[1], ref.shape[2]), ref.dtype)
+    for l in range(len(lut)):
+        out[l] = ref[ph[l]][:, lut[l]]
+    return out
+
+
+# ---------------------------------------------------------------- structure factor
+def sf_amplitudes(rel, q, directions, freqs) -> np.ndarray:
+    rel = _f32(rel).reshape(-1, 3)
+    d = _f32(directions)
+    f = _f64(freqs)
+    out = np.zeros((len(f), len(d)), np.float64)
+    lib().orc_sf_amplitudes(rel, len(rel), _f64(q), d, len(d), f, len(f), out)
+    return out
+
+
+def sf_score(rel, q, directions, freqs, target) -> float:
+    rel = _f32(rel).reshape(-1, 3)
+    d = _f32(directions)
+    f = _f64(freqs)
+    return lib().orc_sf_score(rel, len(rel), _f64(q), d, len(d), f, len(f), _f64(target))
+
+
+def sf_grad_fd(rel, q, directions, freqs, target, h: float = 1e-6) -> np.ndarray:
+    rel = _f32(rel).reshape(-1, 3)
+    d = _f32(directions)
+    f = _f64(freqs)
+    g = np.zeros(4, np.float64)
+    lib().orc_sf_grad_fd(rel, len(rel), _f64(q), d, len(d), f, len(f), _f64(target), h, g)
+    return g
+
+
+def sf_batch(rel, offsets, quats, directions, freqs, targets, h: float = 1e-6, grad: bool = True,
+             threads: Optional[int] = None):
+    rel = _f32(rel).reshape(-1, 3)
+    off = np.ascontiguousarray(offsets, np.int64)
+    q = _f64(quats).reshape(-1, 4)
+    n = len(q)
+    d = _f32(directions)
+    f = _f64(freqs).reshape(n, -1)
+    T = _f64(targets).reshape(n, f.shape[1], len(d))
+    sc = np.zeros(n, np.float64)
+    g = np.zeros((n, 4), np.float64) if grad else None
+    lib().orc_sf_batch(rel, off, n, q, d, len(d), f, f.shape[1], T, h, sc,
+                       g.ctypes.data if grad else None, threads or default_threads())
+    return sc, g
