@@ -1,0 +1,302 @@
+/*
+ * araullo.h - C ABI of the MI355X (gfx950) implementation of the real-space
+ * signature and orientation-indexing method of Kuehbach, Kasemer, Gault and
+ * Breen, "On Open and Strong-Scaling Tools for Atom Probe Crystallography:
+ * High-Throughput Methods for Indexing Crystal Structure and Orientation"
+ * (arXiv 2009.00735).
+ *
+ * Conventions for every entry point:
+ *  - Lengths are in nm.  Arrays are C-contiguous, row-major.
+ *  - "device" pointers are HIP device allocations on the context's device,
+ *    owned by the caller; the library reads/writes them in stream order and
+ *    never frees or retains them after the stream has passed the call.
+ *    "host" pointers are ordinary host memory, read or written before the
+ *    function returns.
+ *  - All arguments are validated before any work is queued, so a call that
+ *    returns an error has written nothing.  Errors: AR_EINVAL (bad argument),
+ *    AR_ENOMEM (a workspace allocation failed), AR_EDEVICE (a HIP runtime
+ *    error, including an earlier asynchronous fault), AR_EUNSUPPORTED.
+ *    ar_last_error() returns a thread-local message for the last failure.
+ *  - No exceptions cross this boundary.
+ *  - Work is queued on `stream` (a hipStream_t passed as void*; NULL is the
+ *    null stream).  Calls that must know a data-dependent size on the host
+ *    (marked "synchronises") wait for the stream.
+ *  - Calls on one context are not thread-safe; use one context per thread.
+ */
+#ifndef ARAULLO_H
+#define ARAULLO_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    AR_OK = 0,
+    AR_EINVAL = -1,
+    AR_ENOMEM = -2,
+    AR_EDEVICE = -3,
+    AR_EUNSUPPORTED = -4
+} ar_status;
+
+typedef struct ar_context ar_context;
+typedef struct ar_library ar_library;
+typedef struct ar_plan ar_plan;
+
+/* Message of the last failed call on this thread ("" if none). */
+const char *ar_last_error(void);
+
+/* Version string of the library build. */
+const char *ar_version(void);
+
+/* Create a context on HIP device `device`: it owns reusable device
+ * workspace and the tables the kernels read.  Destroy frees them. */
+ar_status ar_context_create(int device, ar_context **out);
+ar_status ar_context_destroy(ar_context *ctx);
+
+/*
+ * Window of DFT indices for a lattice-spacing interval [d_min, d_max]
+ * (supplement, reconstruction parameters: the signature takes the highest
+ * amplitude in the bin interval of a spacing range; Fig. 2 caption: spacing
+ * d sits at index L/d with L = 2R + 2dR the histogram span and
+ * dR = R / (nbins/2 - 1) the bin width of Eq. (1)).
+ * Result: k_lo = ceil(L/d_max), k_hi = floor(L/d_min), evaluated in FP64.
+ * Host call.  AR_EINVAL unless nbins is a power of two in [256, 4096],
+ * radius > 0, 0 < d_min <= d_max and 1 <= k_lo <= k_hi <= nbins/2.
+ */
+ar_status ar_window_bins(double radius, int32_t nbins, double d_min, double d_max,
+                         int32_t *k_lo, int32_t *k_hi);
+
+/*
+ * ROI query (Sec. 2.1: every spherical ROI of radius R collects the atoms
+ * around its centre; supplement, cost model: the query precedes the
+ * projections).  An atom belongs to ROI r iff, in FP32,
+ * fmaf(dz,dz,fmaf(dy,dy,dx*dx)) <= (float)(R*R) with d = p - c_r.
+ *   positions  device float [n_atoms][3]
+ *   centres    device float [n_roi][3]
+ *   offsets    device int64 [n_roi+1], out: CSR row starts (offsets[0] = 0)
+ *   rel        device float [cap][4] or NULL, out: relative coordinates
+ *              d = p - c (FP32 subtraction), 4th component 0; rows of ROI r
+ *              are rel[offsets[r] .. offsets[r+1]); within a ROI atoms come
+ *              in a fixed (deterministic) order
+ *   total      host int64, out: offsets[n_roi]
+ * With rel == NULL only offsets and total are produced.  AR_EINVAL if
+ * rel != NULL and cap < total (offsets and total are still written).
+ * Synchronises.
+ */
+ar_status ar_roi_gather(ar_context *ctx, const float *positions, int64_t n_atoms,
+                        const float *centres, int64_t n_roi, float radius,
+                        int64_t *offsets, float *rel, int64_t cap, int64_t *total,
+                        void *stream);
+
+/*
+ * Real-space signatures (Sec. 2.2, RSP paragraph and Eq. (1); supplement,
+ * "Controlled windowing of the SDMs" and reconstruction parameters).  For
+ * every ROI r and direction v: the ROI's atoms are projected on v and binned
+ * by Eq. (1) into nbins bins spanning [-(R+dR), R+dR], dR = R/(nbins/2-1),
+ *   s = fmaf(vz,dz,fmaf(vy,dy,vx*dx)),  t = (s + (float)(R+dR)) *
+ *   (float)(nbins/(2R+2dR)),  b = clamp(floor(t), 0, nbins-1)   (FP32),
+ * the histogram is Fourier transformed, and
+ *   images[r][w][v] = max_{k_lo(w) <= k <= k_hi(w)} |X_k|,
+ *   X_k = sum_n h_n exp(-2 pi i k n / nbins)                     (FP32).
+ *   positions  device float [n_atoms][3]
+ *   centres    device float [n_roi][3]
+ *   directions device float [n_dir][3], unit vectors
+ *   nbins      2^m, m in [8, 12]
+ *   windows    host int32 [n_win][2] inclusive (k_lo, k_hi), 1 <= k_lo <=
+ *              k_hi <= nbins/2, n_win in [1, 16]
+ *   images     device float [n_roi][n_win][n_dir], out
+ *   roi_counts device int32 [n_roi] or NULL, out: atoms per ROI
+ * ROIs with no atoms get zero images.  Any atom count is accepted (atoms are
+ * streamed through registers in chunks).  Synchronises (ROI query).
+ */
+ar_status araullo_signatures(ar_context *ctx, const float *positions, int64_t n_atoms,
+                             const float *centres, int64_t n_roi, float radius,
+                             const float *directions, int32_t n_dir, int32_t nbins,
+                             const int32_t *windows, int32_t n_win,
+                             float *images, int32_t *roi_counts, void *stream);
+
+/*
+ * Same Eq. (1) histograms and spectra as araullo_signatures, written out in
+ * full for inspection and parity checks.
+ *   hist  device int32 [n_roi][n_dir][nbins] or NULL, out
+ *   amp   device float [n_roi][n_dir][nbins/2+1] or NULL, out: |X_k|
+ * Synchronises.
+ */
+ar_status araullo_sdm(ar_context *ctx, const float *positions, int64_t n_atoms,
+                      const float *centres, int64_t n_roi, float radius,
+                      const float *directions, int32_t n_dir, int32_t nbins,
+                      int32_t *hist, float *amp, void *stream);
+
+/*
+ * Signatures from an already gathered CSR (output of ar_roi_gather) with the
+ * plain per-launch kernel: one workgroup per (ROI, direction tile).
+ *   rel      device float [total][4], offsets device int64 [n_roi+1]
+ * Other arguments as araullo_signatures.  Does not synchronise.
+ */
+ar_status araullo_signatures_csr(ar_context *ctx, const float *rel, const int64_t *offsets,
+                                 int64_t n_roi, float radius, const float *directions,
+                                 int32_t n_dir, int32_t nbins, const int32_t *windows,
+                                 int32_t n_win, float *images, void *stream);
+
+/*
+ * Batched signatures for ROIs of uneven atom counts (e.g. clipped at the
+ * specimen surface): one persistent launch whose workgroups pull
+ * (ROI, direction-chunk) items, largest ROIs first, from a device queue
+ * (the paper's scaling limits came from load imbalance, supplement,
+ * "Scalability limits").  A plan fixes the shapes, holds its workspace,
+ * tunes its tile shape on first use (ar_signature_plan_tune) and replays the
+ * whole batch as one captured HIP graph.
+ *   max_roi, max_total  capacity of the plan (ROIs, gathered atoms)
+ * The run call takes a gathered CSR (ar_roi_gather) and writes the same
+ * images as araullo_signatures_csr, bit for bit.
+ */
+ar_status ar_signature_plan_create(ar_context *ctx, int64_t max_roi, int64_t max_total,
+                                   int32_t n_dir, int32_t nbins, int32_t n_win, ar_plan **out);
+ar_status ar_signature_plan_destroy(ar_plan *plan);
+/* Time the candidate tile shapes on the given batch and keep the fastest.
+ * Writes images as a side effect. Synchronises. */
+ar_status ar_signature_plan_tune(ar_plan *plan, const float *rel, const int64_t *offsets,
+                                 int64_t n_roi, float radius, const float *directions,
+                                 const int32_t *windows, float *images, void *stream);
+/* Chosen tile: directions per work item and atoms-per-lane register chunk. */
+ar_status ar_signature_plan_config(const ar_plan *plan, int32_t *dirs_per_item,
+                                   int32_t *atoms_per_lane, int32_t *waves_per_group);
+/* Run the batch. The host reads roi sizes once per new `offsets` pointer or
+ * n_roi to order the queue (synchronises then); with use_graph != 0 the
+ * launch sequence is captured once per argument set and replayed. */
+ar_status ar_signature_plan_run(ar_plan *plan, const float *rel, const int64_t *offsets,
+                                int64_t n_roi, float radius, const float *directions,
+                                const int32_t *windows, float *images, int32_t use_graph,
+                                void *stream);
+
+/*
+ * Indexing library (Sec. 2.4; supplement, "Indexing algorithm"): rotated
+ * reference images, normalised individually by their maximum over the
+ * directions of each window (an all-zero image stays zero), kept as a BF16
+ * copy for the correlation plus per-entry squared norms of that copy and
+ * per-(entry, window) reciprocal maxima for the FP32 rescoring.
+ *   ref_images device float [n_lib][n_win][n_dir]; must stay valid and
+ *              unchanged while the library exists (FP32 rescoring reads it)
+ * The library owns its BF16 copy; destroy frees it.
+ */
+ar_status ar_library_create(ar_context *ctx, const float *ref_images, int64_t n_lib,
+                            int32_t n_win, int32_t n_dir, void *stream, ar_library **out);
+ar_status ar_library_destroy(ar_library *lib);
+
+/*
+ * Orientation indexing: the k library entries with the smallest sum of
+ * squared differences of the normalised images (supplement, Eq. S1, taken
+ * over all nodes of all windows),
+ *   Delta(r,l) = sum_{w,v} (S_r[w][v]/max_v S_r[w] - L_l[w][v]/max_v L_l[w])^2.
+ * Candidates come from a BF16-input / FP32-accumulate MFMA correlation
+ * (score = |L_l|^2 - 2 <S_r, L_l>) keeping the best `cand` (>= k, <= 64)
+ * per ROI, which are then rescored in FP32 from the FP32 images; the output
+ * is sorted ascending by (FP32 Delta, library index).
+ *   images    device float [n_roi][n_win][n_dir] (raw signatures)
+ *   k         1 .. 64 outputs per ROI
+ *   top_idx   device int32 [n_roi][k], out
+ *   top_score device float [n_roi][k], out: FP32 Delta
+ * Does not synchronise.
+ */
+ar_status index_orientations(ar_context *ctx, const float *images, int64_t n_roi,
+                             const ar_library *lib, int32_t k, int32_t *top_idx, float *top_score,
+                             void *stream);
+
+/* As index_orientations with an explicit candidate count `cand`
+ * (k <= cand <= 64; index_orientations uses cand = max(k, 16)), optionally
+ * returning the BF16-stage candidates before rescoring.
+ *   cand_idx  device int32 [n_roi][cand] or NULL, out */
+ar_status index_orientations_ex(ar_context *ctx, const float *images, int64_t n_roi,
+                                const ar_library *lib, int32_t k, int32_t cand, int32_t *top_idx,
+                                float *top_score, int32_t *cand_idx, void *stream);
+
+/*
+ * Disorientation angle in degrees under cubic symmetry (supplement,
+ * "Creation of test orientations": the misorientation with the smallest
+ * rotation angle among the symmetrically equivalent ones), FP64:
+ *   deg[i] = 2 acos(min(1, max_S |(qa_i^-1 * qb_i * S).w|)) * 180/pi
+ * over the 24 proper rotations S of m-3m.  Quaternions (w, x, y, z),
+ * need not be normalised.
+ *   qa, qb device double [n][4];  deg device double [n], out
+ */
+ar_status ar_disorientation_cubic(const double *qa, const double *qb, int64_t n, double *deg,
+                                  void *stream);
+
+/*
+ * Rotated reference images (supplement, "Indexing algorithm": rotated nodes
+ * are replaced by their closest neighbouring mesh node):
+ *   out[l][w][v] = reference[phase[l]][w][u*],
+ *   u* = argmax_u n_u . (R(q_l)^T n_v)   (ties to the lower index).
+ * Candidates are ranked in FP32 and those within 1e-5 of the best re-ranked
+ * in FP64.
+ *   reference  device float [n_phase][n_win][n_dir]
+ *   directions device float [n_dir][3]
+ *   quats      device double [n_lib][4] (w, x, y, z), phase device int32 [n_lib]
+ *   out        device float [n_lib][n_win][n_dir]
+ */
+ar_status ar_rotate_reference(ar_context *ctx, const float *reference, int32_t n_phase, int32_t n_win,
+                              const float *directions, int32_t n_dir, const double *quats,
+                              const int32_t *phase, int64_t n_lib, float *out, void *stream);
+
+/*
+ * Structure-factor matching score and its gradient with respect to the ROI
+ * orientation quaternion, built on the direct Fourier transform of Eq. (2)
+ * (Sec. 2.2, FSP paragraph) evaluated on spherical shells |k| = f_w along
+ * the rotated mesh directions u_v = R(q/|q|) n_v:
+ *   F_{w,v} = sum_j exp(-2 pi i f_w u_v . x_j),  A = |F| / N_w,
+ *   J(q) = sum_{w,v} (A_{w,v} - T_{p,w,v})^2,   p = phase of the ROI,
+ *   grad = dJ/dq (4-vector, orthogonal to q).
+ * Terms with |F| < 1e-12 N_w add nothing to the gradient.
+ *   rel, offsets  gathered CSR (ar_roi_gather)
+ *   quats         device float [n_roi][4]
+ *   phase         device int32 [n_roi]
+ *   freqs         device float [n_phase][n_freq]
+ *   targets       device float [n_phase][n_freq][n_dir]
+ *   score         device float [n_roi], out
+ *   grad          device float [n_roi][4] or NULL, out (NULL: forward only)
+ * n_freq in [1, 8].  Does not synchronise.
+ */
+ar_status ar_sf_score_grad(ar_context *ctx, const float *rel, const int64_t *offsets, int64_t n_roi,
+                           const float *quats, const int32_t *phase, const float *directions,
+                           int32_t n_dir, const float *freqs, const float *targets, int32_t n_phase,
+                           int32_t n_freq, float *score, float *grad, void *stream);
+
+/* FP64 forward of the same score (for finite-difference checks):
+ *   quats device double [n_roi][4]; score device double [n_roi], out. */
+ar_status ar_sf_score_f64(ar_context *ctx, const float *rel, const int64_t *offsets, int64_t n_roi,
+                          const double *quats, const int32_t *phase, const float *directions,
+                          int32_t n_dir, const double *freqs, const double *targets, int32_t n_phase,
+                          int32_t n_freq, double *score, void *stream);
+
+/* Structure-factor amplitudes A[r][w][v] (FP32) for given orientations,
+ * e.g. to build targets from reference crystals.
+ *   amp device float [n_roi][n_freq][n_dir], out; freqs per ROI's phase. */
+ar_status ar_sf_amplitudes(ar_context *ctx, const float *rel, const int64_t *offsets, int64_t n_roi,
+                           const float *quats, const int32_t *phase, const float *directions,
+                           int32_t n_dir, const float *freqs, int32_t n_phase, int32_t n_freq,
+                           float *amp, void *stream);
+
+/*
+ * Orientation refinement below the library grid: `steps` iterations of
+ * projected gradient descent on J (ar_sf_score_grad) with a per-ROI
+ * backtracking step: a trial q' = normalise(q - a g) is accepted iff
+ * J(q') <= J(q) - 1e-4 a |g|^2, then a grows by 1.5; otherwise a halves
+ * and q stays.  Every iteration evaluates J and its gradient once at the
+ * trial points of all ROIs.  Starting step a0 (radian-scale units of q).
+ *   quats  device float [n_roi][4], in: start, out: refined
+ *   score  device float [n_roi] or NULL, out: final J
+ * Does not synchronise.
+ */
+ar_status ar_refine_orientations(ar_context *ctx, const float *rel, const int64_t *offsets,
+                                 int64_t n_roi, float *quats, const int32_t *phase,
+                                 const float *directions, int32_t n_dir, const float *freqs,
+                                 const float *targets, int32_t n_phase, int32_t n_freq,
+                                 int32_t steps, float a0, float *score, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ARAULLO_H */

@@ -57,7 +57,7 @@ def lib():
         L.orc_amplitudes.argtypes = [I32P, c_i32, F64P]
         L.orc_signatures.argtypes = [F32P, c_i64, F32P, c_i64, c_f32, F32P, c_i32, c_i32, I32P, c_i32, F64P,
                                      I32P, c_i32]
-        L.orc_sdm_debug.argtypes = [F32P, c_i64, c_f32, F32P, c_i32, c_i32, I32P, F64P]
+        L.orc_sdm_debug.argtypes = [F32P, c_i64, c_f32, F32P, c_i32, c_i32, I32P, ctypes.c_void_p]
         L.orc_normalise.argtypes = [F32P, c_i64, c_i32, c_i32, F64P]
         L.orc_index_topk.argtypes = [F64P, c_i64, F64P, c_i64, c_i64, c_i32, I32P, F64P, c_i32]
         L.orc_ssd_pairs.argtypes = [F64P, F64P, c_i64, I64P, I64P, c_i64, F64P]
@@ -144,12 +144,13 @@ def signatures(positions, centres, radius: float, directions, nbins: int, window
     return img, cnt
 
 
-def sdm_debug(rel, radius: float, directions, nbins: int) -> Tuple[np.ndarray, np.ndarray]:
+def sdm_debug(rel, radius: float, directions, nbins: int, spectra: bool = True):
+    """Histograms [n_dir][nbins] and (if spectra) amplitudes [n_dir][nbins/2+1]."""
     rel = _f32(rel).reshape(-1, 3)
     d = _f32(directions)
     h = np.zeros((len(d), nbins), np.int32)
-    a = np.zeros((len(d), nbins // 2 + 1), np.float64)
-    lib().orc_sdm_debug(rel, len(rel), radius, d, len(d), nbins, h, a)
+    a = np.zeros((len(d), nbins // 2 + 1), np.float64) if spectra else None
+    lib().orc_sdm_debug(rel, len(rel), radius, d, len(d), nbins, h, a.ctypes.data if spectra else None)
     return h, a
 
 

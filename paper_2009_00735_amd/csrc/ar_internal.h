@@ -1,0 +1,106 @@
+// Internal declarations shared by the HIP translation units of libaraullo.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdarg.h>
+#include <stdint.h>
+
+#include <map>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "araullo.h"
+
+namespace ar {
+
+// Record a thread-local error message and return `s`.
+ar_status fail(ar_status s, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+void clear_error();
+
+#define AR_HIP(call)                                                                   \
+    do {                                                                               \
+        hipError_t e_ = (call);                                                        \
+        if (e_ != hipSuccess)                                                          \
+            return ::ar::fail(AR_EDEVICE, "%s failed: %s", #call, hipGetErrorString(e_)); \
+    } while (0)
+
+#define AR_TRY(expr)                                                                   \
+    do {                                                                               \
+        ar_status s_ = (expr);                                                         \
+        if (s_ != AR_OK) return s_;                                                    \
+    } while (0)
+
+#define AR_CHECK(cond, ...)                                                            \
+    do {                                                                               \
+        if (!(cond)) return ::ar::fail(AR_EINVAL, __VA_ARGS__);                        \
+    } while (0)
+
+// Grow-only device buffer.  Growing frees the old allocation (hipFree waits
+// for outstanding work on the device).
+struct DeviceBuffer {
+    void *ptr = nullptr;
+    size_t bytes = 0;
+    ~DeviceBuffer();
+    ar_status reserve(size_t n);
+    template <class T> T *as() const { return static_cast<T *>(ptr); }
+};
+
+// Eq. (1) constants, computed once in FP64 and rounded to FP32.
+struct BinConsts {
+    float shift;   // (float)(R + dR)
+    float scale;   // (float)(nbins / (2R + 2dR))
+};
+BinConsts bin_consts(float radius, int nbins);
+
+constexpr int kMaxWindows = 16;
+struct WindowSet {
+    int n;
+    int kmin, kmax;          // union of all windows
+    int lo[kMaxWindows];
+    int hi[kMaxWindows];
+};
+ar_status make_windows(const int32_t *windows, int32_t n_win, int32_t nbins, WindowSet *ws);
+
+bool valid_nbins(int32_t nbins);
+int log2i(int32_t x);
+
+}  // namespace ar
+
+struct ar_context {
+    int device = 0;
+    int cu_count = 0;
+    int lds_per_block = 0;
+    // gather workspace
+    ar::DeviceBuffer g_keys, g_vals, g_keys2, g_vals2, g_cell_start, g_sorted, g_counts, g_temp,
+        g_bbox, g_offsets;
+    // gathered CSR used by the position-taking signature entry points
+    ar::DeviceBuffer s_rel;
+    // indexing workspace
+    ar::DeviceBuffer i_bf16, i_inv, i_cand_idx, i_cand_score, i_merge_idx;
+    // refinement workspace
+    ar::DeviceBuffer r_partials, r_state;
+    // twiddle tables exp(-2 pi i j / nbins), j < nbins, per nbins
+    std::map<int, std::unique_ptr<ar::DeviceBuffer>> twiddles;
+    ar_status twiddle_table(int nbins, const float2 **out);
+};
+
+struct ar_library {
+    ar_context *ctx = nullptr;
+    const float *ref = nullptr;   // caller-owned FP32 raw images [n_lib][K]
+    int64_t n_lib = 0;
+    int32_t n_win = 0, n_dir = 0;
+    int64_t K = 0;                // n_win * n_dir
+    int64_t Kp = 0;               // padded to a multiple of the GEMM K tile
+    int64_t n_pad = 0;            // n_lib padded to a multiple of the GEMM N tile
+    ar::DeviceBuffer bf16;        // [n_pad][Kp] bf16, normalised
+    ar::DeviceBuffer norm2;       // [n_pad] float, |bf16 row|^2 (pad rows: +inf)
+    ar::DeviceBuffer inv_max;     // [n_lib][n_win] float, 1/max (0 for a zero image)
+};
+
+namespace ar {
+// internal entry points used across translation units
+ar_status gather_csr(ar_context *ctx, const float *positions, int64_t n_atoms, const float *centres,
+                     int64_t n_roi, float radius, int64_t *offsets, float *rel, int64_t cap,
+                     int64_t *total, hipStream_t stream);
+}

@@ -1,0 +1,244 @@
+// ROI query: atoms within radius R of each ROI centre, as a CSR of relative
+// coordinates (Sec. 2.1: spherical ROIs scan the dataset; supplement, cost
+// model: one neighbour query per ROI before the projections).
+//
+// GPU design: a uniform cell grid (cell edge R/2) over the box spanned by the
+// ROI centres +- R; atoms are bucketed by a stable radix sort on the cell id
+// (so the order inside a cell is the input order), each ROI is served by one
+// wavefront that walks the rows of cells overlapping its ball (+-1 cell of
+// slack against FP32 rounding of the cell index).  Rows of cells are
+// contiguous in the sorted array, so each row is one coalesced range.
+// Membership is decided exactly as the paper's single-precision test:
+// fmaf(dz,dz,fmaf(dy,dy,dx*dx)) <= (float)(R*R).
+#include <hipcub/hipcub.hpp>
+
+#include "ar_internal.h"
+
+namespace ar {
+namespace {
+
+struct Grid {
+    float ox, oy, oz, inv_h;
+    int nx, ny, nz;
+};
+
+__global__ __launch_bounds__(1024) void k_centre_bbox(const float *__restrict__ c, int64_t n,
+                                                      float *__restrict__ out)
+{
+    __shared__ float red[6][1024];
+    float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int64_t i = threadIdx.x; i < n; i += blockDim.x)
+        for (int a = 0; a < 3; ++a) {
+            float v = c[3 * i + a];
+            lo[a] = fminf(lo[a], v);
+            hi[a] = fmaxf(hi[a], v);
+        }
+    for (int a = 0; a < 3; ++a) {
+        red[a][threadIdx.x] = lo[a];
+        red[3 + a][threadIdx.x] = hi[a];
+    }
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s)
+            for (int a = 0; a < 3; ++a) {
+                red[a][threadIdx.x] = fminf(red[a][threadIdx.x], red[a][threadIdx.x + s]);
+                red[3 + a][threadIdx.x] = fmaxf(red[3 + a][threadIdx.x], red[3 + a][threadIdx.x + s]);
+            }
+        __syncthreads();
+    }
+    if (threadIdx.x < 6) out[threadIdx.x] = red[threadIdx.x][0];
+}
+
+__device__ __forceinline__ int cell_coord(float p, float o, float inv_h) { return (int)floorf((p - o) * inv_h); }
+
+__global__ __launch_bounds__(256) void k_cell_keys(const float *__restrict__ pos, int64_t n, Grid g,
+                                                   uint32_t *__restrict__ keys, int32_t *__restrict__ vals)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t ncells = (uint32_t)g.nx * g.ny * g.nz;
+    int cx = cell_coord(pos[3 * i + 0], g.ox, g.inv_h);
+    int cy = cell_coord(pos[3 * i + 1], g.oy, g.inv_h);
+    int cz = cell_coord(pos[3 * i + 2], g.oz, g.inv_h);
+    bool in = cx >= 0 && cx < g.nx && cy >= 0 && cy < g.ny && cz >= 0 && cz < g.nz;
+    keys[i] = in ? (uint32_t)(cx + g.nx * (cy + g.ny * cz)) : ncells;
+    vals[i] = (int32_t)i;
+}
+
+// cell_start[c] = first sorted index whose key >= c, for c in [0, ncells].
+__global__ __launch_bounds__(256) void k_cell_bounds(const uint32_t *__restrict__ keys, int64_t n,
+                                                     uint32_t ncells, int32_t *__restrict__ cell_start)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i > n) return;
+    int64_t prev = i == 0 ? -1 : (int64_t)keys[i - 1];
+    int64_t cur = i == n ? (int64_t)ncells : (int64_t)keys[i];
+    if (cur > (int64_t)ncells) cur = ncells;
+    for (int64_t c = prev + 1; c <= cur; ++c) cell_start[c] = (int32_t)i;
+}
+
+__global__ __launch_bounds__(256) void k_sorted_pos(const float *__restrict__ pos, const int32_t *__restrict__ idx,
+                                                    const int32_t *__restrict__ cell_start, uint32_t ncells,
+                                                    float4 *__restrict__ out)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= cell_start[ncells]) return;
+    const int64_t a = idx[i];
+    out[i] = make_float4(pos[3 * a], pos[3 * a + 1], pos[3 * a + 2], 0.f);
+}
+
+// One wavefront per ROI.  FILL == false: count; FILL == true: write rows.
+template <bool FILL>
+__global__ __launch_bounds__(256) void k_roi_query(const float4 *__restrict__ spos, const int32_t *__restrict__ cell_start,
+                                                   Grid g, const float *__restrict__ centres, int64_t n_roi,
+                                                   float radius, float R2, int64_t *__restrict__ counts_or_offsets,
+                                                   int64_t *__restrict__ offsets0, float4 *__restrict__ rel)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t r = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    if (!FILL && blockIdx.x == 0 && threadIdx.x == 0) offsets0[0] = 0;
+    if (r >= n_roi) return;
+    const float cx = centres[3 * r], cy = centres[3 * r + 1], cz = centres[3 * r + 2];
+    const int x0 = max(cell_coord(cx - radius, g.ox, g.inv_h) - 1, 0);
+    const int x1 = min(cell_coord(cx + radius, g.ox, g.inv_h) + 1, g.nx - 1);
+    const int y0 = max(cell_coord(cy - radius, g.oy, g.inv_h) - 1, 0);
+    const int y1 = min(cell_coord(cy + radius, g.oy, g.inv_h) + 1, g.ny - 1);
+    const int z0 = max(cell_coord(cz - radius, g.oz, g.inv_h) - 1, 0);
+    const int z1 = min(cell_coord(cz + radius, g.oz, g.inv_h) + 1, g.nz - 1);
+    int64_t count = 0;
+    const int64_t base = FILL ? counts_or_offsets[r] : 0;
+    const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    for (int z = z0; z <= z1; ++z)
+        for (int y = y0; y <= y1; ++y) {
+            const int row = g.nx * (y + g.ny * z);
+            const int a0 = cell_start[row + x0], a1 = cell_start[row + x1 + 1];
+            for (int i0 = a0; i0 < a1; i0 += 64) {
+                const int i = i0 + lane;
+                bool in = false;
+                float dx = 0.f, dy = 0.f, dz = 0.f;
+                if (i < a1) {
+                    const float4 p = spos[i];
+                    dx = p.x - cx;
+                    dy = p.y - cy;
+                    dz = p.z - cz;
+                    in = fmaf(dz, dz, fmaf(dy, dy, dx * dx)) <= R2;
+                }
+                const uint64_t m = __ballot(in);
+                if (FILL && in) rel[base + count + __popcll(m & lt_mask)] = make_float4(dx, dy, dz, 0.f);
+                count += __popcll(m);
+            }
+        }
+    if (!FILL && lane == 0) counts_or_offsets[r] = count;
+}
+
+}  // namespace
+
+ar_status gather_csr(ar_context *ctx, const float *positions, int64_t n_atoms, const float *centres, int64_t n_roi,
+                     float radius, int64_t *offsets, float *rel, int64_t cap, int64_t *total, hipStream_t stream)
+{
+    AR_CHECK(ctx != nullptr, "context is NULL");
+    AR_CHECK(n_atoms >= 0 && n_atoms < (int64_t)INT32_MAX, "n_atoms must be in [0, 2^31-1)");
+    AR_CHECK(n_roi >= 1, "n_roi must be >= 1");
+    AR_CHECK(radius > 0.f && isfinite(radius), "radius must be finite and > 0");
+    AR_CHECK(centres && offsets && total, "centres/offsets/total must not be NULL");
+    AR_CHECK(n_atoms == 0 || positions, "positions is NULL");
+    AR_HIP(hipSetDevice(ctx->device));
+
+    // bounding box of the centres
+    AR_TRY(ctx->g_bbox.reserve(6 * sizeof(float)));
+    k_centre_bbox<<<1, 1024, 0, stream>>>(centres, n_roi, ctx->g_bbox.as<float>());
+    AR_HIP(hipGetLastError());
+    float bb[6];
+    AR_HIP(hipMemcpyAsync(bb, ctx->g_bbox.ptr, sizeof(bb), hipMemcpyDeviceToHost, stream));
+    AR_HIP(hipStreamSynchronize(stream));
+    for (int a = 0; a < 6; ++a) AR_CHECK(isfinite(bb[a]), "ROI centres must be finite");
+
+    // grid: cell edge R/2, grown if the box would need too many cells
+    double h = 0.5 * (double)radius;
+    const double pad = (double)radius + h;
+    double ext[3];
+    for (int a = 0; a < 3; ++a) ext[a] = (double)bb[3 + a] - (double)bb[a] + 2.0 * pad;
+    for (;;) {
+        double cells = 1.0;
+        for (int a = 0; a < 3; ++a) cells *= floor(ext[a] / h) + 1.0;
+        if (cells <= 6.4e7) break;
+        h *= 1.5;
+    }
+    Grid g;
+    g.ox = (float)((double)bb[0] - pad);
+    g.oy = (float)((double)bb[1] - pad);
+    g.oz = (float)((double)bb[2] - pad);
+    g.inv_h = (float)(1.0 / h);
+    g.nx = (int)(floor(ext[0] / h) + 1.0);
+    g.ny = (int)(floor(ext[1] / h) + 1.0);
+    g.nz = (int)(floor(ext[2] / h) + 1.0);
+    const uint32_t ncells = (uint32_t)g.nx * g.ny * g.nz;
+    int end_bit = 1;
+    while (end_bit < 32 && ((uint64_t)1 << end_bit) <= ncells) ++end_bit;
+
+    const int64_t n = n_atoms;
+    AR_TRY(ctx->g_keys.reserve(sizeof(uint32_t) * (n + 1)));
+    AR_TRY(ctx->g_keys2.reserve(sizeof(uint32_t) * (n + 1)));
+    AR_TRY(ctx->g_vals.reserve(sizeof(int32_t) * (n + 1)));
+    AR_TRY(ctx->g_vals2.reserve(sizeof(int32_t) * (n + 1)));
+    AR_TRY(ctx->g_cell_start.reserve(sizeof(int32_t) * ((size_t)ncells + 1)));
+    AR_TRY(ctx->g_sorted.reserve(sizeof(float4) * (n + 1)));
+
+    size_t sort_bytes = 0, scan_bytes = 0;
+    AR_HIP(hipcub::DeviceRadixSort::SortPairs(nullptr, sort_bytes, (uint32_t *)nullptr, (uint32_t *)nullptr,
+                                              (int32_t *)nullptr, (int32_t *)nullptr, (int)n, 0, end_bit, stream));
+    AR_HIP(hipcub::DeviceScan::InclusiveSum(nullptr, scan_bytes, (int64_t *)nullptr, (int64_t *)nullptr,
+                                            (int)n_roi, stream));
+    AR_TRY(ctx->g_temp.reserve(sort_bytes > scan_bytes ? sort_bytes : scan_bytes));
+
+    if (n > 0) {
+        k_cell_keys<<<(unsigned)((n + 255) / 256), 256, 0, stream>>>(positions, n, g, ctx->g_keys.as<uint32_t>(),
+                                                                    ctx->g_vals.as<int32_t>());
+        AR_HIP(hipGetLastError());
+        size_t tb = ctx->g_temp.bytes;
+        AR_HIP(hipcub::DeviceRadixSort::SortPairs(ctx->g_temp.ptr, tb, ctx->g_keys.as<uint32_t>(),
+                                                  ctx->g_keys2.as<uint32_t>(), ctx->g_vals.as<int32_t>(),
+                                                  ctx->g_vals2.as<int32_t>(), (int)n, 0, end_bit, stream));
+    }
+    k_cell_bounds<<<(unsigned)((n + 1 + 255) / 256), 256, 0, stream>>>(ctx->g_keys2.as<uint32_t>(), n, ncells,
+                                                                      ctx->g_cell_start.as<int32_t>());
+    AR_HIP(hipGetLastError());
+    if (n > 0) {
+        k_sorted_pos<<<(unsigned)((n + 255) / 256), 256, 0, stream>>>(positions, ctx->g_vals2.as<int32_t>(),
+                                                                     ctx->g_cell_start.as<int32_t>(), ncells,
+                                                                     ctx->g_sorted.as<float4>());
+        AR_HIP(hipGetLastError());
+    }
+    const float R2 = (float)((double)radius * (double)radius);
+    const unsigned qblocks = (unsigned)((n_roi + 3) / 4);
+    AR_TRY(ctx->g_counts.reserve(sizeof(int64_t) * n_roi));
+    k_roi_query<false><<<qblocks, 256, 0, stream>>>(ctx->g_sorted.as<float4>(), ctx->g_cell_start.as<int32_t>(), g,
+                                                   centres, n_roi, radius, R2, ctx->g_counts.as<int64_t>(), offsets,
+                                                   nullptr);
+    AR_HIP(hipGetLastError());
+    {
+        size_t tb = ctx->g_temp.bytes;
+        AR_HIP(hipcub::DeviceScan::InclusiveSum(ctx->g_temp.ptr, tb, ctx->g_counts.as<int64_t>(), offsets + 1,
+                                                (int)n_roi, stream));
+    }
+    int64_t tot = 0;
+    AR_HIP(hipMemcpyAsync(&tot, offsets + n_roi, sizeof(int64_t), hipMemcpyDeviceToHost, stream));
+    AR_HIP(hipStreamSynchronize(stream));
+    *total = tot;
+    if (!rel) return AR_OK;
+    AR_CHECK(cap >= tot, "rel capacity %lld is smaller than the %lld gathered rows", (long long)cap, (long long)tot);
+    k_roi_query<true><<<qblocks, 256, 0, stream>>>(ctx->g_sorted.as<float4>(), ctx->g_cell_start.as<int32_t>(), g,
+                                                  centres, n_roi, radius, R2, offsets, nullptr, (float4 *)rel);
+    AR_HIP(hipGetLastError());
+    return AR_OK;
+}
+
+}  // namespace ar
+
+extern "C" ar_status ar_roi_gather(ar_context *ctx, const float *positions, int64_t n_atoms, const float *centres,
+                                   int64_t n_roi, float radius, int64_t *offsets, float *rel, int64_t cap,
+                                   int64_t *total, void *stream)
+{
+    return ar::gather_csr(ctx, positions, n_atoms, centres, n_roi, radius, offsets, rel, cap, total,
+                          (hipStream_t)stream);
+}

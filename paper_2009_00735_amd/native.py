@@ -1,0 +1,371 @@
+"""ctypes binding of libaraullo.so (the C ABI in include/araullo.h).
+
+Argument marshalling only: every function takes/returns torch tensors on the
+context's GPU, passes raw device pointers and the current HIP stream to the
+C entry point of the same name, and raises AraulloError on a non-zero status.
+There is no fallback: if the shared library is missing, importing this
+module raises ImportError.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence, Tuple
+
+import torch
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libaraullo.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_2009_00735_amd.build`")
+
+_L = ctypes.CDLL(LIB_PATH)
+
+vp, i32, i64, f32, f64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_float, ctypes.c_double
+P = ctypes.POINTER
+
+_SIGS = {
+    "ar_last_error": ([], ctypes.c_char_p),
+    "ar_version": ([], ctypes.c_char_p),
+    "ar_context_create": ([ctypes.c_int, P(vp)], ctypes.c_int),
+    "ar_context_destroy": ([vp], ctypes.c_int),
+    "ar_window_bins": ([f64, i32, f64, f64, P(i32), P(i32)], ctypes.c_int),
+    "ar_roi_gather": ([vp, vp, i64, vp, i64, f32, vp, vp, i64, P(i64), vp], ctypes.c_int),
+    "araullo_signatures": ([vp, vp, i64, vp, i64, f32, vp, i32, i32, vp, i32, vp, vp, vp], ctypes.c_int),
+    "araullo_sdm": ([vp, vp, i64, vp, i64, f32, vp, i32, i32, vp, vp, vp], ctypes.c_int),
+    "araullo_signatures_csr": ([vp, vp, vp, i64, f32, vp, i32, i32, vp, i32, vp, vp], ctypes.c_int),
+    "ar_signature_plan_create": ([vp, i64, i64, i32, i32, i32, P(vp)], ctypes.c_int),
+    "ar_signature_plan_destroy": ([vp], ctypes.c_int),
+    "ar_signature_plan_tune": ([vp, vp, vp, i64, f32, vp, vp, vp, vp], ctypes.c_int),
+    "ar_signature_plan_config": ([vp, P(i32), P(i32), P(i32)], ctypes.c_int),
+    "ar_signature_plan_run": ([vp, vp, vp, i64, f32, vp, vp, vp, i32, vp], ctypes.c_int),
+    "ar_library_create": ([vp, vp, i64, i32, i32, vp, P(vp)], ctypes.c_int),
+    "ar_library_destroy": ([vp], ctypes.c_int),
+    "index_orientations": ([vp, vp, i64, vp, i32, vp, vp, vp], ctypes.c_int),
+    "index_orientations_ex": ([vp, vp, i64, vp, i32, i32, vp, vp, vp, vp], ctypes.c_int),
+    "ar_disorientation_cubic": ([vp, vp, i64, vp, vp], ctypes.c_int),
+    "ar_rotate_reference": ([vp, vp, i32, i32, vp, i32, vp, vp, i64, vp, vp], ctypes.c_int),
+    "ar_sf_score_grad": ([vp, vp, vp, i64, vp, vp, vp, i32, vp, vp, i32, i32, vp, vp, vp], ctypes.c_int),
+    "ar_sf_score_f64": ([vp, vp, vp, i64, vp, vp, vp, i32, vp, vp, i32, i32, vp, vp], ctypes.c_int),
+    "ar_sf_amplitudes": ([vp, vp, vp, i64, vp, vp, vp, i32, vp, i32, i32, vp, vp], ctypes.c_int),
+    "ar_refine_orientations": ([vp, vp, vp, i64, vp, vp, vp, i32, vp, vp, i32, i32, i32, f32, vp, vp],
+                               ctypes.c_int),
+}
+for _name, (_args, _res) in _SIGS.items():
+    _fn = getattr(_L, _name)
+    _fn.argtypes = _args
+    _fn.restype = _res
+
+EXPORTED = tuple(_SIGS)
+
+
+class AraulloError(RuntimeError):
+    def __init__(self, fn: str, status: int):
+        msg = _L.ar_last_error().decode(errors="replace")
+        super().__init__(f"{fn} returned {status}: {msg}")
+        self.status = status
+
+
+def _call(name: str, *args) -> None:
+    st = getattr(_L, name)(*args)
+    if st != 0:
+        raise AraulloError(name, st)
+
+
+def version() -> str:
+    return _L.ar_version().decode()
+
+
+def _stream(device: torch.device) -> int:
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+def _dev(t: torch.Tensor, dtype, device, name: str) -> int:
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch.Tensor")
+    if t.device != device:
+        raise ValueError(f"{name} must be on {device}, got {t.device}")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return t.data_ptr()
+
+
+class Context:
+    """ar_context on one GPU."""
+
+    def __init__(self, device: int = 0):
+        self.device = torch.device("cuda", device)
+        h = vp()
+        _call("ar_context_create", device, ctypes.byref(h))
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None) and self.handle.value:
+            _L.ar_context_destroy(self.handle)
+            self.handle = vp()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def ar_window_bins(radius: float, nbins: int, d_min: float, d_max: float) -> Tuple[int, int]:
+    lo, hi = i32(), i32()
+    _call("ar_window_bins", radius, nbins, d_min, d_max, ctypes.byref(lo), ctypes.byref(hi))
+    return lo.value, hi.value
+
+
+def windows_for(radius: float, nbins: int, spacings) -> torch.Tensor:
+    """Host int32 [n_win][2] from (d_min, d_max) pairs."""
+    return torch.tensor([ar_window_bins(radius, nbins, float(a), float(b)) for a, b in spacings], dtype=torch.int32)
+
+
+def _host_windows(windows) -> torch.Tensor:
+    w = torch.as_tensor(windows, dtype=torch.int32).reshape(-1, 2).contiguous()
+    if w.device.type != "cpu":
+        w = w.cpu()
+    return w
+
+
+def ar_roi_gather(ctx: Context, positions: torch.Tensor, centres: torch.Tensor, radius: float):
+    """-> (offsets int64 [n_roi+1], rel float32 [total][4]) on the GPU."""
+    d = ctx.device
+    n_roi = centres.shape[0]
+    offsets = torch.empty(n_roi + 1, dtype=torch.int64, device=d)
+    total = i64()
+    pp = _dev(positions, torch.float32, d, "positions") if positions.numel() else None
+    cp = _dev(centres, torch.float32, d, "centres")
+    s = _stream(d)
+    _call("ar_roi_gather", ctx.handle, pp, positions.shape[0], cp, n_roi, radius, offsets.data_ptr(), None, 0,
+          ctypes.byref(total), s)
+    rel = torch.empty((max(total.value, 1), 4), dtype=torch.float32, device=d)
+    _call("ar_roi_gather", ctx.handle, pp, positions.shape[0], cp, n_roi, radius, offsets.data_ptr(),
+          rel.data_ptr(), rel.shape[0], ctypes.byref(total), s)
+    return offsets, rel[:total.value]
+
+
+def araullo_signatures(ctx: Context, positions: torch.Tensor, centres: torch.Tensor, radius: float,
+                       directions: torch.Tensor, nbins: int, windows, counts: bool = True):
+    """-> images float32 [n_roi][n_win][n_dir] (and int32 counts [n_roi])."""
+    d = ctx.device
+    w = _host_windows(windows)
+    n_roi, n_dir, n_win = centres.shape[0], directions.shape[0], w.shape[0]
+    images = torch.empty((n_roi, n_win, n_dir), dtype=torch.float32, device=d)
+    cnt = torch.empty(n_roi, dtype=torch.int32, device=d) if counts else None
+    _call("araullo_signatures", ctx.handle, _dev(positions, torch.float32, d, "positions") if positions.numel() else None,
+          positions.shape[0], _dev(centres, torch.float32, d, "centres"), n_roi, radius,
+          _dev(directions, torch.float32, d, "directions"), n_dir, nbins, w.data_ptr(), n_win, images.data_ptr(),
+          cnt.data_ptr() if counts else None, _stream(d))
+    return (images, cnt) if counts else images
+
+
+def araullo_sdm(ctx: Context, positions: torch.Tensor, centres: torch.Tensor, radius: float,
+                directions: torch.Tensor, nbins: int):
+    """-> (hist int32 [n_roi][n_dir][nbins], amp float32 [n_roi][n_dir][nbins/2+1])."""
+    d = ctx.device
+    n_roi, n_dir = centres.shape[0], directions.shape[0]
+    hist = torch.empty((n_roi, n_dir, nbins), dtype=torch.int32, device=d)
+    amp = torch.empty((n_roi, n_dir, nbins // 2 + 1), dtype=torch.float32, device=d)
+    _call("araullo_sdm", ctx.handle, _dev(positions, torch.float32, d, "positions") if positions.numel() else None,
+          positions.shape[0], _dev(centres, torch.float32, d, "centres"), n_roi, radius,
+          _dev(directions, torch.float32, d, "directions"), n_dir, nbins, hist.data_ptr(), amp.data_ptr(), _stream(d))
+    return hist, amp
+
+
+def araullo_signatures_csr(ctx: Context, rel: torch.Tensor, offsets: torch.Tensor, radius: float,
+                           directions: torch.Tensor, nbins: int, windows, out: Optional[torch.Tensor] = None):
+    d = ctx.device
+    w = _host_windows(windows)
+    n_roi, n_dir, n_win = offsets.shape[0] - 1, directions.shape[0], w.shape[0]
+    images = out if out is not None else torch.empty((n_roi, n_win, n_dir), dtype=torch.float32, device=d)
+    relp = rel if rel.numel() else torch.zeros((1, 4), dtype=torch.float32, device=d)
+    _call("araullo_signatures_csr", ctx.handle, _dev(relp, torch.float32, d, "rel"),
+          _dev(offsets, torch.int64, d, "offsets"), n_roi, radius, _dev(directions, torch.float32, d, "directions"),
+          n_dir, nbins, w.data_ptr(), n_win, _dev(images, torch.float32, d, "images"), _stream(d))
+    return images
+
+
+class SignaturePlan:
+    """ar_plan: batched persistent signatures, autotuned, graph-replayed."""
+
+    def __init__(self, ctx: Context, max_roi: int, max_total: int, n_dir: int, nbins: int, n_win: int):
+        self.ctx = ctx
+        h = vp()
+        _call("ar_signature_plan_create", ctx.handle, max_roi, max_total, n_dir, nbins, n_win, ctypes.byref(h))
+        self.handle = h
+        self.n_dir, self.nbins, self.n_win = n_dir, nbins, n_win
+
+    def _args(self, rel, offsets, directions, images):
+        d = self.ctx.device
+        relp = rel if rel.numel() else torch.zeros((1, 4), dtype=torch.float32, device=d)
+        return (_dev(relp, torch.float32, d, "rel"), _dev(offsets, torch.int64, d, "offsets"), offsets.shape[0] - 1,
+                _dev(directions, torch.float32, d, "directions"), _dev(images, torch.float32, d, "images"))
+
+    def _out(self, offsets, out):
+        if out is not None:
+            return out
+        return torch.empty((offsets.shape[0] - 1, self.n_win, self.n_dir), dtype=torch.float32,
+                           device=self.ctx.device)
+
+    def tune(self, rel, offsets, radius, directions, windows, out=None):
+        images = self._out(offsets, out)
+        w = _host_windows(windows)
+        r, o, n, dp, ip = self._args(rel, offsets, directions, images)
+        _call("ar_signature_plan_tune", self.handle, r, o, n, radius, dp, w.data_ptr(), ip, _stream(self.ctx.device))
+        return images
+
+    def config(self) -> Tuple[int, int, int]:
+        a, b, c = i32(), i32(), i32()
+        _call("ar_signature_plan_config", self.handle, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c))
+        return a.value, b.value, c.value
+
+    def run(self, rel, offsets, radius, directions, windows, out=None, use_graph: bool = True):
+        images = self._out(offsets, out)
+        w = _host_windows(windows)
+        self._w = w  # keep the host array alive for the call
+        r, o, n, dp, ip = self._args(rel, offsets, directions, images)
+        _call("ar_signature_plan_run", self.handle, r, o, n, radius, dp, w.data_ptr(), ip, int(use_graph),
+              _stream(self.ctx.device))
+        return images
+
+    def close(self):
+        if getattr(self, "handle", None) and self.handle.value:
+            _L.ar_signature_plan_destroy(self.handle)
+            self.handle = vp()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Library:
+    """ar_library: normalised BF16 reference images + norms (keeps ref alive)."""
+
+    def __init__(self, ctx: Context, ref_images: torch.Tensor):
+        self.ctx = ctx
+        n_lib, n_win, n_dir = ref_images.shape
+        self.ref = ref_images
+        self.n_lib, self.n_win, self.n_dir = n_lib, n_win, n_dir
+        h = vp()
+        _call("ar_library_create", ctx.handle, _dev(ref_images, torch.float32, ctx.device, "ref_images"), n_lib,
+              n_win, n_dir, _stream(ctx.device), ctypes.byref(h))
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None) and self.handle.value:
+            _L.ar_library_destroy(self.handle)
+            self.handle = vp()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def index_orientations(ctx: Context, images: torch.Tensor, library: Library, k: int = 16):
+    """-> (top_idx int32 [n_roi][k], top_score float32 [n_roi][k])."""
+    d = ctx.device
+    n_roi = images.shape[0]
+    idx = torch.empty((n_roi, k), dtype=torch.int32, device=d)
+    sc = torch.empty((n_roi, k), dtype=torch.float32, device=d)
+    _call("index_orientations", ctx.handle, _dev(images, torch.float32, d, "images"), n_roi, library.handle, k,
+          idx.data_ptr(), sc.data_ptr(), _stream(d))
+    return idx, sc
+
+
+def index_orientations_ex(ctx: Context, images: torch.Tensor, library: Library, k: int, cand: int):
+    """-> (top_idx, top_score, cand_idx int32 [n_roi][cand])."""
+    d = ctx.device
+    n_roi = images.shape[0]
+    idx = torch.empty((n_roi, k), dtype=torch.int32, device=d)
+    sc = torch.empty((n_roi, k), dtype=torch.float32, device=d)
+    ci = torch.empty((n_roi, cand), dtype=torch.int32, device=d)
+    _call("index_orientations_ex", ctx.handle, _dev(images, torch.float32, d, "images"), n_roi, library.handle, k,
+          cand, idx.data_ptr(), sc.data_ptr(), ci.data_ptr(), _stream(d))
+    return idx, sc, ci
+
+
+def ar_disorientation_cubic(qa: torch.Tensor, qb: torch.Tensor) -> torch.Tensor:
+    d = qa.device
+    n = qa.shape[0]
+    out = torch.empty(n, dtype=torch.float64, device=d)
+    _call("ar_disorientation_cubic", _dev(qa, torch.float64, d, "qa"), _dev(qb, torch.float64, d, "qb"), n,
+          out.data_ptr(), _stream(d))
+    return out
+
+
+def ar_rotate_reference(ctx: Context, reference: torch.Tensor, directions: torch.Tensor, quats: torch.Tensor,
+                        phase: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    d = ctx.device
+    n_phase, n_win, n_dir = reference.shape
+    n_lib = quats.shape[0]
+    o = out if out is not None else torch.empty((n_lib, n_win, n_dir), dtype=torch.float32, device=d)
+    _call("ar_rotate_reference", ctx.handle, _dev(reference, torch.float32, d, "reference"), n_phase, n_win,
+          _dev(directions, torch.float32, d, "directions"), n_dir, _dev(quats, torch.float64, d, "quats"),
+          _dev(phase, torch.int32, d, "phase"), n_lib, _dev(o, torch.float32, d, "out"), _stream(d))
+    return o
+
+
+def ar_sf_score_grad(ctx: Context, rel, offsets, quats, phase, directions, freqs, targets, grad: bool = True):
+    """-> (score float32 [n_roi], grad float32 [n_roi][4] or None)."""
+    d = ctx.device
+    n_roi = offsets.shape[0] - 1
+    n_phase, n_freq = freqs.shape
+    score = torch.empty(n_roi, dtype=torch.float32, device=d)
+    g = torch.empty((n_roi, 4), dtype=torch.float32, device=d) if grad else None
+    relp = rel if rel.numel() else torch.zeros((1, 4), dtype=torch.float32, device=d)
+    _call("ar_sf_score_grad", ctx.handle, _dev(relp, torch.float32, d, "rel"), _dev(offsets, torch.int64, d, "offsets"),
+          n_roi, _dev(quats, torch.float32, d, "quats"), _dev(phase, torch.int32, d, "phase"),
+          _dev(directions, torch.float32, d, "directions"), directions.shape[0], _dev(freqs, torch.float32, d, "freqs"),
+          _dev(targets, torch.float32, d, "targets"), n_phase, n_freq, score.data_ptr(),
+          g.data_ptr() if grad else None, _stream(d))
+    return score, g
+
+
+def ar_sf_score_f64(ctx: Context, rel, offsets, quats, phase, directions, freqs, targets) -> torch.Tensor:
+    d = ctx.device
+    n_roi = offsets.shape[0] - 1
+    n_phase, n_freq = freqs.shape
+    score = torch.empty(n_roi, dtype=torch.float64, device=d)
+    relp = rel if rel.numel() else torch.zeros((1, 4), dtype=torch.float32, device=d)
+    _call("ar_sf_score_f64", ctx.handle, _dev(relp, torch.float32, d, "rel"), _dev(offsets, torch.int64, d, "offsets"),
+          n_roi, _dev(quats, torch.float64, d, "quats"), _dev(phase, torch.int32, d, "phase"),
+          _dev(directions, torch.float32, d, "directions"), directions.shape[0], _dev(freqs, torch.float64, d, "freqs"),
+          _dev(targets, torch.float64, d, "targets"), n_phase, n_freq, score.data_ptr(), _stream(d))
+    return score
+
+
+def ar_sf_amplitudes(ctx: Context, rel, offsets, quats, phase, directions, freqs) -> torch.Tensor:
+    d = ctx.device
+    n_roi = offsets.shape[0] - 1
+    n_phase, n_freq = freqs.shape
+    amp = torch.empty((n_roi, n_freq, directions.shape[0]), dtype=torch.float32, device=d)
+    relp = rel if rel.numel() else torch.zeros((1, 4), dtype=torch.float32, device=d)
+    _call("ar_sf_amplitudes", ctx.handle, _dev(relp, torch.float32, d, "rel"), _dev(offsets, torch.int64, d, "offsets"),
+          n_roi, _dev(quats, torch.float32, d, "quats"), _dev(phase, torch.int32, d, "phase"),
+          _dev(directions, torch.float32, d, "directions"), directions.shape[0], _dev(freqs, torch.float32, d, "freqs"),
+          n_phase, n_freq, amp.data_ptr(), _stream(d))
+    return amp
+
+
+def ar_refine_orientations(ctx: Context, rel, offsets, quats, phase, directions, freqs, targets, steps: int = 50,
+                           a0: float = 1e-3):
+    """Refines quats in place; -> final score float32 [n_roi]."""
+    d = ctx.device
+    n_roi = offsets.shape[0] - 1
+    n_phase, n_freq = freqs.shape
+    score = torch.empty(n_roi, dtype=torch.float32, device=d)
+    relp = rel if rel.numel() else torch.zeros((1, 4), dtype=torch.float32, device=d)
+    _call("ar_refine_orientations", ctx.handle, _dev(relp, torch.float32, d, "rel"),
+          _dev(offsets, torch.int64, d, "offsets"), n_roi, _dev(quats, torch.float32, d, "quats"),
+          _dev(phase, torch.int32, d, "phase"), _dev(directions, torch.float32, d, "directions"), directions.shape[0],
+          _dev(freqs, torch.float32, d, "freqs"), _dev(targets, torch.float32, d, "targets"), n_phase, n_freq, steps,
+          a0, score.data_ptr(), _stream(d))
+    return score
