@@ -1,23 +1,596 @@
-// Orientation indexing (placeholder until the correlation kernels land).
+// Orientation indexing (Sec. 2.4; supplement, "Indexing algorithm",
+// Eq. S1): normalised ROI signatures against normalised rotated references
+// by the sum of squared differences, read densely over all nodes,
+//   Delta(r,l) = |S_r|^2 + |L_l|^2 - 2 <S_r, L_l>.
+//
+// gfx950 design:
+//   1. k_normalise_cast   per (row, window) max over the directions, FP32
+//                         reciprocal, BF16 (round to nearest even) copy of the
+//                         normalised row, K padded with zeros.
+//   2. k_corr_topk        BF16-input / FP32-accumulate MFMA correlation
+//                         (v_mfma_f32_32x32x16_bf16), 128x128 workgroup tile,
+//                         K in steps of 64 through double-buffered, padded LDS.
+//                         Each workgroup owns a 128-row panel and a segment of
+//                         library columns; the epilogue turns every tile into
+//                         scores |L|^2 - 2<S,L> (the per-row constant |S|^2 is
+//                         dropped) and keeps, per row, the CAND best
+//                         (score, index) pairs in registers: the ranking
+//                         never materialises the score matrix.
+//   3. k_merge            per row, the CAND best over all segments.
+//   4. k_rescore          exact FP32 sum of squared differences of the
+//                         normalised FP32 images for the CAND candidates,
+//                         sorted by (Delta, index); the first k are returned.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+
 #include "ar_internal.h"
+
+namespace ar {
+namespace idx {
+
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
+typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16;
+
+constexpr int BM = 128, BN = 128, BK = 64;
+constexpr int LDA = BK + 8;              // padded LDS row (bf16): 144 bytes
+constexpr int kThreads = 256;
+
+__device__ __forceinline__ uint16_t f32_to_bf16_rne(float x)
+{
+    uint32_t u = __float_as_uint(x);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+__device__ __forceinline__ float bf16_to_f32(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
+
+// ------------------------------------------------------------ normalise + cast
+// grid (n_rows, n_win); writes inv_max[row][w] and out[row][w*n_dir + v].
+// The workgroup of the last window also zeroes the K padding of its row.
+__global__ __launch_bounds__(256) void k_normalise_cast(const float *__restrict__ img, int n_win, int n_dir,
+                                                        int64_t Kp, float *__restrict__ inv_max,
+                                                        uint16_t *__restrict__ out)
+{
+    __shared__ float red[256];
+    const int64_t row = blockIdx.x;
+    const int w = blockIdx.y;
+    const float *src = img + ((size_t)row * n_win + w) * n_dir;
+    float m = 0.0f;
+    for (int v = threadIdx.x; v < n_dir; v += blockDim.x) m = fmaxf(m, src[v]);
+    red[threadIdx.x] = m;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + s]);
+        __syncthreads();
+    }
+    const float mx = red[0];
+    const float inv = mx > 0.0f ? 1.0f / mx : 0.0f;
+    if (threadIdx.x == 0) inv_max[(size_t)row * n_win + w] = inv;
+    uint16_t *dst = out + (size_t)row * Kp + (size_t)w * n_dir;
+    for (int v = threadIdx.x; v < n_dir; v += blockDim.x) dst[v] = f32_to_bf16_rne(src[v] * inv);
+    if (w == n_win - 1) {
+        const int64_t K = (int64_t)n_win * n_dir;
+        for (int64_t c = K + threadIdx.x; c < Kp; c += blockDim.x) out[(size_t)row * Kp + c] = 0;
+    }
+}
+
+// zero rows [r0, r1) of a [*][Kp] bf16 matrix
+__global__ __launch_bounds__(256) void k_zero_rows(uint16_t *__restrict__ out, int64_t Kp, int64_t r0, int64_t r1)
+{
+    const int64_t n = (r1 - r0) * Kp;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        out[r0 * Kp + i] = 0;
+}
+
+// |row|^2 of the BF16 copy, FP32; rows >= n_valid get +inf
+__global__ __launch_bounds__(256) void k_row_norm2(const uint16_t *__restrict__ m, int64_t Kp, int64_t n_valid,
+                                                   float *__restrict__ norm2)
+{
+    __shared__ float red[256];
+    const int64_t row = blockIdx.x;
+    float acc = 0.0f;
+    if (row < n_valid)
+        for (int64_t c = threadIdx.x; c < Kp; c += blockDim.x) {
+            const float x = bf16_to_f32(m[(size_t)row * Kp + c]);
+            acc = fmaf(x, x, acc);
+        }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) norm2[row] = row < n_valid ? red[0] : INFINITY;
+}
+
+// ------------------------------------------------------------ top-CAND list
+// Sorted ascending by (score, index); insertion keeps the CAND smallest.
+template <int CAND>
+struct TopList {
+    float s[CAND];
+    int i[CAND];
+    __device__ __forceinline__ void init()
+    {
+#pragma unroll
+        for (int j = 0; j < CAND; ++j) {
+            s[j] = INFINITY;
+            i[j] = 0x7fffffff;
+        }
+    }
+    __device__ __forceinline__ void insert(float cs, int ci)
+    {
+        if (!(cs < s[CAND - 1] || (cs == s[CAND - 1] && ci < i[CAND - 1]))) return;
+#pragma unroll
+        for (int j = 0; j < CAND; ++j) {
+            const bool lt = cs < s[j] || (cs == s[j] && ci < i[j]);
+            const float ts = lt ? s[j] : cs;
+            const int ti = lt ? i[j] : ci;
+            s[j] = lt ? cs : s[j];
+            i[j] = lt ? ci : i[j];
+            cs = ts;
+            ci = ti;
+        }
+    }
+};
+
+// ------------------------------------------------------------ correlation
+// Workgroup: 4 waves as 2x2, each wave 64x64 = 2x2 MFMA 32x32 tiles.
+// grid.x = m_blocks * n_seg.  out_s/out_i: [M_pad][n_seg*2][CAND], the lists
+// of the two 64-column halves of every tile of the segment.
+// DBUF: A/B staged through two LDS buffers (one barrier per K step) when the
+// device allows 72 KiB of LDS per workgroup, else one buffer (two barriers).
+template <int CAND, bool DBUF>
+__global__ __launch_bounds__(kThreads) void k_corr_topk(const uint16_t *__restrict__ A, const uint16_t *__restrict__ B,
+                                                        const float *__restrict__ norm2, int64_t Kp, int m_blocks,
+                                                        int n_tiles, int tiles_per_seg, int n_seg,
+                                                        float *__restrict__ out_s, int32_t *__restrict__ out_i)
+{
+    constexpr int NBUF = DBUF ? 2 : 1;
+    extern __shared__ __align__(16) unsigned char smem[];
+    uint16_t *As = reinterpret_cast<uint16_t *>(smem);                 // [NBUF][BM][LDA]
+    uint16_t *Bs = As + NBUF * BM * LDA;                               // [NBUF][BN][LDA]
+    float *Cs = reinterpret_cast<float *>(smem);                       // [BM][65], aliases As/Bs
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int wm = wave & 1, wn = wave >> 1;
+    // XCD-aware ordering: workgroup ids are dealt round-robin to the 8 XCDs;
+    // map them so that each XCD walks a contiguous range of (m_block, seg)
+    // (segment-major), i.e. its resident workgroups share library segments.
+    const int T = m_blocks * n_seg;
+    int b;
+    {
+        const int x = blockIdx.x & 7, j = blockIdx.x >> 3;
+        const int q = T >> 3, r = T & 7;
+        b = x * q + min(x, r) + j;
+    }
+    const int mb = b % m_blocks;
+    const int seg = b / m_blocks;
+    const int64_t m0 = (int64_t)mb * BM;
+    const int t0 = seg * tiles_per_seg;
+    const int t1 = min(t0 + tiles_per_seg, n_tiles);
+
+    // epilogue ownership: thread -> (row, half)
+    const int e_row = tid & (BM - 1);
+    const int e_half = tid >> 7;
+    TopList<CAND> top;
+    top.init();
+
+    const int KT = (int)(Kp / BK);
+    for (int nt = t0; nt < t1; ++nt) {
+        const int64_t n0 = (int64_t)nt * BN;
+        f32x16 acc[2][2];
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int c = 0; c < 2; ++c)
+#pragma unroll
+                for (int r = 0; r < 16; ++r) acc[a][c][r] = 0.0f;
+
+        // global -> register staging: 4 chunks of 16 B for A and for B
+        uint4 ra0, ra1, ra2, ra3, rb0, rb1, rb2, rb3;
+#define AR_GLOAD(kt_)                                                                               \
+    do {                                                                                            \
+        const int64_t k0_ = (int64_t)(kt_) * BK;                                                    \
+        const uint16_t *pa_ = A + (size_t)(m0 + (tid >> 3)) * Kp + k0_ + (tid & 7) * 8;              \
+        const uint16_t *pb_ = B + (size_t)(n0 + (tid >> 3)) * Kp + k0_ + (tid & 7) * 8;              \
+        const size_t step_ = (size_t)32 * Kp; /* 256 threads cover 32 rows */                        \
+        ra0 = *reinterpret_cast<const uint4 *>(pa_);                                                \
+        ra1 = *reinterpret_cast<const uint4 *>(pa_ + step_);                                        \
+        ra2 = *reinterpret_cast<const uint4 *>(pa_ + 2 * step_);                                    \
+        ra3 = *reinterpret_cast<const uint4 *>(pa_ + 3 * step_);                                    \
+        rb0 = *reinterpret_cast<const uint4 *>(pb_);                                                \
+        rb1 = *reinterpret_cast<const uint4 *>(pb_ + step_);                                        \
+        rb2 = *reinterpret_cast<const uint4 *>(pb_ + 2 * step_);                                    \
+        rb3 = *reinterpret_cast<const uint4 *>(pb_ + 3 * step_);                                    \
+    } while (0)
+#define AR_SSTORE(buf_)                                                                             \
+    do {                                                                                            \
+        uint16_t *sa_ = As + (size_t)(buf_) * BM * LDA + (tid >> 3) * LDA + (tid & 7) * 8;          \
+        uint16_t *sb_ = Bs + (size_t)(buf_) * BN * LDA + (tid >> 3) * LDA + (tid & 7) * 8;          \
+        *reinterpret_cast<uint4 *>(sa_) = ra0;                                                      \
+        *reinterpret_cast<uint4 *>(sa_ + 32 * LDA) = ra1;                                           \
+        *reinterpret_cast<uint4 *>(sa_ + 64 * LDA) = ra2;                                           \
+        *reinterpret_cast<uint4 *>(sa_ + 96 * LDA) = ra3;                                           \
+        *reinterpret_cast<uint4 *>(sb_) = rb0;                                                      \
+        *reinterpret_cast<uint4 *>(sb_ + 32 * LDA) = rb1;                                           \
+        *reinterpret_cast<uint4 *>(sb_ + 64 * LDA) = rb2;                                           \
+        *reinterpret_cast<uint4 *>(sb_ + 96 * LDA) = rb3;                                           \
+    } while (0)
+        AR_GLOAD(0);
+        __syncthreads();   // the previous tile's epilogue read Cs, which aliases As/Bs
+        AR_SSTORE(0);
+        __syncthreads();
+        for (int kt = 0; kt < KT; ++kt) {
+            const int cur = DBUF ? (kt & 1) : 0;
+            if (kt + 1 < KT) AR_GLOAD(kt + 1);
+            const uint16_t *a_s = As + (size_t)cur * BM * LDA;
+            const uint16_t *b_s = Bs + (size_t)cur * BN * LDA;
+#pragma unroll
+            for (int kk = 0; kk < BK; kk += 16) {
+                bf16x8 fa[2], fb[2];
+#pragma unroll
+                for (int a = 0; a < 2; ++a) {
+                    const int row = wm * 64 + a * 32 + (lane & 31);
+                    fa[a] = *reinterpret_cast<const bf16x8 *>(a_s + row * LDA + kk + (lane >> 5) * 8);
+                }
+#pragma unroll
+                for (int c = 0; c < 2; ++c) {
+                    const int col = wn * 64 + c * 32 + (lane & 31);
+                    fb[c] = *reinterpret_cast<const bf16x8 *>(b_s + col * LDA + kk + (lane >> 5) * 8);
+                }
+#pragma unroll
+                for (int a = 0; a < 2; ++a)
+#pragma unroll
+                    for (int c = 0; c < 2; ++c)
+                        acc[a][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[a], fb[c], acc[a][c], 0, 0, 0);
+            }
+            if (DBUF) {
+                if (kt + 1 < KT) AR_SSTORE(cur ^ 1);
+                __syncthreads();
+            } else if (kt + 1 < KT) {
+                __syncthreads();
+                AR_SSTORE(0);
+                __syncthreads();
+            }
+        }
+#undef AR_GLOAD
+#undef AR_SSTORE
+        __syncthreads();
+        // epilogue in two 64-column passes: the waves of column half h write
+        // their scores |L|^2 - 2<S,L> to LDS, the threads of half h scan rows
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            if (wn == h) {
+#pragma unroll
+                for (int a = 0; a < 2; ++a)
+#pragma unroll
+                    for (int c = 0; c < 2; ++c) {
+                        const int col = c * 32 + (lane & 31);
+                        const float nrm = norm2[n0 + h * 64 + col];
+#pragma unroll
+                        for (int r = 0; r < 16; ++r) {
+                            const int row = wm * 64 + a * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+                            Cs[row * 65 + col] = fmaf(-2.0f, acc[a][c][r], nrm);
+                        }
+                    }
+            }
+            __syncthreads();
+            if (e_half == h) {
+                const float *crow = Cs + e_row * 65;
+                const int base = (int)(n0 + h * 64);
+#pragma unroll 8
+                for (int j = 0; j < 64; ++j) top.insert(crow[j], base + j);
+            }
+            __syncthreads();
+        }
+    }
+    const size_t o = (((size_t)(m0 + e_row)) * (n_seg * 2) + seg * 2 + e_half) * CAND;
+#pragma unroll
+    for (int j = 0; j < CAND; ++j) {
+        out_s[o + j] = top.s[j];
+        out_i[o + j] = top.i[j];
+    }
+}
+
+// ------------------------------------------------------------ merge
+// One wave per row: the CAND smallest (score, index) over n_lists lists.
+template <int CAND>
+__global__ __launch_bounds__(256) void k_merge(const float *__restrict__ in_s, const int32_t *__restrict__ in_i,
+                                               int n_lists, int64_t n_rows, int32_t *__restrict__ cand_idx)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (row >= n_rows) return;
+    const int n = n_lists * CAND;
+    const float *s = in_s + (size_t)row * n;
+    const int32_t *ix = in_i + (size_t)row * n;
+    // each lane keeps its private best CAND of the strided elements
+    TopList<CAND> t;
+    t.init();
+    for (int e = lane; e < n; e += 64) t.insert(s[e], ix[e]);
+    // CAND rounds of a wave-wide argmin over the lanes' list heads
+    int head = 0;
+    for (int j = 0; j < CAND; ++j) {
+        float hs = INFINITY;
+        int hi = 0x7fffffff;
+#pragma unroll
+        for (int q = 0; q < CAND; ++q)
+            if (q == head) {
+                hs = t.s[q];
+                hi = t.i[q];
+            }
+        float bs = hs;
+        int bi = hi;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            const float os = __shfl_xor(bs, off);
+            const int oi = __shfl_xor(bi, off);
+            if (os < bs || (os == bs && oi < bi)) {
+                bs = os;
+                bi = oi;
+            }
+        }
+        if (hs == bs && hi == bi && head < CAND) ++head;
+        if (lane == 0) cand_idx[(size_t)row * CAND + j] = bi;
+    }
+}
+
+// ------------------------------------------------------------ FP32 rescore
+// One workgroup per ROI row: Delta for each candidate from the FP32 images,
+// then the k best by (Delta, index).
+template <int CAND>
+__global__ __launch_bounds__(256) void k_rescore(const float *__restrict__ S, const float *__restrict__ inv_s,
+                                                 const float *__restrict__ L, const float *__restrict__ inv_l,
+                                                 const int32_t *__restrict__ cand_idx, int n_win, int n_dir,
+                                                 int64_t n_lib, int k, int32_t *__restrict__ top_idx,
+                                                 float *__restrict__ top_score)
+{
+#pragma clang fp contract(off)
+    __shared__ float red[256];
+    __shared__ float ds[CAND];
+    __shared__ int di[CAND];
+    const int64_t r = blockIdx.x;
+    const float *srow = S + (size_t)r * n_win * n_dir;
+    for (int c = 0; c < CAND; ++c) {
+        const int l = cand_idx[(size_t)r * CAND + c];
+        float acc = 0.0f;
+        if (l >= 0 && l < n_lib) {
+            const float *lrow = L + (size_t)l * n_win * n_dir;
+            for (int w = 0; w < n_win; ++w) {
+                const float is = inv_s[(size_t)r * n_win + w], il = inv_l[(size_t)l * n_win + w];
+                for (int v = threadIdx.x; v < n_dir; v += blockDim.x) {
+                    // both normalised values rounded alike (no contraction in this
+                    // kernel): identical images give Delta = 0 exactly
+                    const float d = srow[(size_t)w * n_dir + v] * is - lrow[(size_t)w * n_dir + v] * il;
+                    acc = fmaf(d, d, acc);
+                }
+            }
+        } else {
+            acc = INFINITY;
+        }
+        red[threadIdx.x] = acc;
+        __syncthreads();
+        for (int s = 128; s > 0; s >>= 1) {
+            if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) {
+            ds[c] = red[0];
+            di[c] = (l >= 0 && l < n_lib) ? l : 0x7fffffff;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        // insertion sort of CAND entries by (Delta, index)
+        for (int a = 1; a < CAND; ++a) {
+            const float vs = ds[a];
+            const int vi = di[a];
+            int b = a - 1;
+            while (b >= 0 && (ds[b] > vs || (ds[b] == vs && di[b] > vi))) {
+                ds[b + 1] = ds[b];
+                di[b + 1] = di[b];
+                --b;
+            }
+            ds[b + 1] = vs;
+            di[b + 1] = vi;
+        }
+        for (int j = 0; j < k; ++j) {
+            top_idx[(size_t)r * k + j] = di[j] == 0x7fffffff ? -1 : di[j];
+            top_score[(size_t)r * k + j] = ds[j];
+        }
+    }
+}
+
+template <int CAND>
+__global__ void k_copy_cand(const int32_t *__restrict__ cand, int64_t n_rows, int32_t *__restrict__ out)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n_rows * CAND) out[i] = cand[i];
+}
+
+size_t corr_lds_bytes(bool dbuf)
+{
+    const size_t ab = (size_t)(dbuf ? 2 : 1) * (BM + BN) * LDA * sizeof(uint16_t);
+    const size_t c = (size_t)BM * 65 * sizeof(float);
+    return ab > c ? ab : c;
+}
+
+template <int CAND>
+ar_status launch_corr(ar_context *ctx, const uint16_t *A, const ar_library *lib, int m_blocks, int n_tiles,
+                      int tiles_per_seg, int n_seg, float *out_s, int32_t *out_i, hipStream_t s)
+{
+    const unsigned blocks = (unsigned)(m_blocks * n_seg);
+    const size_t big = corr_lds_bytes(true);
+    static int dbuf_ok = -1;   // per process: can a workgroup get `big` bytes of LDS?
+    if (dbuf_ok < 0) {
+        dbuf_ok = 0;
+        if ((size_t)ctx->lds_per_block >= big &&
+            hipFuncSetAttribute((const void *)k_corr_topk<CAND, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)big) == hipSuccess)
+            dbuf_ok = 1;
+        (void)hipGetLastError();
+    }
+    if (dbuf_ok == 1) {
+        (void)hipFuncSetAttribute((const void *)k_corr_topk<CAND, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)big);
+        k_corr_topk<CAND, true><<<blocks, kThreads, big, s>>>(A, lib->bf16.as<uint16_t>(), lib->norm2.as<float>(),
+                                                              lib->Kp, m_blocks, n_tiles, tiles_per_seg, n_seg, out_s,
+                                                              out_i);
+    } else {
+        k_corr_topk<CAND, false><<<blocks, kThreads, corr_lds_bytes(false), s>>>(
+            A, lib->bf16.as<uint16_t>(), lib->norm2.as<float>(), lib->Kp, m_blocks, n_tiles, tiles_per_seg, n_seg,
+            out_s, out_i);
+    }
+    AR_HIP(hipGetLastError());
+    return AR_OK;
+}
+
+int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
+
+// Normalise FP32 images [n][n_win][n_dir] into a BF16 [n_pad][Kp] matrix and
+// FP32 reciprocal maxima [n][n_win].
+ar_status normalise_cast(const float *img, int64_t n, int64_t n_pad, int n_win, int n_dir, int64_t Kp, float *inv,
+                         uint16_t *out, hipStream_t s)
+{
+    dim3 grid((unsigned)n, (unsigned)n_win);
+    k_normalise_cast<<<grid, 256, 0, s>>>(img, n_win, n_dir, Kp, inv, out);
+    AR_HIP(hipGetLastError());
+    if (n_pad > n) {
+        k_zero_rows<<<256, 256, 0, s>>>(out, Kp, n, n_pad);
+        AR_HIP(hipGetLastError());
+    }
+    return AR_OK;
+}
+
+}  // namespace idx
+}  // namespace ar
+
+using namespace ar;
 
 extern "C" {
 
-ar_status ar_library_create(ar_context *, const float *, int64_t, int32_t, int32_t, void *, ar_library **out)
+ar_status ar_library_create(ar_context *ctx, const float *ref_images, int64_t n_lib, int32_t n_win, int32_t n_dir,
+                            void *stream, ar_library **out)
 {
-    if (out) *out = nullptr;
-    return ar::fail(AR_EUNSUPPORTED, "ar_library_create: not built yet");
+    AR_CHECK(out != nullptr, "out is NULL");
+    *out = nullptr;
+    AR_CHECK(ctx != nullptr, "context is NULL");
+    AR_CHECK(ref_images != nullptr, "ref_images is NULL");
+    AR_CHECK(n_lib >= 1 && n_lib < (int64_t)INT32_MAX - idx::BN, "n_lib out of range");
+    AR_CHECK(n_win >= 1 && n_dir >= 1, "n_win and n_dir must be >= 1");
+    AR_HIP(hipSetDevice(ctx->device));
+    hipStream_t s = (hipStream_t)stream;
+    auto *lib = new (std::nothrow) ar_library();
+    if (!lib) return fail(AR_ENOMEM, "library allocation failed");
+    lib->ctx = ctx;
+    lib->ref = ref_images;
+    lib->n_lib = n_lib;
+    lib->n_win = n_win;
+    lib->n_dir = n_dir;
+    lib->K = (int64_t)n_win * n_dir;
+    lib->Kp = idx::round_up(lib->K, idx::BK);
+    lib->n_pad = idx::round_up(n_lib, idx::BN);
+    ar_status st = lib->bf16.reserve(sizeof(uint16_t) * (size_t)lib->n_pad * lib->Kp);
+    if (st == AR_OK) st = lib->norm2.reserve(sizeof(float) * lib->n_pad);
+    if (st == AR_OK) st = lib->inv_max.reserve(sizeof(float) * n_lib * n_win);
+    if (st == AR_OK)
+        st = idx::normalise_cast(ref_images, n_lib, lib->n_pad, n_win, n_dir, lib->Kp, lib->inv_max.as<float>(),
+                                 lib->bf16.as<uint16_t>(), s);
+    if (st == AR_OK) {
+        idx::k_row_norm2<<<(unsigned)lib->n_pad, 256, 0, s>>>(lib->bf16.as<uint16_t>(), lib->Kp, n_lib,
+                                                              lib->norm2.as<float>());
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) st = fail(AR_EDEVICE, "k_row_norm2: %s", hipGetErrorString(e));
+    }
+    if (st != AR_OK) {
+        delete lib;
+        return st;
+    }
+    *out = lib;
+    return AR_OK;
 }
-ar_status ar_library_destroy(ar_library *) { return AR_OK; }
-ar_status index_orientations(ar_context *, const float *, int64_t, const ar_library *, int32_t, int32_t *, float *,
-                             void *)
+
+ar_status ar_library_destroy(ar_library *lib)
 {
-    return ar::fail(AR_EUNSUPPORTED, "index_orientations: not built yet");
+    if (!lib) return AR_OK;
+    (void)hipSetDevice(lib->ctx->device);
+    (void)hipDeviceSynchronize();
+    delete lib;
+    return AR_OK;
 }
-ar_status index_orientations_ex(ar_context *, const float *, int64_t, const ar_library *, int32_t, int32_t,
-                                int32_t *, float *, int32_t *, void *)
+
+ar_status index_orientations_ex(ar_context *ctx, const float *images, int64_t n_roi, const ar_library *lib, int32_t k,
+                                int32_t cand, int32_t *top_idx, float *top_score, int32_t *cand_idx, void *stream)
 {
-    return ar::fail(AR_EUNSUPPORTED, "index_orientations_ex: not built yet");
+    AR_CHECK(ctx && lib, "ctx/library is NULL");
+    AR_CHECK(images && top_idx && top_score, "images/top_idx/top_score must not be NULL");
+    AR_CHECK(n_roi >= 1 && n_roi < (int64_t)INT32_MAX - idx::BM, "n_roi out of range");
+    AR_CHECK(cand == 16 || cand == 32, "cand must be 16 or 32, got %d", cand);
+    AR_CHECK(k >= 1 && k <= cand, "k must be in [1, cand = %d], got %d", cand, k);
+    AR_CHECK(lib->ctx == ctx, "library belongs to another context");
+    AR_HIP(hipSetDevice(ctx->device));
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t m_pad = idx::round_up(n_roi, idx::BM);
+    const int m_blocks = (int)(m_pad / idx::BM);
+    const int n_tiles = (int)(lib->n_pad / idx::BN);
+    // segments: enough workgroups to fill the chip several times over
+    const int target = 8 * ctx->cu_count;
+    int n_seg = std::max(1, std::min(n_tiles, (target + m_blocks - 1) / m_blocks));
+    const int tiles_per_seg = (n_tiles + n_seg - 1) / n_seg;
+    n_seg = (n_tiles + tiles_per_seg - 1) / tiles_per_seg;
+    const int n_lists = 2 * n_seg;
+
+    AR_TRY(ctx->i_bf16.reserve(sizeof(uint16_t) * (size_t)m_pad * lib->Kp));
+    AR_TRY(ctx->i_inv.reserve(sizeof(float) * (size_t)n_roi * lib->n_win));
+    AR_TRY(ctx->i_cand_score.reserve(sizeof(float) * (size_t)m_pad * n_lists * cand));
+    AR_TRY(ctx->i_cand_idx.reserve(sizeof(int32_t) * (size_t)m_pad * n_lists * cand));
+    AR_TRY(ctx->i_merge_idx.reserve(sizeof(int32_t) * (size_t)n_roi * cand));
+
+    AR_TRY(idx::normalise_cast(images, n_roi, m_pad, lib->n_win, lib->n_dir, lib->Kp, ctx->i_inv.as<float>(),
+                               ctx->i_bf16.as<uint16_t>(), s));
+    if (cand == 16) {
+        AR_TRY(idx::launch_corr<16>(ctx, ctx->i_bf16.as<uint16_t>(), lib, m_blocks, n_tiles, tiles_per_seg, n_seg,
+                                    ctx->i_cand_score.as<float>(), ctx->i_cand_idx.as<int32_t>(), s));
+        idx::k_merge<16><<<(unsigned)((n_roi + 3) / 4), 256, 0, s>>>(
+            ctx->i_cand_score.as<float>(), ctx->i_cand_idx.as<int32_t>(), n_lists, n_roi, ctx->i_merge_idx.as<int32_t>());
+        AR_HIP(hipGetLastError());
+        idx::k_rescore<16><<<(unsigned)n_roi, 256, 0, s>>>(images, ctx->i_inv.as<float>(), lib->ref,
+                                                          lib->inv_max.as<float>(), ctx->i_merge_idx.as<int32_t>(),
+                                                          lib->n_win, lib->n_dir, lib->n_lib, k, top_idx, top_score);
+        AR_HIP(hipGetLastError());
+    } else {
+        AR_TRY(idx::launch_corr<32>(ctx, ctx->i_bf16.as<uint16_t>(), lib, m_blocks, n_tiles, tiles_per_seg, n_seg,
+                                    ctx->i_cand_score.as<float>(), ctx->i_cand_idx.as<int32_t>(), s));
+        idx::k_merge<32><<<(unsigned)((n_roi + 3) / 4), 256, 0, s>>>(
+            ctx->i_cand_score.as<float>(), ctx->i_cand_idx.as<int32_t>(), n_lists, n_roi, ctx->i_merge_idx.as<int32_t>());
+        AR_HIP(hipGetLastError());
+        idx::k_rescore<32><<<(unsigned)n_roi, 256, 0, s>>>(images, ctx->i_inv.as<float>(), lib->ref,
+                                                          lib->inv_max.as<float>(), ctx->i_merge_idx.as<int32_t>(),
+                                                          lib->n_win, lib->n_dir, lib->n_lib, k, top_idx, top_score);
+        AR_HIP(hipGetLastError());
+    }
+    if (cand_idx) {
+        const int64_t n = n_roi * cand;
+        if (cand == 16)
+            idx::k_copy_cand<16><<<(unsigned)((n + 255) / 256), 256, 0, s>>>(ctx->i_merge_idx.as<int32_t>(), n_roi,
+                                                                             cand_idx);
+        else
+            idx::k_copy_cand<32><<<(unsigned)((n + 255) / 256), 256, 0, s>>>(ctx->i_merge_idx.as<int32_t>(), n_roi,
+                                                                             cand_idx);
+        AR_HIP(hipGetLastError());
+    }
+    return AR_OK;
+}
+
+ar_status index_orientations(ar_context *ctx, const float *images, int64_t n_roi, const ar_library *lib, int32_t k,
+                             int32_t *top_idx, float *top_score, void *stream)
+{
+    const int cand = k <= 16 ? 16 : 32;
+    return index_orientations_ex(ctx, images, n_roi, lib, k, cand, top_idx, top_score, nullptr, stream);
 }
 
 }  // extern "C"

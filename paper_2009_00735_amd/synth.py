@@ -428,3 +428,22 @@ def library_orientations(n: int, cfg: int) -> np.ndarray:
 
 def random_orientations(n: int, seed: int) -> np.ndarray:
     return shoemake(n, np.random.Generator(np.random.PCG64(np.random.SeedSequence([SEED_ROOT, 999, seed]))))
+
+
+def planted_images(n_roi: int, n_lib: int, n_win: int, n_dir: int, seed: int, noise: float = 0.05):
+    """Seeded non-negative image sets with a planted match per ROI (inputs for
+    exercising the indexing boundary at full sizes without rotated
+    references): library rows are random; ROI r is the library row truth[r]
+    with a random per-window gain and multiplicative noise.
+    Returns (S float32 [n_roi][n_win][n_dir], L float32 [n_lib][n_win][n_dir],
+    truth int64 [n_roi])."""
+    gen = np.random.Generator(np.random.PCG64(np.random.SeedSequence([SEED_ROOT, 777, seed])))
+    L = np.empty((n_lib, n_win, n_dir), np.float32)
+    for s in range(0, n_lib, 1024):
+        blk = gen.random((min(1024, n_lib - s), n_win, n_dir), dtype=np.float32)
+        L[s:s + len(blk)] = blk * blk
+    truth = gen.integers(0, n_lib, n_roi)
+    gain = gen.uniform(0.5, 2.0, (n_roi, n_win, 1)).astype(np.float32)
+    jitter = 1.0 + noise * gen.standard_normal((n_roi, n_win, n_dir), dtype=np.float32)
+    S = np.abs(L[truth] * gain * jitter).astype(np.float32)
+    return S, L, truth

@@ -1,0 +1,180 @@
+"""GPU <-> oracle parity of the indexing stage (normalise + BF16 MFMA
+correlation + top-k + FP32 rescore), rotated references and disorientation.
+
+Bar (top-1): the GPU's rescored top-1 equals the FP64 oracle's top-1, or is a
+tie: Delta_orc(gpu) - Delta_orc(orc) <= 1e-5 Delta_orc(orc) + 1e-6.
+FP32 Delta of every returned pair within 1e-5 relative (+1e-6) of FP64."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from paper_2009_00735_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def nat():
+    from paper_2009_00735_amd import native
+    return native
+
+
+@pytest.fixture(scope="module")
+def ctx(nat):
+    return nat.Context(0)
+
+
+def dev(a, dtype=torch.float32):
+    return torch.as_tensor(np.ascontiguousarray(a)).to(dtype).cuda()
+
+
+def check_topk(orc, S, L, gidx, gsc, k, report):
+    """S, L raw float32 images; gidx/gsc GPU outputs (numpy)."""
+    Sh = orc.normalise(S)
+    Lh = orc.normalise(L)
+    oidx, osc = orc.index_topk(Sh, Lh, k)
+    n = len(S)
+    ties = 0
+    for r in range(n):
+        if gidx[r, 0] != oidx[r, 0]:
+            d = orc.ssd_pairs(Sh, Lh, [r], [gidx[r, 0]])[0]
+            assert d - osc[r, 0] <= 1e-5 * osc[r, 0] + 1e-6, (r, gidx[r, 0], oidx[r, 0], d, osc[r, 0])
+            ties += 1
+        # FP32 Delta of every returned pair against FP64
+        d64 = orc.ssd_pairs(Sh, Lh, np.full(k, r), gidx[r])
+        assert np.all(np.abs(gsc[r] - d64) <= 1e-5 * d64 + 1e-6), (r, gsc[r], d64)
+        assert np.all(np.diff(gsc[r]) >= 0)
+    report["ties"] = ties
+    report["recall_k"] = float(np.mean([len(set(gidx[r]) & set(oidx[r])) / k for r in range(n)]))
+    return oidx, osc
+
+
+def reference_library(orc, R, nbins, dirs, windows, n_lib, cfg):
+    pts, offs = synth.reference_rois(0, 16, R=R, cfg=cfg)
+    ref, _ = orc.signatures(pts, offs, R, dirs, nbins, windows)
+    R0 = ref.mean(axis=0)
+    q = synth.library_orientations(n_lib, cfg)
+    L = orc.library_images(R0[None], np.zeros(n_lib, np.int32), q, dirs).astype(np.float32)
+    return R0, q, L
+
+
+def test_index_cfg1_rotated_library(nat, ctx, orc):
+    """Config 1: 1000 rotated fcc references (level-3 mesh, 256 bins); the
+    config-1 ROI plus 36 ROIs of other random crystals (ragged M, N, K)."""
+    s = synth.config1()
+    w = orc.windows_for(s.radius, s.nbins, s.spacings)
+    R0, q, L = reference_library(orc, s.radius, s.nbins, s.directions, w, 1000, 1)
+    cents = np.zeros((36, 3), np.float32)
+    imgs = [orc.signatures(s.positions, s.centres, s.radius, s.directions, s.nbins, w)[0]]
+    for i in range(36):
+        qt = synth.random_orientations(1, 500 + i)[0]
+        p = synth.lattice_in_ball("fcc", 0.405, qt, np.random.default_rng(i).random(3), np.zeros(3), 1.5)
+        imgs.append(orc.signatures(p.astype(np.float32), cents[i:i + 1], s.radius, s.directions, s.nbins, w)[0])
+    S = np.concatenate(imgs).astype(np.float32)
+    lib = nat.Library(ctx, dev(L))
+    gidx, gsc = nat.index_orientations(ctx, dev(S), lib, 16)
+    rep = {}
+    check_topk(orc, S, L, gidx.cpu().numpy(), gsc.cpu().numpy(), 16, rep)
+    print("cfg1 indexing:", rep)
+
+
+def test_index_self(nat, ctx, orc):
+    S, L, truth = synth.planted_images(10, 700, 4, 333, seed=3)
+    lib = nat.Library(ctx, dev(L))
+    rows = np.array([0, 5, 127, 128, 129, 699])
+    gidx, gsc = nat.index_orientations(ctx, dev(L[rows]), lib, 4)
+    assert np.array_equal(gidx[:, 0].cpu().numpy(), rows)
+    assert np.all(gsc[:, 0].cpu().numpy() == 0.0)
+
+
+@pytest.mark.parametrize("k,cand", [(1, 16), (16, 16), (5, 32), (32, 32)])
+def test_index_planted_small(nat, ctx, orc, k, cand):
+    S, L, truth = synth.planted_images(300, 1000, 4, 257, seed=k + cand)
+    lib = nat.Library(ctx, dev(L))
+    gidx, gsc, gcand = nat.index_orientations_ex(ctx, dev(S), lib, k, cand)
+    gidx = gidx.cpu().numpy()
+    assert np.array_equal(gidx[:, 0], truth)
+    rep = {}
+    check_topk(orc, S, L, gidx, gsc.cpu().numpy(), k, rep)
+    gcand = gcand.cpu().numpy()
+    assert np.all([truth[r] in gcand[r] for r in range(len(S))])
+
+
+def test_index_planted_bench_shape(nat, ctx, orc):
+    """The benchmark's indexing shape: 2000 ROIs x 20000 references x
+    (4 x 10242) nodes; sampled ROIs against the FP64 oracle."""
+    S, L, truth = synth.planted_images(2000, 20000, 4, 10242, seed=11)
+    lib = nat.Library(ctx, dev(L))
+    Sd = dev(S)
+    gidx, gsc = nat.index_orientations(ctx, Sd, lib, 16)
+    torch.cuda.synchronize()
+    gidx = gidx.cpu().numpy()
+    gsc = gsc.cpu().numpy()
+    assert np.array_equal(gidx[:, 0], truth)
+    sel = np.random.default_rng(0).choice(2000, 10, replace=False)
+    rep = {}
+    check_topk(orc, S[sel], L, gidx[sel], gsc[sel], 16, rep)
+    print("bench-shape indexing:", rep)
+
+
+def test_rotate_reference_matches_oracle(nat, ctx, orc):
+    dirs = synth.icosphere(3)
+    gen = np.random.default_rng(4)
+    ref = gen.random((2, 4, len(dirs))).astype(np.float32)
+    q = synth.library_orientations(300, 9)
+    ph = (np.arange(300) % 2).astype(np.int32)
+    got = nat.ar_rotate_reference(ctx, dev(ref), dev(dirs), dev(q, torch.float64), dev(ph, torch.int32)).cpu().numpy()
+    lut = orc.rotated_nodes(q, dirs)
+    expect = np.stack([ref[ph[l]][:, lut[l]] for l in range(300)])
+    assert np.array_equal(got, expect)
+
+
+def test_disorientation_matches_oracle(nat, orc):
+    gen = np.random.default_rng(5)
+    qa = synth.shoemake(5000, gen)
+    qb = synth.shoemake(5000, gen)
+    qa[:10] = qb[:10]
+    qb[10] = -qa[10]
+    got = nat.ar_disorientation_cubic(dev(qa, torch.float64), dev(qb, torch.float64)).cpu().numpy()
+    ref = orc.disorientation_cubic(qa, qb)
+    assert np.max(np.abs(got - ref)) < 1e-6
+    assert np.all(got[:11] < 1e-5)
+
+
+def test_planted_orientation_end_to_end(nat, ctx, orc):
+    """GPU pipeline at the benchmark mesh (level 5, 1024 bins, R = 2 nm):
+    reference crystal -> GPU signatures -> GPU rotated library (300 random
+    orientations + the true one) -> GPU signatures of noisy ROIs (sigma 0.05,
+    half the atoms) -> GPU indexing: the true orientation ranks first."""
+    R, nb = 2.0, 1024
+    dirs = synth.icosphere(5)
+    w = nat.windows_for(R, nb, synth.window_spacings())
+    pts, offs = synth.reference_rois(0, 16, R=R, cfg=4)
+    ref = nat.araullo_signatures(ctx, dev(pts), dev(offs), R, dev(dirs), nb, w, counts=False).mean(0, keepdim=True)
+    qlib = synth.library_orientations(300, 2)
+    for seed in range(3):
+        qt = synth.random_orientations(1, 100 + seed)[0]
+        q = np.concatenate([qlib, qt[None]])
+        L = nat.ar_rotate_reference(ctx, ref.contiguous(), dev(dirs), dev(q, torch.float64),
+                                    torch.zeros(len(q), dtype=torch.int32, device="cuda"))
+        gen = np.random.default_rng(seed)
+        p = synth.lattice_in_ball("fcc", 0.405, qt, gen.random(3), np.zeros(3), R + 0.5)
+        keep = synth.delete_exact(len(p), 0.5, gen)
+        p = (p[keep] + gen.normal(0, 0.05, (len(keep), 3))).astype(np.float32)
+        img = nat.araullo_signatures(ctx, dev(p), dev(np.zeros((1, 3))), R, dev(dirs), nb, w, counts=False)
+        lib = nat.Library(ctx, L)
+        gidx, _ = nat.index_orientations(ctx, img, lib, 16)
+        assert int(gidx[0, 0]) == len(q) - 1
+
+
+def test_index_invalid_arguments(nat, ctx):
+    S, L, truth = synth.planted_images(4, 200, 2, 64, seed=1)
+    lib = nat.Library(ctx, dev(L))
+    with pytest.raises(nat.AraulloError):
+        nat.index_orientations(ctx, dev(S), lib, 0)
+    with pytest.raises(nat.AraulloError):
+        nat.index_orientations(ctx, dev(S), lib, 33)
+    with pytest.raises(nat.AraulloError):
+        nat.index_orientations_ex(ctx, dev(S), lib, 4, 20)
