@@ -1,0 +1,315 @@
+#!/usr/bin/env python3
+"""Benchmark of the real-space signature + orientation indexing hot path on
+one MI355X, on the single-grain fcc Al workload (config 2 of the benchmark
+definition): a 20 x 20 x 40 nm box at 30 atoms/nm^3, sigma = 0.05 nm,
+2000 ROIs of R = 2 nm on a 2 nm grid, 10242 icosphere directions, 1024 bins,
+4 peak windows, indexed against 20000 rotated fcc references.
+
+One step = the whole hot path over that batch, inputs resident in HBM:
+  a1      ROI query (ar_roi_gather)
+  a2-a5   Eq. (1) histograms + FFT + window maxima, persistent autotuned
+          launch replayed as a HIP graph (ar_signature_plan_run)
+  a6-a8   normalise + BF16 MFMA correlation + top-16 + FP32 rescore
+          (index_orientations)
+  a9      FP64 cubic disorientation of the top-1 against the ground truth
+  a10     50-step structure-factor refinement of the top-1 orientation
+          (ar_refine_orientations)
+
+Prints one JSON line.  `--gpus N` with N > 1 exits: this build targets one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import platform
+import subprocess
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK_FP32_VECTOR = 157.3e12      # MI355X datasheet, FLOP/s (packed FP32 counted)
+PEAK_BF16_DENSE = 2.5e15         # MI355X datasheet, FLOP/s dense
+PEAK_HBM = 8.0e12                # B/s
+F_AL = (4.2767, 4.9383, 6.9838, 8.1892)   # 1/d of fcc Al {111},{200},{220},{311}, nm^-1
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--refine-steps", type=int, default=50)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample-rois", type=int, default=16)
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run a plain device copy of 1 GiB (scale factor for HBM counters)")
+    return ap.parse_args()
+
+
+def cpu_info():
+    model = platform.processor() or ""
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name"):
+                model = line.split(":", 1)[1].strip()
+    except Exception:
+        pass
+    return model
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); this build has no multi-GPU path. "
+              "See DESIGN.md for how the ROI and library axes would shard.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2009_00735_amd import native as nat
+    from paper_2009_00735_amd import synth
+
+    dev = torch.device("cuda", 0)
+    if args.copy_probe:
+        n = 1 << 28
+        a = torch.ones(n, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_read": 4 * n, "copy_probe_bytes_written": 4 * n}))
+        return
+
+    # ------------------------------------------------------------ setup (untimed)
+    t_setup = time.perf_counter()
+    s = synth.config2()
+    n_roi, n_dir, nb, R = len(s.centres), len(s.directions), s.nbins, s.radius
+    ctx = nat.Context(0)
+    pos = torch.from_numpy(s.positions).to(dev)
+    cen = torch.from_numpy(s.centres).to(dev)
+    dirs = torch.from_numpy(s.directions).to(dev)
+    windows = nat.windows_for(R, nb, s.spacings)
+    n_win = windows.shape[0]
+    # reference (noise-free, unrotated fcc Al, 16 in-cell offsets) and library
+    rpos, roffs = synth.reference_rois(0, 16, R=R, cfg=4)
+    rpos_d, roffs_d = torch.from_numpy(rpos).to(dev), torch.from_numpy(roffs).to(dev)
+    ref = nat.araullo_signatures(ctx, rpos_d, roffs_d, R, dirs, nb, windows, counts=False).mean(0, keepdim=True)
+    n_lib = 20000
+    lib_q = synth.library_orientations(n_lib, 2)
+    lib_q_d = torch.from_numpy(lib_q).to(dev)
+    L = nat.ar_rotate_reference(ctx, ref.contiguous(), dirs, lib_q_d, torch.zeros(n_lib, dtype=torch.int32, device=dev))
+    lib = nat.Library(ctx, L)
+    # structure-factor target: amplitudes of the reference ROIs at identity
+    ident = torch.tensor([[1.0, 0, 0, 0]], device=dev).repeat(len(roffs), 1).contiguous()
+    roff_csr, rrel = nat.ar_roi_gather(ctx, rpos_d, roffs_d, R)
+    freqs = torch.tensor([F_AL], dtype=torch.float32, device=dev)
+    T = nat.ar_sf_amplitudes(ctx, rrel.contiguous(), roff_csr, ident, torch.zeros(len(roffs), dtype=torch.int32,
+                                                                                   device=dev), dirs, freqs)
+    T = T.mean(0, keepdim=True).contiguous()
+    truth_q = torch.from_numpy(s.truth_q).to(dev)
+    phase = torch.zeros(n_roi, dtype=torch.int32, device=dev)
+    # gather buffers and the signature plan (autotuned once)
+    off_buf = torch.empty(n_roi + 1, dtype=torch.int64, device=dev)
+    off_buf, rel0 = nat.ar_roi_gather(ctx, pos, cen, R)
+    total = rel0.shape[0]
+    rel_buf = torch.empty((int(total * 1.05) + 64, 4), dtype=torch.float32, device=dev)
+    images = torch.empty((n_roi, n_win, n_dir), dtype=torch.float32, device=dev)
+    plan = nat.SignaturePlan(ctx, n_roi, rel_buf.shape[0], n_dir, nb, n_win)
+    _, rel = nat.ar_roi_gather(ctx, pos, cen, R, out=(off_buf, rel_buf))
+    plan.tune(rel, off_buf, R, dirs, windows, out=images)
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t_setup
+    log(f"setup {t_setup:.1f} s: {n_roi} ROIs, {total} gathered atoms, library {n_lib}, plan {plan.config()}")
+
+    stream = torch.cuda.current_stream(dev)
+    ev = {}
+
+    def mark(name):
+        e = torch.cuda.Event(enable_timing=True)
+        e.record(stream)
+        ev.setdefault(name, []).append(e)
+
+    out = {}
+
+    def step():
+        mark("a1")
+        _, rel = nat.ar_roi_gather(ctx, pos, cen, R, out=(off_buf, rel_buf))
+        mark("a2_a5")
+        plan.run(rel, off_buf, R, dirs, windows, out=images, use_graph=True)
+        mark("a6_a8")
+        idx, score = nat.index_orientations(ctx, images, lib, 16)
+        mark("a9")
+        top_q = lib_q_d[idx[:, 0].long()].contiguous()
+        dis = nat.ar_disorientation_cubic(top_q, truth_q)
+        mark("a10")
+        q = top_q.float().contiguous()
+        nat.ar_refine_orientations(ctx, rel, off_buf, q, phase, dirs, freqs, T, args.refine_steps, 0.01)
+        dis_ref = nat.ar_disorientation_cubic(q.double().contiguous(), truth_q)
+        mark("end")
+        out.update(idx=idx, score=score, dis=dis, dis_ref=dis_ref, q=q)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    ev.clear()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms_step = 1e3 * elapsed / args.steps
+
+    names = ["a1", "a2_a5", "a6_a8", "a9", "a10", "end"]
+    stage_ms = {}
+    for a, b in zip(names[:-1], names[1:]):
+        stage_ms[a] = float(np.mean([x.elapsed_time(y) for x, y in zip(ev[a], ev[b])]))
+    log("stage ms:", json.dumps({k: round(v, 3) for k, v in stage_ms.items()}))
+
+    dis = out["dis"].cpu().numpy()
+    dis_ref = out["dis_ref"].cpu().numpy()
+    counts = torch.diff(off_buf).cpu().numpy()
+    n_w_mean = float(counts.mean())
+
+    # ------------------------------------------------------------ rooflines
+    # a10 adjoint (dominant): per atom x direction x frequency term, 2 sin/cos
+    # + 9 FP32 ops (1 mul phase, 2 adds C,S, 6 FMA for P,Q) + the shared dot
+    # product (3 ops / 4 frequencies).  ALU-bound; peak issue rate derived in
+    # 4 SIMD x 16 lanes per CU per clock for full-rate ops, a
+    # quarter of that for transcendentals -> 18.25 issue slots per term.
+    n_freq = len(F_AL)
+    terms_eval = float(counts.sum()) * n_dir * n_freq
+    evals = args.refine_steps + 1
+    a10_s = stage_ms["a10"] / 1e3
+    clk, cus = 2.4e9, 256
+    slots_per_term = 9 + 3.0 / n_freq + 2 * 4
+    peak_terms = cus * 64 * clk / slots_per_term
+    flop_per_term = 1 + 2 + 12 + 5.0 / n_freq        # algorithmic FP32 flops (FMA = 2)
+    achieved_terms = terms_eval * evals / a10_s
+    roofline = {
+        "kernel": "k_sf<1,4> (structure-factor adjoint, a10)",
+        "bound": "alu",
+        "achieved": achieved_terms * flop_per_term / 1e12,
+        "peak": peak_terms * flop_per_term / 1e12,
+        "unit": "TFLOP/s",
+        "frac": achieved_terms / peak_terms,
+        "traffic": None,
+        "terms_per_s": achieved_terms,
+    }
+    # signatures: algorithmic FP32 flops per ROI x direction = 7 N_w (Eq. (1)
+    # projection + bin) + 2.5 N_b log2 N_b (real FFT) -- against the FP32
+    # vector peak; the persistent launch is the whole a2-a5 stage.
+    sig_flops = (7.0 * n_w_mean + 2.5 * nb * math.log2(nb)) * n_roi * n_dir
+    sig_s = stage_ms["a2_a5"] / 1e3
+    roof_sig = {"kernel": "k_signatures_persistent<10,*> (a2-a5)", "bound": "alu",
+                "achieved": sig_flops / sig_s / 1e12, "peak": PEAK_FP32_VECTOR / 1e12, "unit": "TFLOP/s",
+                "frac": sig_flops / sig_s / PEAK_FP32_VECTOR,
+                "hbm_gbps": (16.0 * counts.sum() + 4.0 * n_roi * n_win * n_dir) / sig_s / 1e9}
+    Kp = lib.n_win * lib.n_dir
+    Kp = (Kp + 63) // 64 * 64
+    gemm_flops = 2.0 * ((n_roi + 127) // 128 * 128) * ((n_lib + 127) // 128 * 128) * Kp
+    roof_idx = {"kernel": "index_orientations (a6-a8, BF16 MFMA correlation + rescore)", "bound": "mfma",
+                "achieved": gemm_flops / (stage_ms["a6_a8"] / 1e3) / 1e12, "peak": PEAK_BF16_DENSE / 1e12,
+                "unit": "TFLOP/s", "frac": gemm_flops / (stage_ms["a6_a8"] / 1e3) / PEAK_BF16_DENSE}
+
+    rec = {
+        "metric": "ROI·direction signatures/s + indexed ROIs/s at fixed top-1 disorientation",
+        "value": n_roi * n_dir / (ms_step / 1e3),
+        "unit": "ROI·direction/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "cfg2 single-grain fcc Al box 20x20x40 nm, 30 atoms/nm^3, sigma 0.05 nm; "
+                               "2000 ROIs R=2 nm; 10242 directions; 1024 bins; 4 windows; "
+                               "20000-orientation library; 50-step refinement",
+                   "n_roi": n_roi, "n_dir": n_dir, "nbins": nb, "n_win": n_win, "n_lib": n_lib,
+                   "mean_atoms_per_roi": n_w_mean, "refine_steps": args.refine_steps,
+                   "signature_plan": dict(zip(["dirs_per_item", "atoms_per_lane", "waves"], plan.config()))},
+        "indexed_rois_per_s": n_roi / (ms_step / 1e3),
+        "stage_ms": stage_ms,
+        "stage_rates": {
+            "signatures_roi_dir_per_s": n_roi * n_dir / (stage_ms["a1"] / 1e3 + sig_s),
+            "indexing_rois_per_s": n_roi / (stage_ms["a6_a8"] / 1e3),
+            "refine_roi_steps_per_s": n_roi * args.refine_steps / a10_s,
+        },
+        "accuracy": {
+            "top1_disorientation_deg": {"median": float(np.median(dis)), "p95": float(np.percentile(dis, 95))},
+            "refined_disorientation_deg": {"median": float(np.median(dis_ref)),
+                                           "p95": float(np.percentile(dis_ref, 95))},
+        },
+        "roofline": roofline,
+        "roofline_signatures": roof_sig,
+        "roofline_indexing": roof_idx,
+    }
+
+    # ------------------------------------------------------------ CPU oracle baseline
+    if not args.no_cpu_baseline:
+        rec["cpu_baseline"] = cpu_baseline(s, windows.numpy(), L, lib_q, ref, T, args, n_lib)
+    print(json.dumps(rec), flush=True)
+
+
+def cpu_baseline(s, windows, L, lib_q, ref, T, args, n_lib):
+    """The oracle, as it stands, on a bounded sample of the same workload:
+    signatures of `cpu_sample_rois` ROIs (all directions), their FP64 indexing
+    against the full library, and the FP64 refinement of the same ROIs for 2
+    iterations (finite-difference gradients), extrapolated per ROI to the
+    step's 50 iterations."""
+    from oracle import oracle as orc
+    threads = orc.default_threads()
+    n = args.cpu_sample_rois
+    sel = np.linspace(0, len(s.centres) - 1, n).astype(int)
+    Lh = None
+    t0 = time.perf_counter()
+    img, cnt = orc.signatures(s.positions, s.centres[sel], s.radius, s.directions, s.nbins, windows, threads)
+    t_sig = time.perf_counter() - t0
+    Lcpu = L.cpu().numpy()
+    t0 = time.perf_counter()
+    Lh = orc.normalise(Lcpu)
+    Sh = orc.normalise(img.astype(np.float32))
+    idx, sc = orc.index_topk(Sh, Lh, 16, threads)
+    t_idx = time.perf_counter() - t0
+    del Lh
+    # refinement: 2 iterations on `threads` ROIs in parallel (one per thread)
+    import concurrent.futures as cf
+    Tn = T.cpu().numpy()[0].astype(np.float64)
+    it = 2
+    rels = [orc.roi_gather(s.positions, s.centres[r], s.radius) for r in sel[:threads]]
+    qs = [lib_q[idx[i, 0]] for i in range(len(rels))]
+    t0 = time.perf_counter()
+    with cf.ThreadPoolExecutor(max_workers=threads) as ex:
+        list(ex.map(lambda a: orc.sf_refine(a[0], a[1], s.directions, np.array(F_AL), Tn, steps=it),
+                    zip(rels, qs)))
+    t_ref = time.perf_counter() - t0
+    per_roi = t_sig / n + t_idx / n + (t_ref / len(rels)) * (args.refine_steps / it)
+    return {
+        "value": len(s.directions) / per_roi,
+        "unit": "ROI·direction/s",
+        "cores": threads,
+        "kind": "oracle",
+        "cpu_model": cpu_info(),
+        "sample": (f"{n} of 2000 ROIs: oracle signatures (all 10242 directions) {t_sig:.1f} s and FP64 indexing "
+                   f"against all {n_lib} references {t_idx:.1f} s; FP64 finite-difference refinement of "
+                   f"{len(rels)} ROIs for {it} iterations {t_ref:.1f} s, scaled per ROI to "
+                   f"{args.refine_steps} iterations; {threads} threads"),
+        "seconds": {"signatures": t_sig, "indexing": t_idx, "refinement_sample": t_ref},
+    }
+
+
+if __name__ == "__main__":
+    main()

@@ -281,11 +281,12 @@ ar_status ar_sf_amplitudes(ar_context *ctx, const float *rel, const int64_t *off
 /*
  * Orientation refinement below the library grid: `steps` iterations of
  * projected gradient descent on J (ar_sf_score_grad) with a per-ROI
- * backtracking step: a trial q' = normalise(q - a g) is accepted iff
- * J(q') <= J(q) - 1e-4 a |g|^2, then a grows by 1.5; otherwise a halves
- * and q stays.  Every iteration evaluates J and its gradient once at the
- * trial points of all ROIs.  Starting step a0 (radian-scale units of q).
+ * backtracking step along the normalised gradient: a trial
+ * q' = normalise(q - a g/|g|) is accepted iff J(q') <= J(q) - 1e-4 a |g|,
+ * then a grows by 1.5; otherwise a halves and q stays.  Every iteration
+ * evaluates J and its gradient once, at the trial points of all ROIs.
  *   quats  device float [n_roi][4], in: start, out: refined
+ *   a0     starting step (quaternion arc length, e.g. 0.01)
  *   score  device float [n_roi] or NULL, out: final J
  * Does not synchronise.
  */

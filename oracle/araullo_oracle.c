@@ -475,3 +475,36 @@ void orc_sf_batch(const float *rel, const int64_t *offsets, int64_t n_roi, const
         if (grad) orc_sf_grad_fd(x, n_w, quats + 4 * r, dirs, n_dir, f, n_freq, T, h, grad + 4 * r);
     }
 }
+
+/* Refinement trajectory (reading R11 plus the stated update rule, FP64 with
+ * central-difference gradients): per iteration a trial q' = normalise(q -
+ * a g/|g|) is accepted iff J(q') <= J(q) - 1e-4 a |g| (then a *= 1.5, the
+ * gradient is re-evaluated at q'), else a *= 0.5.  `steps` trials. */
+double orc_sf_refine(const float *rel, int64_t n_w, double *q, const float *dirs, int32_t n_dir,
+                     const double *freqs, int32_t n_freq, const double *target, int32_t steps, double a0, double h)
+{
+    double n = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+    for (int i = 0; i < 4; ++i) q[i] /= n;
+    double J = orc_sf_score(rel, n_w, q, dirs, n_dir, freqs, n_freq, target);
+    double g[4];
+    orc_sf_grad_fd(rel, n_w, q, dirs, n_dir, freqs, n_freq, target, h, g);
+    double a = a0;
+    for (int it = 0; it < steps; ++it) {
+        double gn = sqrt(g[0] * g[0] + g[1] * g[1] + g[2] * g[2] + g[3] * g[3]);
+        if (gn == 0.0) break;
+        double t[4];
+        for (int i = 0; i < 4; ++i) t[i] = q[i] - a * g[i] / gn;
+        double tn = sqrt(t[0] * t[0] + t[1] * t[1] + t[2] * t[2] + t[3] * t[3]);
+        for (int i = 0; i < 4; ++i) t[i] /= tn;
+        double Jt = orc_sf_score(rel, n_w, t, dirs, n_dir, freqs, n_freq, target);
+        if (Jt <= J - 1e-4 * a * gn) {
+            for (int i = 0; i < 4; ++i) q[i] = t[i];
+            J = Jt;
+            orc_sf_grad_fd(rel, n_w, q, dirs, n_dir, freqs, n_freq, target, h, g);
+            a *= 1.5;
+        } else {
+            a *= 0.5;
+        }
+    }
+    return J;
+}

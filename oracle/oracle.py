@@ -70,6 +70,8 @@ def lib():
         L.orc_sf_grad_fd.argtypes = [F32P, c_i64, F64P, F32P, c_i32, F64P, c_i32, F64P, c_f64, F64P]
         L.orc_sf_batch.argtypes = [F32P, I64P, c_i64, F64P, F32P, c_i32, F64P, c_i32, F64P, c_f64, F64P,
                                    ctypes.c_void_p, c_i32]
+        L.orc_sf_refine.argtypes = [F32P, c_i64, F64P, F32P, c_i32, F64P, c_i32, F64P, c_i32, c_f64, c_f64]
+        L.orc_sf_refine.restype = c_f64
         _lib = L
     return _lib
 
@@ -257,3 +259,13 @@ def sf_batch(rel, offsets, quats, directions, freqs, targets, h: float = 1e-6, g
     lib().orc_sf_batch(rel, off, n, q, d, len(d), f, f.shape[1], T, h, sc,
                        g.ctypes.data if grad else None, threads or default_threads())
     return sc, g
+
+
+def sf_refine(rel, q, directions, freqs, target, steps: int = 50, a0: float = 0.01, h: float = 1e-6):
+    """-> (refined unit quaternion float64 [4], final J)."""
+    rel = _f32(rel).reshape(-1, 3)
+    d = _f32(directions)
+    f = _f64(freqs)
+    qq = _f64(q).copy()
+    J = lib().orc_sf_refine(rel, len(rel), qq, d, len(d), f, len(f), _f64(target), steps, a0, h)
+    return qq, J

@@ -1,29 +1,472 @@
-// Structure-factor refinement (placeholder until the kernels land).
+// Orientation refinement below the library grid with an unbinned
+// structure-factor score built on the direct Fourier transform of Eq. (2)
+// (Sec. 2.2, FSP paragraph), evaluated on spherical shells |k| = f_w along
+// the mesh directions rotated by the ROI orientation q:
+//   u_v = R(q/|q|) n_v,  F_{w,v} = sum_j exp(-2 pi i f_w u_v . x_j) = C - i S,
+//   C = sum_j cos th_j, S = sum_j sin th_j, th_j = 2 pi f_w u_v . x_j,
+//   A = |F| / N_w,  J = sum_{w,v} (A - T_{p,w,v})^2.
+// Adjoint: with P = sum_j x_j sin th_j and Q = sum_j x_j cos th_j,
+//   d|F|/du = 2 pi f (S Q - C P) / |F|,
+//   dJ/du_v = sum_w 2 (A - T) / N_w * d|F|/du,
+//   G = dJ/dR = sum_v (dJ/du_v) n_v^T,
+//   dJ/dq^ = sum_ab G_ab dR_ab/dq^,   dJ/dq = (I - q^ q^T) dJ/dq^ / |q|.
+//
+// gfx950 design: one workgroup per (ROI, 256-direction tile); the ROI's
+// relative coordinates are staged in LDS (broadcast reads: every lane of a
+// wave reads the same atom), each lane owns one direction and all
+// frequencies, sin/cos by the hardware transcendental unit (v_sin_f32 and
+// v_cos_f32 take the phase in turns, so f * (u . x) needs no 2 pi and no
+// range reduction for |f u.x| < 256).  Per-tile partial sums (J and the
+// 3x3 G) are reduced across tiles in a fixed order by a second kernel, so
+// results are deterministic.
+#include <math.h>
+
 #include "ar_internal.h"
+
+namespace ar {
+namespace sf {
+
+constexpr int kTile = 256;       // directions per workgroup
+constexpr int kMaxFreq = 8;
+constexpr int kChunk = 1024;     // atoms staged in LDS per pass
+constexpr int kPartial = 10;     // J + G(3x3)
+
+template <typename T>
+__device__ __forceinline__ void rotation(const T *q, T *M)
+{
+    T w = q[0], x = q[1], y = q[2], z = q[3];
+    const T n = sqrt(w * w + x * x + y * y + z * z);
+    w /= n; x /= n; y /= n; z /= n;
+    M[0] = 1 - 2 * (y * y + z * z); M[1] = 2 * (x * y - w * z);     M[2] = 2 * (x * z + w * y);
+    M[3] = 2 * (x * y + w * z);     M[4] = 1 - 2 * (x * x + z * z); M[5] = 2 * (y * z - w * x);
+    M[6] = 2 * (x * z - w * y);     M[7] = 2 * (y * z + w * x);     M[8] = 1 - 2 * (x * x + y * y);
+}
+
+// MODE 0: score partials; MODE 1: score + gradient partials; MODE 2: amplitudes.
+// NF: number of frequencies (compile-time so the accumulators stay in VGPRs).
+template <int MODE, int NF>
+__global__ __launch_bounds__(kTile) void k_sf(const float4 *__restrict__ rel, const int64_t *__restrict__ offsets,
+                                              const float *__restrict__ quats, const int32_t *__restrict__ phase,
+                                              const float *__restrict__ dirs, int n_dir, int n_tiles,
+                                              const float *__restrict__ freqs, const float *__restrict__ targets,
+                                              float *__restrict__ partials, float *__restrict__ amp)
+{
+    __shared__ float4 xs[kChunk];
+    __shared__ float red[kPartial][kTile / 64];
+    const int64_t r = blockIdx.x / n_tiles;
+    const int tile = blockIdx.x - (int)(r * n_tiles);
+    const int v = tile * kTile + threadIdx.x;
+    const bool valid = v < n_dir;
+    const int p = phase[r];
+    float q[4] = {quats[4 * r], quats[4 * r + 1], quats[4 * r + 2], quats[4 * r + 3]};
+    float M[9];
+    rotation(q, M);
+    float nx = 0.f, ny = 0.f, nz = 0.f;
+    if (valid) {
+        nx = dirs[3 * v];
+        ny = dirs[3 * v + 1];
+        nz = dirs[3 * v + 2];
+    }
+    const float ux = M[0] * nx + M[1] * ny + M[2] * nz;
+    const float uy = M[3] * nx + M[4] * ny + M[5] * nz;
+    const float uz = M[6] * nx + M[7] * ny + M[8] * nz;
+    float f[NF];
+#pragma unroll
+    for (int w = 0; w < NF; ++w) f[w] = freqs[p * NF + w];
+    float C[NF], S[NF], P[NF][3], Q[NF][3];
+#pragma unroll
+    for (int w = 0; w < NF; ++w) {
+        C[w] = S[w] = 0.f;
+        P[w][0] = P[w][1] = P[w][2] = Q[w][0] = Q[w][1] = Q[w][2] = 0.f;
+    }
+    const int64_t off0 = offsets[r];
+    const int nw = (int)(offsets[r + 1] - off0);
+    for (int c0 = 0; c0 < nw; c0 += kChunk) {
+        const int nc = min(kChunk, nw - c0);
+        __syncthreads();
+        for (int i = threadIdx.x; i < nc; i += kTile) xs[i] = rel[off0 + c0 + i];
+        __syncthreads();
+        for (int j = 0; j < nc; ++j) {
+            const float4 x = xs[j];
+            const float s = fmaf(uz, x.z, fmaf(uy, x.y, ux * x.x));
+#pragma unroll
+            for (int w = 0; w < NF; ++w) {
+                const float t = f[w] * s;   // phase in turns
+                const float sn = __builtin_amdgcn_sinf(t);
+                const float cs = __builtin_amdgcn_cosf(t);
+                C[w] += cs;
+                S[w] += sn;
+                if (MODE == 1) {
+                    P[w][0] = fmaf(x.x, sn, P[w][0]);
+                    P[w][1] = fmaf(x.y, sn, P[w][1]);
+                    P[w][2] = fmaf(x.z, sn, P[w][2]);
+                    Q[w][0] = fmaf(x.x, cs, Q[w][0]);
+                    Q[w][1] = fmaf(x.y, cs, Q[w][1]);
+                    Q[w][2] = fmaf(x.z, cs, Q[w][2]);
+                }
+            }
+        }
+    }
+    const float inv_n = nw > 0 ? 1.0f / (float)nw : 0.f;
+    float J = 0.f, gu[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+    for (int w = 0; w < NF; ++w) {
+        const float mag = sqrtf(fmaf(C[w], C[w], S[w] * S[w]));
+        const float A = mag * inv_n;
+        if (MODE == 2) {
+            if (valid) amp[((size_t)r * NF + w) * n_dir + v] = A;
+            continue;
+        }
+        const float e = valid ? A - targets[((size_t)p * NF + w) * n_dir + v] : 0.f;
+        J = fmaf(e, e, J);
+        if (MODE == 1 && valid && mag >= 1e-12f * (float)nw && nw > 0) {
+            const float k = 2.0f * e * inv_n * 6.283185307179586f * f[w] / mag;
+            gu[0] = fmaf(k, S[w] * Q[w][0] - C[w] * P[w][0], gu[0]);
+            gu[1] = fmaf(k, S[w] * Q[w][1] - C[w] * P[w][1], gu[1]);
+            gu[2] = fmaf(k, S[w] * Q[w][2] - C[w] * P[w][2], gu[2]);
+        }
+    }
+    if (MODE == 2) return;
+    float part[kPartial];
+    part[0] = J;
+    part[1] = gu[0] * nx; part[2] = gu[0] * ny; part[3] = gu[0] * nz;
+    part[4] = gu[1] * nx; part[5] = gu[1] * ny; part[6] = gu[1] * nz;
+    part[7] = gu[2] * nx; part[8] = gu[2] * ny; part[9] = gu[2] * nz;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < kPartial; ++k) {
+        float x = part[k];
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
+        if (lane == 0) red[k][wave] = x;
+    }
+    __syncthreads();
+    if (threadIdx.x < kPartial) {
+        float x = 0.f;
+#pragma unroll
+        for (int w = 0; w < kTile / 64; ++w) x += red[threadIdx.x][w];
+        partials[((size_t)r * n_tiles + tile) * kPartial + threadIdx.x] = x;
+    }
+}
+
+// dJ/dq from G for the normalised quaternion, projected on the tangent space.
+__device__ __forceinline__ void grad_from_G(const float *q, const float *G, float *g)
+{
+    const float n = sqrtf(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+    const float w = q[0] / n, x = q[1] / n, y = q[2] / n, z = q[3] / n;
+    // dR/dw, dR/dx, dR/dy, dR/dz (row-major 3x3) of the rotation formula
+    const float D[4][9] = {
+        {0, -2 * z, 2 * y, 2 * z, 0, -2 * x, -2 * y, 2 * x, 0},
+        {0, 2 * y, 2 * z, 2 * y, -4 * x, -2 * w, 2 * z, 2 * w, -4 * x},
+        {-4 * y, 2 * x, 2 * w, 2 * x, 0, 2 * z, -2 * w, 2 * z, -4 * y},
+        {-4 * z, -2 * w, 2 * x, 2 * w, -4 * z, 2 * y, 2 * x, 2 * y, 0}};
+    float gh[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        float a = 0.f;
+#pragma unroll
+        for (int k = 0; k < 9; ++k) a = fmaf(G[k], D[i][k], a);
+        gh[i] = a;
+    }
+    const float qh[4] = {w, x, y, z};
+    const float dot = gh[0] * w + gh[1] * x + gh[2] * y + gh[3] * z;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) g[i] = (gh[i] - qh[i] * dot) / n;
+}
+
+// Sum the tile partials of each ROI in tile order; write score (and grad).
+__global__ __launch_bounds__(256) void k_sf_reduce(const float *__restrict__ partials, int n_tiles, int64_t n_roi,
+                                                   const float *__restrict__ quats, float *__restrict__ score,
+                                                   float *__restrict__ grad)
+{
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n_roi) return;
+    float acc[kPartial];
+#pragma unroll
+    for (int k = 0; k < kPartial; ++k) acc[k] = 0.f;
+    for (int t = 0; t < n_tiles; ++t)
+#pragma unroll
+        for (int k = 0; k < kPartial; ++k) acc[k] += partials[((size_t)r * n_tiles + t) * kPartial + k];
+    if (score) score[r] = acc[0];
+    if (grad) {
+        const float q[4] = {quats[4 * r], quats[4 * r + 1], quats[4 * r + 2], quats[4 * r + 3]};
+        float g[4];
+        grad_from_G(q, acc + 1, g);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) grad[4 * r + i] = g[i];
+    }
+}
+
+// ------------------------------------------------------------ FP64 forward
+__global__ __launch_bounds__(kTile) void k_sf_f64(const float4 *__restrict__ rel, const int64_t *__restrict__ offsets,
+                                                  const double *__restrict__ quats, const int32_t *__restrict__ phase,
+                                                  const float *__restrict__ dirs, int n_dir, int n_tiles,
+                                                  const double *__restrict__ freqs, const double *__restrict__ targets,
+                                                  int n_freq, double *__restrict__ partials)
+{
+    __shared__ float4 xs[kChunk];
+    __shared__ double red[kTile / 64];
+    const int64_t r = blockIdx.x / n_tiles;
+    const int tile = blockIdx.x - (int)(r * n_tiles);
+    const int v = tile * kTile + threadIdx.x;
+    const bool valid = v < n_dir;
+    const int p = phase[r];
+    double q[4] = {quats[4 * r], quats[4 * r + 1], quats[4 * r + 2], quats[4 * r + 3]};
+    double M[9];
+    rotation(q, M);
+    double nx = 0, ny = 0, nz = 0;
+    if (valid) {
+        nx = dirs[3 * v];
+        ny = dirs[3 * v + 1];
+        nz = dirs[3 * v + 2];
+    }
+    const double ux = M[0] * nx + M[1] * ny + M[2] * nz;
+    const double uy = M[3] * nx + M[4] * ny + M[5] * nz;
+    const double uz = M[6] * nx + M[7] * ny + M[8] * nz;
+    double C[kMaxFreq], S[kMaxFreq];
+    for (int w = 0; w < kMaxFreq; ++w) C[w] = S[w] = 0.0;
+    const int64_t off0 = offsets[r];
+    const int nw = (int)(offsets[r + 1] - off0);
+    for (int c0 = 0; c0 < nw; c0 += kChunk) {
+        const int nc = min(kChunk, nw - c0);
+        __syncthreads();
+        for (int i = threadIdx.x; i < nc; i += kTile) xs[i] = rel[off0 + c0 + i];
+        __syncthreads();
+        for (int j = 0; j < nc; ++j) {
+            const float4 x = xs[j];
+            const double s = ux * (double)x.x + uy * (double)x.y + uz * (double)x.z;
+            for (int w = 0; w < n_freq; ++w) {
+                double sn, cs;
+                sincospi(2.0 * freqs[p * n_freq + w] * s, &sn, &cs);
+                C[w] += cs;
+                S[w] += sn;
+            }
+        }
+    }
+    double J = 0.0;
+    for (int w = 0; w < n_freq; ++w) {
+        const double A = nw > 0 ? sqrt(C[w] * C[w] + S[w] * S[w]) / (double)nw : 0.0;
+        const double e = valid ? A - targets[((size_t)p * n_freq + w) * n_dir + v] : 0.0;
+        J += e * e;
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int o = 32; o > 0; o >>= 1) J += __shfl_xor(J, o);
+    if (lane == 0) red[wave] = J;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double x = 0.0;
+        for (int w = 0; w < kTile / 64; ++w) x += red[w];
+        partials[(size_t)r * n_tiles + tile] = x;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_sf_reduce_f64(const double *__restrict__ partials, int n_tiles,
+                                                       int64_t n_roi, double *__restrict__ score)
+{
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n_roi) return;
+    double acc = 0.0;
+    for (int t = 0; t < n_tiles; ++t) acc += partials[(size_t)r * n_tiles + t];
+    score[r] = acc;
+}
+
+// ------------------------------------------------------------ refinement
+struct RefineState {
+    float q[4];      // accepted orientation
+    float g[4];      // gradient at q
+    float J;         // score at q
+    float a;         // step length (radians of quaternion arc)
+};
+
+// Evaluations happen at the trial quaternions `trial`.  Step 0 only
+// initialises the state from the first evaluation.
+__global__ __launch_bounds__(256) void k_refine_update(RefineState *__restrict__ st, float *__restrict__ trial,
+                                                       const float *__restrict__ Jt, const float *__restrict__ gt,
+                                                       int64_t n_roi, int first, float a0)
+{
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n_roi) return;
+    RefineState s = st[r];
+    if (first) {
+        for (int i = 0; i < 4; ++i) {
+            s.q[i] = trial[4 * r + i];
+            s.g[i] = gt[4 * r + i];
+        }
+        s.J = Jt[r];
+        s.a = a0;
+    } else {
+        const float gn = sqrtf(s.g[0] * s.g[0] + s.g[1] * s.g[1] + s.g[2] * s.g[2] + s.g[3] * s.g[3]);
+        if (Jt[r] <= s.J - 1e-4f * s.a * gn) {
+            for (int i = 0; i < 4; ++i) {
+                s.q[i] = trial[4 * r + i];
+                s.g[i] = gt[4 * r + i];
+            }
+            s.J = Jt[r];
+            s.a *= 1.5f;
+        } else {
+            s.a *= 0.5f;
+        }
+    }
+    // next trial: q - a g/|g|, normalised (the current q when g = 0)
+    const float gn = sqrtf(s.g[0] * s.g[0] + s.g[1] * s.g[1] + s.g[2] * s.g[2] + s.g[3] * s.g[3]);
+    float t[4];
+    const float k = gn > 0.f ? s.a / gn : 0.f;
+    for (int i = 0; i < 4; ++i) t[i] = s.q[i] - k * s.g[i];
+    const float tn = sqrtf(t[0] * t[0] + t[1] * t[1] + t[2] * t[2] + t[3] * t[3]);
+    for (int i = 0; i < 4; ++i) trial[4 * r + i] = t[i] / tn;
+    st[r] = s;
+}
+
+__global__ __launch_bounds__(256) void k_refine_finish(const RefineState *__restrict__ st, int64_t n_roi,
+                                                       float *__restrict__ quats, float *__restrict__ score)
+{
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n_roi) return;
+    for (int i = 0; i < 4; ++i) quats[4 * r + i] = st[r].q[i];
+    if (score) score[r] = st[r].J;
+}
+
+__global__ void k_copy4(const float *__restrict__ a, float *__restrict__ b, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < 4 * n) b[i] = a[i];
+}
+
+}  // namespace sf
+
+static ar_status sf_check(ar_context *ctx, const float *rel, const int64_t *offsets, int64_t n_roi, const void *quats,
+                          const int32_t *phase, const float *dirs, int32_t n_dir, const void *freqs, int32_t n_phase,
+                          int32_t n_freq)
+{
+    AR_CHECK(ctx != nullptr, "context is NULL");
+    AR_CHECK(rel && offsets && quats && phase && dirs && freqs, "NULL argument");
+    AR_CHECK(n_roi >= 1 && n_dir >= 1 && n_phase >= 1, "sizes must be >= 1");
+    AR_CHECK(n_freq >= 1 && n_freq <= sf::kMaxFreq, "n_freq must be in [1, %d]", sf::kMaxFreq);
+    const int64_t tiles = (n_dir + sf::kTile - 1) / sf::kTile;
+    AR_CHECK(n_roi * tiles < (int64_t)INT32_MAX, "too many workgroups");
+    return AR_OK;
+}
+
+using SfFn = void (*)(const float4 *, const int64_t *, const float *, const int32_t *, const float *, int, int,
+                     const float *, const float *, float *, float *);
+
+template <int MODE> SfFn sf_kernel(int n_freq)
+{
+    switch (n_freq) {
+    case 1: return sf::k_sf<MODE, 1>;
+    case 2: return sf::k_sf<MODE, 2>;
+    case 3: return sf::k_sf<MODE, 3>;
+    case 4: return sf::k_sf<MODE, 4>;
+    case 5: return sf::k_sf<MODE, 5>;
+    case 6: return sf::k_sf<MODE, 6>;
+    case 7: return sf::k_sf<MODE, 7>;
+    default: return sf::k_sf<MODE, 8>;
+    }
+}
+
+static ar_status sf_launch(ar_context *ctx, int mode, const float *rel, const int64_t *offsets, int64_t n_roi,
+                           const float *quats, const int32_t *phase, const float *dirs, int32_t n_dir,
+                           const float *freqs, const float *targets, int32_t n_freq, float *score, float *grad,
+                           float *amp, hipStream_t s)
+{
+    const int n_tiles = (n_dir + sf::kTile - 1) / sf::kTile;
+    const unsigned blocks = (unsigned)(n_roi * n_tiles);
+    if (mode == 2) {
+        sf_kernel<2>(n_freq)<<<blocks, sf::kTile, 0, s>>>((const float4 *)rel, offsets, quats, phase, dirs, n_dir,
+                                                          n_tiles, freqs, targets, nullptr, amp);
+        AR_HIP(hipGetLastError());
+        return AR_OK;
+    }
+    AR_TRY(ctx->r_partials.reserve(sizeof(float) * (size_t)n_roi * n_tiles * sf::kPartial));
+    float *part = ctx->r_partials.as<float>();
+    SfFn fn = mode == 1 ? sf_kernel<1>(n_freq) : sf_kernel<0>(n_freq);
+    fn<<<blocks, sf::kTile, 0, s>>>((const float4 *)rel, offsets, quats, phase, dirs, n_dir, n_tiles, freqs, targets,
+                                    part, nullptr);
+    AR_HIP(hipGetLastError());
+    sf::k_sf_reduce<<<(unsigned)((n_roi + 255) / 256), 256, 0, s>>>(part, n_tiles, n_roi, quats, score,
+                                                                    mode == 1 ? grad : nullptr);
+    AR_HIP(hipGetLastError());
+    return AR_OK;
+}
+
+}  // namespace ar
 
 extern "C" {
 
-ar_status ar_sf_score_grad(ar_context *, const float *, const int64_t *, int64_t, const float *, const int32_t *,
-                           const float *, int32_t, const float *, const float *, int32_t, int32_t, float *, float *,
-                           void *)
+ar_status ar_sf_score_grad(ar_context *ctx, const float *rel, const int64_t *offsets, int64_t n_roi,
+                           const float *quats, const int32_t *phase, const float *directions, int32_t n_dir,
+                           const float *freqs, const float *targets, int32_t n_phase, int32_t n_freq, float *score,
+                           float *grad, void *stream)
 {
-    return ar::fail(AR_EUNSUPPORTED, "ar_sf_score_grad: not built yet");
+    AR_TRY(ar::sf_check(ctx, rel, offsets, n_roi, quats, phase, directions, n_dir, freqs, n_phase, n_freq));
+    AR_CHECK(targets && score, "targets/score must not be NULL");
+    AR_HIP(hipSetDevice(ctx->device));
+    return ar::sf_launch(ctx, grad ? 1 : 0, rel, offsets, n_roi, quats, phase, directions, n_dir, freqs, targets,
+                         n_freq, score, grad, nullptr, (hipStream_t)stream);
 }
-ar_status ar_sf_score_f64(ar_context *, const float *, const int64_t *, int64_t, const double *, const int32_t *,
-                          const float *, int32_t, const double *, const double *, int32_t, int32_t, double *, void *)
+
+ar_status ar_sf_amplitudes(ar_context *ctx, const float *rel, const int64_t *offsets, int64_t n_roi,
+                           const float *quats, const int32_t *phase, const float *directions, int32_t n_dir,
+                           const float *freqs, int32_t n_phase, int32_t n_freq, float *amp, void *stream)
 {
-    return ar::fail(AR_EUNSUPPORTED, "ar_sf_score_f64: not built yet");
+    AR_TRY(ar::sf_check(ctx, rel, offsets, n_roi, quats, phase, directions, n_dir, freqs, n_phase, n_freq));
+    AR_CHECK(amp != nullptr, "amp is NULL");
+    AR_HIP(hipSetDevice(ctx->device));
+    return ar::sf_launch(ctx, 2, rel, offsets, n_roi, quats, phase, directions, n_dir, freqs, nullptr, n_freq, nullptr,
+                         nullptr, amp, (hipStream_t)stream);
 }
-ar_status ar_sf_amplitudes(ar_context *, const float *, const int64_t *, int64_t, const float *, const int32_t *,
-                           const float *, int32_t, const float *, int32_t, int32_t, float *, void *)
+
+ar_status ar_sf_score_f64(ar_context *ctx, const float *rel, const int64_t *offsets, int64_t n_roi,
+                          const double *quats, const int32_t *phase, const float *directions, int32_t n_dir,
+                          const double *freqs, const double *targets, int32_t n_phase, int32_t n_freq, double *score,
+                          void *stream)
 {
-    return ar::fail(AR_EUNSUPPORTED, "ar_sf_amplitudes: not built yet");
+    AR_TRY(ar::sf_check(ctx, rel, offsets, n_roi, quats, phase, directions, n_dir, freqs, n_phase, n_freq));
+    AR_CHECK(targets && score, "targets/score must not be NULL");
+    AR_HIP(hipSetDevice(ctx->device));
+    hipStream_t s = (hipStream_t)stream;
+    const int n_tiles = (n_dir + ar::sf::kTile - 1) / ar::sf::kTile;
+    AR_TRY(ctx->r_partials.reserve(sizeof(double) * (size_t)n_roi * n_tiles));
+    double *part = ctx->r_partials.as<double>();
+    ar::sf::k_sf_f64<<<(unsigned)(n_roi * n_tiles), ar::sf::kTile, 0, s>>>(
+        (const float4 *)rel, offsets, quats, phase, directions, n_dir, n_tiles, freqs, targets, n_freq, part);
+    AR_HIP(hipGetLastError());
+    ar::sf::k_sf_reduce_f64<<<(unsigned)((n_roi + 255) / 256), 256, 0, s>>>(part, n_tiles, n_roi, score);
+    AR_HIP(hipGetLastError());
+    return AR_OK;
 }
-ar_status ar_refine_orientations(ar_context *, const float *, const int64_t *, int64_t, float *, const int32_t *,
-                                 const float *, int32_t, const float *, const float *, int32_t, int32_t, int32_t,
-                                 float, float *, void *)
+
+ar_status ar_refine_orientations(ar_context *ctx, const float *rel, const int64_t *offsets, int64_t n_roi,
+                                 float *quats, const int32_t *phase, const float *directions, int32_t n_dir,
+                                 const float *freqs, const float *targets, int32_t n_phase, int32_t n_freq,
+                                 int32_t steps, float a0, float *score, void *stream)
 {
-    return ar::fail(AR_EUNSUPPORTED, "ar_refine_orientations: not built yet");
+    AR_TRY(ar::sf_check(ctx, rel, offsets, n_roi, quats, phase, directions, n_dir, freqs, n_phase, n_freq));
+    AR_CHECK(targets != nullptr, "targets is NULL");
+    AR_CHECK(steps >= 0 && steps <= 100000, "steps out of range");
+    AR_CHECK(a0 > 0.f && isfinite(a0), "a0 must be finite and > 0");
+    AR_HIP(hipSetDevice(ctx->device));
+    hipStream_t s = (hipStream_t)stream;
+    // workspace: state, trial quaternions, trial score, trial gradient
+    const size_t st_bytes = sizeof(ar::sf::RefineState) * n_roi;
+    AR_TRY(ctx->r_state.reserve(st_bytes + sizeof(float) * 9 * n_roi + 256));
+    char *base = ctx->r_state.as<char>();
+    auto *st = reinterpret_cast<ar::sf::RefineState *>(base);
+    float *trial = reinterpret_cast<float *>(base + ((st_bytes + 255) / 256) * 256);
+    float *Jt = trial + 4 * n_roi;
+    float *gt = Jt + n_roi;
+    const unsigned nb = (unsigned)((n_roi + 255) / 256);
+    ar::sf::k_copy4<<<(unsigned)((4 * n_roi + 255) / 256), 256, 0, s>>>(quats, trial, n_roi);
+    AR_HIP(hipGetLastError());
+    for (int it = 0; it <= steps; ++it) {
+        AR_TRY(ar::sf_launch(ctx, 1, rel, offsets, n_roi, trial, phase, directions, n_dir, freqs, targets, n_freq, Jt,
+                             gt, nullptr, s));
+        ar::sf::k_refine_update<<<nb, 256, 0, s>>>(st, trial, Jt, gt, n_roi, it == 0 ? 1 : 0, a0);
+        AR_HIP(hipGetLastError());
+    }
+    ar::sf::k_refine_finish<<<nb, 256, 0, s>>>(st, n_roi, quats, score);
+    AR_HIP(hipGetLastError());
+    return AR_OK;
 }
 
 }  // extern "C"

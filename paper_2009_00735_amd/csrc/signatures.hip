@@ -522,9 +522,17 @@ ar_status ar_signature_plan_tune(ar_plan *p, const float *rel, const int64_t *of
     int bd = p->dpi, bm = p->maxa, bb = p->blocks_per_cu;
     const int dpis[] = {8, 16, 32, 64};
     const int bpcs[] = {2, 4, 8};
+    // register chunks below the largest ROI would stream atoms: only try
+    // chunks that hold it, plus the next smaller one
+    std::vector<int64_t> off(n_roi + 1);
+    AR_HIP(hipMemcpyAsync(off.data(), offsets, sizeof(int64_t) * (n_roi + 1), hipMemcpyDeviceToHost, s));
+    AR_HIP(hipStreamSynchronize(s));
+    int64_t big = 0;
+    for (int64_t r = 0; r < n_roi; ++r) big = std::max(big, off[r + 1] - off[r]);
     for (int maxa : ar::sig::kMaxaOptions)
         for (int dpi : dpis)
             for (int bpc : bpcs) {
+                if ((int64_t)maxa * 64 * 2 < big) continue;
                 p->maxa = maxa;
                 p->dpi = dpi;
                 p->blocks_per_cu = bpc;

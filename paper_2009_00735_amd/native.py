@@ -131,15 +131,26 @@ def _host_windows(windows) -> torch.Tensor:
     return w
 
 
-def ar_roi_gather(ctx: Context, positions: torch.Tensor, centres: torch.Tensor, radius: float):
-    """-> (offsets int64 [n_roi+1], rel float32 [total][4]) on the GPU."""
+def ar_roi_gather(ctx: Context, positions: torch.Tensor, centres: torch.Tensor, radius: float,
+                  out: Optional[Tuple[torch.Tensor, torch.Tensor]] = None):
+    """-> (offsets int64 [n_roi+1], rel float32 [total][4]) on the GPU.
+
+    With out=(offsets, rel_buffer) the rows are written into the given
+    buffers (rel_buffer must hold the total; the result is a view of it)."""
     d = ctx.device
     n_roi = centres.shape[0]
-    offsets = torch.empty(n_roi + 1, dtype=torch.int64, device=d)
     total = i64()
     pp = _dev(positions, torch.float32, d, "positions") if positions.numel() else None
     cp = _dev(centres, torch.float32, d, "centres")
     s = _stream(d)
+    if out is not None:
+        offsets, rel = out
+        _dev(offsets, torch.int64, d, "offsets")
+        _dev(rel, torch.float32, d, "rel")
+        _call("ar_roi_gather", ctx.handle, pp, positions.shape[0], cp, n_roi, radius, offsets.data_ptr(),
+              rel.data_ptr(), rel.shape[0], ctypes.byref(total), s)
+        return offsets, rel[:total.value]
+    offsets = torch.empty(n_roi + 1, dtype=torch.int64, device=d)
     _call("ar_roi_gather", ctx.handle, pp, positions.shape[0], cp, n_roi, radius, offsets.data_ptr(), None, 0,
           ctypes.byref(total), s)
     rel = torch.empty((max(total.value, 1), 4), dtype=torch.float32, device=d)

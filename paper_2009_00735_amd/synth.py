@@ -182,14 +182,33 @@ def lattice_in_ball(kind: str, a: float, q: np.ndarray, offset_frac: np.ndarray,
 
 def lattice_in_box(kind: str, a: float, q: np.ndarray, offset_frac: np.ndarray,
                    lo: np.ndarray, hi: np.ndarray) -> np.ndarray:
-    """Lattice sites of a rotated crystal inside the axis-aligned box [lo, hi)."""
+    """Lattice sites of a rotated crystal inside the axis-aligned box [lo, hi);
+    the crystal origin sits at the box centre + R(q) (offset_frac * a).
+    Enumerates the integer cells covering the box's crystal-frame bounding box."""
     lo = np.asarray(lo, dtype=np.float64)
     hi = np.asarray(hi, dtype=np.float64)
     c = 0.5 * (lo + hi)
-    rad = 0.5 * float(np.linalg.norm(hi - lo)) + a
-    pts = lattice_in_ball(kind, a, q, offset_frac, c, rad)
-    keep = np.all((pts >= lo) & (pts < hi), axis=1)
-    return pts[keep]
+    Rm = quat_matrix(q)
+    corners = np.array([[x, y, z] for x in (lo[0], hi[0]) for y in (lo[1], hi[1]) for z in (lo[2], hi[2])]) - c
+    xc = corners @ Rm                                   # crystal-frame coordinates (R^T p)
+    off = np.asarray(offset_frac, dtype=np.float64)
+    i0 = np.floor(xc.min(0) / a - off).astype(int) - 1
+    i1 = np.ceil(xc.max(0) / a - off).astype(int) + 1
+    out = []
+    basis = BASIS[kind]
+    # slab by slab along the first axis to bound temporaries
+    j = np.arange(i0[1], i1[1] + 1, dtype=np.float64)
+    k = np.arange(i0[2], i1[2] + 1, dtype=np.float64)
+    J, K = np.meshgrid(j, k, indexing="ij")
+    JK = np.stack([J.ravel(), K.ravel()], axis=1)
+    for i in range(i0[0], i1[0] + 1):
+        cell = np.concatenate([np.full((len(JK), 1), float(i)), JK], axis=1)
+        pts = ((cell[:, None, :] + basis[None] + off[None, None]) * a).reshape(-1, 3)
+        lab = pts @ Rm.T + c
+        keep = np.all((lab >= lo) & (lab < hi), axis=1)
+        if keep.any():
+            out.append(lab[keep])
+    return np.concatenate(out) if out else np.zeros((0, 3))
 
 
 def delete_exact(n: int, eta: float, gen: np.random.Generator) -> np.ndarray:
@@ -283,14 +302,23 @@ def in_cone(p: np.ndarray) -> np.ndarray:
     return (z >= 0.0) & (z < CONE_H) & (r2 < cone_radius(z) ** 2)
 
 
-def uniform_in_cone(n: int, gen: np.random.Generator) -> np.ndarray:
-    rb = cone_radius(0.0)
+def in_cone_dilated(p: np.ndarray, margin: float) -> np.ndarray:
+    """Points within `margin` (radially and axially) of the cone."""
+    z = p[:, 2]
+    r2 = p[:, 0] ** 2 + p[:, 1] ** 2
+    return (z >= -margin) & (z < CONE_H + margin) & (r2 < (cone_radius(np.clip(z, 0.0, CONE_H)) + margin) ** 2)
+
+
+def uniform_in_cone(n: int, gen: np.random.Generator, margin: float = 0.0) -> np.ndarray:
+    """n points uniform in the cone dilated by `margin` (rejection sampling)."""
+    rb = cone_radius(0.0) + margin
     out = []
     got = 0
     while got < n:
         m = max(2 * (n - got), 64)
-        p = np.stack([gen.uniform(-rb, rb, m), gen.uniform(-rb, rb, m), gen.uniform(0.0, CONE_H, m)], axis=1)
-        p = p[in_cone(p)]
+        p = np.stack([gen.uniform(-rb, rb, m), gen.uniform(-rb, rb, m),
+                      gen.uniform(-margin, CONE_H + margin, m)], axis=1)
+        p = p[in_cone_dilated(p, margin) if margin > 0 else in_cone(p)]
         out.append(p)
         got += len(p)
     return np.concatenate(out)[:n]
@@ -307,7 +335,9 @@ def polycrystal(n_grains: int = 20, eta: float = 0.5, sigma: float = 0.05, cfg: 
     key = (n_grains, eta, sigma, cfg)
     if key in _POLY_CACHE:
         return _POLY_CACHE[key]
+    from scipy.spatial import cKDTree
     seeds = uniform_in_cone(n_grains, rng(cfg, STREAM_VORONOI))
+    seed_tree = cKDTree(seeds)
     gq = shoemake(n_grains, rng(cfg, STREAM_ORIENTATION))
     goff = rng(cfg, STREAM_OFFSET).random((n_grains, 3))
     gphase = (np.arange(n_grains) % 2).astype(np.int32)
@@ -322,7 +352,7 @@ def polycrystal(n_grains: int = 20, eta: float = 0.5, sigma: float = 0.05, cfg: 
     near_cone = (z > -2 * h) & (z < CONE_H + 2 * h) & (
         vox[:, 0] ** 2 + vox[:, 1] ** 2 < (cone_radius(np.clip(z, 0.0, CONE_H)) + 2 * h) ** 2)
     vox = vox[near_cone]
-    near = np.argmin(((vox[:, None, :] - seeds[None, :, :]) ** 2).sum(-1), axis=1)
+    near = seed_tree.query(vox, workers=-1)[1]
     all_pts, all_g = [], []
     for g in range(n_grains):
         vg = vox[near == g]
@@ -333,13 +363,8 @@ def polycrystal(n_grains: int = 20, eta: float = 0.5, sigma: float = 0.05, cfg: 
         kind, a = PHASES[gphase[g]]
         pts = lattice_in_box(kind, a, gq[g], goff[g], lo, hi)
         pts = pts[in_cone(pts)]
-        # nearest seed must be g (chunked)
-        keep = np.zeros(len(pts), bool)
-        for s in range(0, len(pts), 1 << 18):
-            blk = pts[s:s + (1 << 18)]
-            d = ((blk[:, None, :] - seeds[None, :, :]) ** 2).sum(-1)
-            keep[s:s + len(blk)] = np.argmin(d, axis=1) == g
-        pts = pts[keep]
+        # nearest seed must be g
+        pts = pts[seed_tree.query(pts, workers=-1)[1] == g]
         all_pts.append(pts)
         all_g.append(np.full(len(pts), g, np.int32))
     pts = np.concatenate(all_pts)
@@ -355,7 +380,7 @@ def _roi_truth(tree, pos64, grain, centres, R):
     counts = np.zeros(len(centres), np.int64)
     dom = np.zeros(len(centres), np.int32)
     share = np.zeros(len(centres))
-    for i, idx in enumerate(tree.query_ball_point(centres, R)):
+    for i, idx in enumerate(tree.query_ball_point(centres, R, workers=-1)):
         counts[i] = len(idx)
         if len(idx):
             b = np.bincount(grain[idx])
@@ -377,7 +402,8 @@ def polycrystal_rois(n_roi: int, min_atoms: int = 100, max_atoms: Optional[int] 
     acc_c, acc_g, acc_s, acc_n = [], [], [], []
     got = 0
     while got < n_roi:
-        cand = uniform_in_cone(max(2 * (n_roi - got), 256), gen)
+        # centres up to 0.9 R outside the surface: clipped ROIs keep >= min_atoms
+        cand = uniform_in_cone(max(2 * (n_roi - got), 256), gen, margin=0.9 * R)
         counts, dom, share = _roi_truth(tree, pos, grain, cand, R)
         ok = counts >= min_atoms
         if max_atoms is not None:

@@ -1,0 +1,157 @@
+"""Structure-factor score, its hand-written adjoint and the refinement loop:
+GPU (FP32) against the FP64 oracle; gradient against FP64 central finite
+differences to a relative 1e-3."""
+import numpy as np
+import pytest
+import torch
+
+from paper_2009_00735_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+F_AL = np.array([4.2767, 4.9383, 6.9838, 8.1892])   # 1/d of fcc Al {111},{200},{220},{311}
+
+
+@pytest.fixture(scope="module")
+def nat():
+    from paper_2009_00735_amd import native
+    return native
+
+
+@pytest.fixture(scope="module")
+def ctx(nat):
+    return nat.Context(0)
+
+
+def dev(a, dtype=torch.float32):
+    return torch.as_tensor(np.ascontiguousarray(a)).to(dtype).cuda()
+
+
+def qmul(a, b):
+    w1, x1, y1, z1 = a
+    w2, x2, y2, z2 = b
+    return np.array([w1 * w2 - x1 * x2 - y1 * y2 - z1 * z2, w1 * x2 + x1 * w2 + y1 * z2 - z1 * y2,
+                     w1 * y2 - x1 * z2 + y1 * w2 + z1 * x2, w1 * z2 + x1 * y2 - y1 * x2 + z1 * w2])
+
+
+def make_case(orc, level, n_roi, sigma=0.05, eta=0.5, R=2.0, seed=0, off_deg=3.0):
+    """ROIs cut from fcc Al crystals at random true orientations, start
+    orientations rotated `off_deg` away; target from the unrotated crystal
+    (FP64 oracle, cast to float32 and shared by both sides)."""
+    dirs = synth.icosphere(level)
+    ref = synth.lattice_in_ball("fcc", 0.405, np.array([1.0, 0, 0, 0]), np.zeros(3), np.zeros(3), R + 0.5)
+    rel0 = orc.roi_gather(ref.astype(np.float32), np.array([0.01, 0.02, -0.015], np.float32), R)
+    T = orc.sf_amplitudes(rel0, np.array([1.0, 0, 0, 0]), dirs, F_AL).astype(np.float32)
+    rels, q0s, qts = [], [], []
+    gen = np.random.default_rng(seed)
+    for i in range(n_roi):
+        qt = synth.random_orientations(1, 300 + seed * 100 + i)[0]
+        p = synth.lattice_in_ball("fcc", 0.405, qt, gen.random(3), np.zeros(3), R + 0.5)
+        keep = synth.delete_exact(len(p), eta, gen)
+        p = (p[keep] + gen.normal(0, sigma, (len(keep), 3))).astype(np.float32)
+        rels.append(orc.roi_gather(p, np.zeros(3, np.float32), R))
+        axis = gen.normal(size=3)
+        q0s.append(qmul(qt, synth.quat_axis_angle(axis, off_deg)))
+        qts.append(qt)
+    offsets = np.concatenate([[0], np.cumsum([len(r) for r in rels])]).astype(np.int64)
+    rel4 = np.zeros((offsets[-1], 4), np.float32)
+    rel4[:, :3] = np.concatenate(rels)
+    return dirs, T, rels, offsets, rel4, np.array(q0s), np.array(qts)
+
+
+def gpu_args(dirs, T, offsets, rel4, n_roi):
+    return (dev(rel4), dev(offsets, torch.int64), dev(np.zeros(n_roi, np.int32), torch.int32), dev(dirs),
+            dev(F_AL[None]), dev(T[None]))
+
+
+def test_amplitudes_and_score_match_fp64(nat, ctx, orc):
+    dirs, T, rels, offsets, rel4, q0, qt = make_case(orc, 3, 4)
+    rel, off, ph, d, f, t = gpu_args(dirs, T, offsets, rel4, 4)
+    amp = nat.ar_sf_amplitudes(ctx, rel, off, dev(q0), ph, d, f).cpu().numpy()
+    score, _ = nat.ar_sf_score_grad(ctx, rel, off, dev(q0), ph, d, f, t, grad=False)
+    q0f = q0.astype(np.float32).astype(np.float64)     # the same quaternion both sides see
+    s64 = nat.ar_sf_score_f64(ctx, rel, off, dev(q0f, torch.float64), ph, d, dev(F_AL[None], torch.float64),
+                              dev(T[None].astype(np.float64), torch.float64)).cpu().numpy()
+    for r in range(4):
+        a_ref = orc.sf_amplitudes(rels[r], q0[r].astype(np.float32).astype(np.float64), dirs, F_AL)
+        assert np.max(np.abs(amp[r] - a_ref)) < 2e-6
+        j_ref = orc.sf_score(rels[r], q0[r].astype(np.float32).astype(np.float64), dirs, F_AL, T.astype(np.float64))
+        assert abs(float(score[r]) - j_ref) <= 1e-5 * j_ref
+        assert abs(s64[r] - j_ref) <= 1e-9 * j_ref
+
+
+@pytest.mark.parametrize("level", [3, 5])
+def test_adjoint_matches_fp64_finite_differences(nat, ctx, orc, level):
+    n = 3 if level == 3 else 2
+    dirs, T, rels, offsets, rel4, q0, qt = make_case(orc, level, n, seed=level)
+    rel, off, ph, d, f, t = gpu_args(dirs, T, offsets, rel4, n)
+    qf = q0.astype(np.float32)
+    _, g = nat.ar_sf_score_grad(ctx, rel, off, dev(qf), ph, d, f, t, grad=True)
+    g = g.cpu().numpy().astype(np.float64)
+    # FP64 central differences: oracle (CPU) at level 3, the GPU FP64 forward at level 5
+    h = 1e-6
+    for r in range(n):
+        q64 = qf[r].astype(np.float64)
+        if level == 3:
+            fd = orc.sf_grad_fd(rels[r], q64, dirs, F_AL, T.astype(np.float64), h)
+        else:
+            qs = []
+            for c in range(4):
+                for sgn in (1, -1):
+                    qq = q64.copy()
+                    qq[c] += sgn * h
+                    qs.append(qq)
+            qs = np.array(qs)
+            reps = 8
+            o1 = np.array([offsets[r], offsets[r + 1]])
+            relr = rel4[offsets[r]:offsets[r + 1]]
+            offr = np.array([k * len(relr) for k in range(reps + 1)], np.int64)
+            relrep = np.tile(relr, (reps, 1))
+            js = nat.ar_sf_score_f64(ctx, dev(relrep), dev(offr, torch.int64), dev(qs, torch.float64),
+                                     dev(np.zeros(reps, np.int32), torch.int32), d, dev(F_AL[None], torch.float64),
+                                     dev(T[None].astype(np.float64), torch.float64)).cpu().numpy()
+            fd = np.array([(js[2 * c] - js[2 * c + 1]) / (2 * h) for c in range(4)])
+        err = np.linalg.norm(g[r] - fd) / np.linalg.norm(fd)
+        assert err <= 1e-3, (level, r, g[r], fd, err)
+
+
+def test_autograd_function_uses_the_adjoint(nat, ctx, orc):
+    from paper_2009_00735_amd import refine
+    dirs, T, rels, offsets, rel4, q0, qt = make_case(orc, 3, 3, seed=7)
+    rel, off, ph, d, f, t = gpu_args(dirs, T, offsets, rel4, 3)
+    q = dev(q0).requires_grad_(True)
+    J = refine.sf_score(ctx, q, rel, off, ph, d, f, t)
+    w = torch.tensor([1.0, 2.0, -0.5], device="cuda")
+    (J * w).sum().backward()
+    _, g = nat.ar_sf_score_grad(ctx, rel, off, dev(q0), ph, d, f, t, grad=True)
+    assert torch.allclose(q.grad, g * w[:, None], rtol=1e-6, atol=0)
+
+
+def test_degenerate_rois_have_zero_gradient(nat, ctx):
+    dirs = synth.icosphere(2)
+    T = np.full((1, 4, len(dirs)), 0.3, np.float32)
+    rel4 = np.array([[0.3, -0.2, 0.1, 0.0]], np.float32)          # one atom, then an empty ROI
+    offsets = np.array([0, 1, 1], np.int64)
+    q = synth.random_orientations(2, 1).astype(np.float32)
+    score, g = nat.ar_sf_score_grad(ctx, dev(rel4), dev(offsets, torch.int64), dev(q),
+                                    dev(np.zeros(2, np.int32), torch.int32), dev(dirs), dev(F_AL[None]), dev(T))
+    g = g.cpu().numpy()
+    assert np.allclose(g, 0.0, atol=1e-4)
+    s = score.cpu().numpy()
+    assert abs(s[0] - 4 * len(dirs) * 0.7 ** 2) < 1e-2        # A = 1 for one atom
+    assert abs(s[1] - 4 * len(dirs) * 0.3 ** 2) < 1e-3        # A = 0 for no atom
+
+
+def test_refinement_recovers_orientation_and_tracks_oracle(nat, ctx, orc):
+    dirs, T, rels, offsets, rel4, q0, qt = make_case(orc, 3, 6, sigma=0.03, seed=2, off_deg=3.0)
+    rel, off, ph, d, f, t = gpu_args(dirs, T, offsets, rel4, 6)
+    q = dev(q0)
+    nat.ar_refine_orientations(ctx, rel, off, q, ph, d, f, t, steps=50, a0=0.01)
+    qr = q.cpu().numpy().astype(np.float64)
+    start = orc.disorientation_cubic(q0, qt)
+    end = orc.disorientation_cubic(qr, qt)
+    assert np.all(end < 0.5 * start) and np.median(end) < 0.5, (start, end)
+    # the FP64 oracle trajectory of the same update rule lands on the same orientation
+    qo, Jo = orc.sf_refine(rels[0], q0[0].astype(np.float32).astype(np.float64), dirs, F_AL, T.astype(np.float64),
+                           steps=50, a0=0.01)
+    assert orc.disorientation_cubic(qo, qr[0])[0] < 0.1
