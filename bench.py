@@ -182,29 +182,33 @@ def main():
     n_w_mean = float(counts.mean())
 
     # ------------------------------------------------------------ rooflines
-    # a10 adjoint (dominant): per atom x direction x frequency term, 2 sin/cos
-    # + 9 FP32 ops (1 mul phase, 2 adds C,S, 6 FMA for P,Q) + the shared dot
-    # product (3 ops / 4 frequencies).  ALU-bound; peak issue rate derived in
-    # 4 SIMD x 16 lanes per CU per clock for full-rate ops, a
-    # quarter of that for transcendentals -> 18.25 issue slots per term.
+    # a10 adjoint (dominant).  Unit: one (atom, evaluated direction,
+    # frequency) term; antipodal mesh directions share one evaluation, so
+    # n_eval = n_dir / 2 for the icosphere.  Algorithmic FP32 operations per
+    # term (FMA = 2 flops, sin and cos 1 each): phase 1 + sin/cos 2 + C,S
+    # accumulation 2 + P,Q accumulation 6 FMA = 12, plus the shared dot
+    # product 5/n_freq.  Bound: FP32 vector ALU, peak 157.3 TFLOP/s.
     n_freq = len(F_AL)
-    terms_eval = float(counts.sum()) * n_dir * n_freq
+    key = {tuple(v): i for i, v in enumerate(s.directions.tolist())}
+    n_eval = 0
+    for i, v in enumerate(s.directions.tolist()):
+        m = key.get(tuple(-x for x in v), -1)
+        n_eval += 1 if (m < 0 or m > i) else 0
+    terms_eval = float(counts.sum()) * n_eval * n_freq
     evals = args.refine_steps + 1
     a10_s = stage_ms["a10"] / 1e3
-    clk, cus = 2.4e9, 256
-    slots_per_term = 9 + 3.0 / n_freq + 2 * 4
-    peak_terms = cus * 64 * clk / slots_per_term
-    flop_per_term = 1 + 2 + 12 + 5.0 / n_freq        # algorithmic FP32 flops (FMA = 2)
+    flop_per_term = 1 + 2 + 2 + 12 + 5.0 / n_freq
     achieved_terms = terms_eval * evals / a10_s
     roofline = {
         "kernel": "k_sf<1,4> (structure-factor adjoint, a10)",
         "bound": "alu",
         "achieved": achieved_terms * flop_per_term / 1e12,
-        "peak": peak_terms * flop_per_term / 1e12,
+        "peak": PEAK_FP32_VECTOR / 1e12,
         "unit": "TFLOP/s",
-        "frac": achieved_terms / peak_terms,
+        "frac": achieved_terms * flop_per_term / PEAK_FP32_VECTOR,
         "traffic": None,
         "terms_per_s": achieved_terms,
+        "evaluated_directions": n_eval,
     }
     # signatures: algorithmic FP32 flops per ROI x direction = 7 N_w (Eq. (1)
     # projection + bin) + 2.5 N_b log2 N_b (real FFT) -- against the FP32

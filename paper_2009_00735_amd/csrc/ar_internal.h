@@ -79,7 +79,7 @@ struct ar_context {
     // indexing workspace
     ar::DeviceBuffer i_bf16, i_inv, i_cand_idx, i_cand_score, i_merge_idx;
     // refinement workspace
-    ar::DeviceBuffer r_partials, r_state;
+    ar::DeviceBuffer r_partials, r_state, r_dirs;
     // twiddle tables exp(-2 pi i j / nbins), j < nbins, per nbins
     std::map<int, std::unique_ptr<ar::DeviceBuffer>> twiddles;
     ar_status twiddle_table(int nbins, const float2 **out);

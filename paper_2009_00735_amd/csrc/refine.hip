@@ -19,6 +19,13 @@
 // range reduction for |f u.x| < 256).  Per-tile partial sums (J and the
 // 3x3 G) are reduced across tiles in a fixed order by a second kernel, so
 // results are deterministic.
+//
+// Antipodal pairs: F(-u) is the complex conjugate of F(u), so A(-u) = A(u).
+// The geodesic mesh is centrally symmetric (n_v' = -n_v exactly), so each
+// antipodal pair is evaluated once: with e = A - T_v and e' = A - T_v',
+// J gains e^2 + e'^2 and the pair's gradient is (e + e') dA/du_v n_v^T
+// (d/dR of A(R n_v') equals d/dR of A(R n_v) because A is even in u).
+// Directions without an exact antipode are evaluated on their own.
 #include <math.h>
 
 #include "ar_internal.h"
@@ -47,7 +54,9 @@ __device__ __forceinline__ void rotation(const T *q, T *M)
 template <int MODE, int NF>
 __global__ __launch_bounds__(kTile) void k_sf(const float4 *__restrict__ rel, const int64_t *__restrict__ offsets,
                                               const float *__restrict__ quats, const int32_t *__restrict__ phase,
-                                              const float *__restrict__ dirs, int n_dir, int n_tiles,
+                                              const float *__restrict__ dirs, int n_dir, const int32_t *__restrict__ rep,
+                                              const int32_t *__restrict__ mate, const int32_t *__restrict__ n_eval_p,
+                                              int n_tiles,
                                               const float *__restrict__ freqs, const float *__restrict__ targets,
                                               float *__restrict__ partials, float *__restrict__ amp)
 {
@@ -55,8 +64,15 @@ __global__ __launch_bounds__(kTile) void k_sf(const float4 *__restrict__ rel, co
     __shared__ float red[kPartial][kTile / 64];
     const int64_t r = blockIdx.x / n_tiles;
     const int tile = blockIdx.x - (int)(r * n_tiles);
-    const int v = tile * kTile + threadIdx.x;
-    const bool valid = v < n_dir;
+    const int n_eval = *n_eval_p;
+    if (tile * kTile >= n_eval) {       // tiles past the evaluation list: nothing to add
+        if (MODE != 2 && threadIdx.x < kPartial) partials[((size_t)r * n_tiles + tile) * kPartial + threadIdx.x] = 0.f;
+        return;
+    }
+    const int i_eval = tile * kTile + threadIdx.x;
+    const bool valid = i_eval < n_eval;
+    const int v = valid ? rep[i_eval] : 0;
+    const int vm = valid ? mate[i_eval] : -1;
     const int p = phase[r];
     float q[4] = {quats[4 * r], quats[4 * r + 1], quats[4 * r + 2], quats[4 * r + 3]};
     float M[9];
@@ -114,13 +130,18 @@ __global__ __launch_bounds__(kTile) void k_sf(const float4 *__restrict__ rel, co
         const float mag = sqrtf(fmaf(C[w], C[w], S[w] * S[w]));
         const float A = mag * inv_n;
         if (MODE == 2) {
-            if (valid) amp[((size_t)r * NF + w) * n_dir + v] = A;
+            if (valid) {
+                amp[((size_t)r * NF + w) * n_dir + v] = A;
+                if (vm >= 0) amp[((size_t)r * NF + w) * n_dir + vm] = A;
+            }
             continue;
         }
         const float e = valid ? A - targets[((size_t)p * NF + w) * n_dir + v] : 0.f;
+        const float em = (valid && vm >= 0) ? A - targets[((size_t)p * NF + w) * n_dir + vm] : 0.f;
         J = fmaf(e, e, J);
+        J = fmaf(em, em, J);
         if (MODE == 1 && valid && mag >= 1e-12f * (float)nw && nw > 0) {
-            const float k = 2.0f * e * inv_n * 6.283185307179586f * f[w] / mag;
+            const float k = 2.0f * (e + em) * inv_n * 6.283185307179586f * f[w] / mag;
             gu[0] = fmaf(k, S[w] * Q[w][0] - C[w] * P[w][0], gu[0]);
             gu[1] = fmaf(k, S[w] * Q[w][1] - C[w] * P[w][1], gu[1]);
             gu[2] = fmaf(k, S[w] * Q[w][2] - C[w] * P[w][2], gu[2]);
@@ -147,6 +168,77 @@ __global__ __launch_bounds__(kTile) void k_sf(const float4 *__restrict__ rel, co
         for (int w = 0; w < kTile / 64; ++w) x += red[threadIdx.x][w];
         partials[((size_t)r * n_tiles + tile) * kPartial + threadIdx.x] = x;
     }
+}
+
+// Antipodal pairing of the directions.  mate_of[v] = the smallest u with
+// n_u == -n_v exactly, else -1.  One thread per v, all u scanned (done once
+// per call; the list is rebuilt on the device, nothing is cached by pointer).
+__global__ __launch_bounds__(256) void k_antipodes(const float *__restrict__ dirs, int n_dir,
+                                                   int32_t *__restrict__ mate_of)
+{
+    __shared__ float sd[3 * 256];
+    const int v = blockIdx.x * blockDim.x + threadIdx.x;
+    float x = 0.f, y = 0.f, z = 0.f;
+    if (v < n_dir) {
+        x = -dirs[3 * v];
+        y = -dirs[3 * v + 1];
+        z = -dirs[3 * v + 2];
+    }
+    int found = -1;
+    for (int u0 = 0; u0 < n_dir; u0 += 256) {
+        __syncthreads();
+        const int u = u0 + threadIdx.x;
+        if (u < n_dir) {
+            sd[3 * threadIdx.x] = dirs[3 * u];
+            sd[3 * threadIdx.x + 1] = dirs[3 * u + 1];
+            sd[3 * threadIdx.x + 2] = dirs[3 * u + 2];
+        }
+        __syncthreads();
+        const int m = min(256, n_dir - u0);
+        for (int k = 0; k < m; ++k)
+            if (found < 0 && sd[3 * k] == x && sd[3 * k + 1] == y && sd[3 * k + 2] == z) found = u0 + k;
+    }
+    if (v < n_dir) mate_of[v] = found;
+}
+
+// Evaluation list: v is evaluated iff it has no antipode or its antipode has
+// a larger index (then mate = antipode).  Written in index order by one
+// workgroup with a block-wide prefix sum.
+__global__ __launch_bounds__(1024) void k_eval_list(const int32_t *__restrict__ mate_of, int n_dir,
+                                                    int32_t *__restrict__ rep, int32_t *__restrict__ mate,
+                                                    int32_t *__restrict__ n_eval)
+{
+    __shared__ int32_t scan[1024];
+    __shared__ int32_t base;
+    if (threadIdx.x == 0) base = 0;
+    __syncthreads();
+    for (int v0 = 0; v0 < n_dir; v0 += 1024) {
+        const int v = v0 + threadIdx.x;
+        int keep = 0, m = -1;
+        if (v < n_dir) {
+            m = mate_of[v];
+            // pairs need mutual mates (n_v' = -n_v both ways); self-pairs cannot occur
+            keep = (m < 0 || m > v) ? 1 : 0;
+            if (m >= 0 && mate_of[m] != v) { keep = 1; m = -1; }
+        }
+        scan[threadIdx.x] = keep;
+        __syncthreads();
+        for (int o = 1; o < 1024; o <<= 1) {
+            const int t = threadIdx.x >= o ? scan[threadIdx.x - o] : 0;
+            __syncthreads();
+            scan[threadIdx.x] += t;
+            __syncthreads();
+        }
+        if (keep) {
+            const int pos = base + scan[threadIdx.x] - 1;
+            rep[pos] = v;
+            mate[pos] = m;
+        }
+        __syncthreads();
+        if (threadIdx.x == 1023) base += scan[1023];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *n_eval = base;
 }
 
 // dJ/dq from G for the normalised quaternion, projected on the tangent space.
@@ -347,8 +439,26 @@ static ar_status sf_check(ar_context *ctx, const float *rel, const int64_t *offs
     return AR_OK;
 }
 
-using SfFn = void (*)(const float4 *, const int64_t *, const float *, const int32_t *, const float *, int, int,
-                     const float *, const float *, float *, float *);
+using SfFn = void (*)(const float4 *, const int64_t *, const float *, const int32_t *, const float *, int,
+                     const int32_t *, const int32_t *, const int32_t *, int, const float *, const float *, float *,
+                     float *);
+
+// Device evaluation list for `dirs` in ctx workspace: rep, mate [n_dir], n_eval.
+static ar_status eval_list(ar_context *ctx, const float *dirs, int32_t n_dir, const int32_t **rep,
+                           const int32_t **mate, const int32_t **n_eval, hipStream_t s)
+{
+    AR_TRY(ctx->r_dirs.reserve(sizeof(int32_t) * (3 * (size_t)n_dir + 1)));
+    int32_t *base = ctx->r_dirs.as<int32_t>();
+    int32_t *mate_of = base, *r = base + n_dir, *m = base + 2 * n_dir, *n = base + 3 * n_dir;
+    sf::k_antipodes<<<(unsigned)((n_dir + 255) / 256), 256, 0, s>>>(dirs, n_dir, mate_of);
+    AR_HIP(hipGetLastError());
+    sf::k_eval_list<<<1, 1024, 0, s>>>(mate_of, n_dir, r, m, n);
+    AR_HIP(hipGetLastError());
+    *rep = r;
+    *mate = m;
+    *n_eval = n;
+    return AR_OK;
+}
 
 template <int MODE> SfFn sf_kernel(int n_freq)
 {
@@ -367,21 +477,27 @@ template <int MODE> SfFn sf_kernel(int n_freq)
 static ar_status sf_launch(ar_context *ctx, int mode, const float *rel, const int64_t *offsets, int64_t n_roi,
                            const float *quats, const int32_t *phase, const float *dirs, int32_t n_dir,
                            const float *freqs, const float *targets, int32_t n_freq, float *score, float *grad,
-                           float *amp, hipStream_t s)
+                           float *amp, hipStream_t s, bool have_list = false)
 {
+    if (!have_list) {
+        const int32_t *a, *b, *c;
+        AR_TRY(eval_list(ctx, dirs, n_dir, &a, &b, &c, s));
+    }
+    const int32_t *base = ctx->r_dirs.as<int32_t>();
+    const int32_t *rep = base + n_dir, *mate = base + 2 * n_dir, *n_eval = base + 3 * n_dir;
     const int n_tiles = (n_dir + sf::kTile - 1) / sf::kTile;
     const unsigned blocks = (unsigned)(n_roi * n_tiles);
     if (mode == 2) {
         sf_kernel<2>(n_freq)<<<blocks, sf::kTile, 0, s>>>((const float4 *)rel, offsets, quats, phase, dirs, n_dir,
-                                                          n_tiles, freqs, targets, nullptr, amp);
+                                                          rep, mate, n_eval, n_tiles, freqs, targets, nullptr, amp);
         AR_HIP(hipGetLastError());
         return AR_OK;
     }
     AR_TRY(ctx->r_partials.reserve(sizeof(float) * (size_t)n_roi * n_tiles * sf::kPartial));
     float *part = ctx->r_partials.as<float>();
     SfFn fn = mode == 1 ? sf_kernel<1>(n_freq) : sf_kernel<0>(n_freq);
-    fn<<<blocks, sf::kTile, 0, s>>>((const float4 *)rel, offsets, quats, phase, dirs, n_dir, n_tiles, freqs, targets,
-                                    part, nullptr);
+    fn<<<blocks, sf::kTile, 0, s>>>((const float4 *)rel, offsets, quats, phase, dirs, n_dir, rep, mate, n_eval,
+                                    n_tiles, freqs, targets, part, nullptr);
     AR_HIP(hipGetLastError());
     sf::k_sf_reduce<<<(unsigned)((n_roi + 255) / 256), 256, 0, s>>>(part, n_tiles, n_roi, quats, score,
                                                                     mode == 1 ? grad : nullptr);
@@ -458,9 +574,13 @@ ar_status ar_refine_orientations(ar_context *ctx, const float *rel, const int64_
     const unsigned nb = (unsigned)((n_roi + 255) / 256);
     ar::sf::k_copy4<<<(unsigned)((4 * n_roi + 255) / 256), 256, 0, s>>>(quats, trial, n_roi);
     AR_HIP(hipGetLastError());
+    {
+        const int32_t *a, *b, *c;
+        AR_TRY(ar::eval_list(ctx, directions, n_dir, &a, &b, &c, s));
+    }
     for (int it = 0; it <= steps; ++it) {
         AR_TRY(ar::sf_launch(ctx, 1, rel, offsets, n_roi, trial, phase, directions, n_dir, freqs, targets, n_freq, Jt,
-                             gt, nullptr, s));
+                             gt, nullptr, s, true));
         ar::sf::k_refine_update<<<nb, 256, 0, s>>>(st, trial, Jt, gt, n_roi, it == 0 ? 1 : 0, a0);
         AR_HIP(hipGetLastError());
     }
