@@ -44,6 +44,22 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def measured_traffic(profile: str, source: str):
+    """HBM bytes per launch from a committed rocprofv3 counter summary, or None
+    when the kernel source changed since the counters were taken."""
+    import hashlib
+    try:
+        text = open(os.path.join(ROOT, "profiles", profile)).read()
+        vals = dict(l.split(": ", 1) for l in text.splitlines() if ": " in l and l.split(": ", 1)[0] in
+                    ("traffic_bytes_per_launch", "source_sha256"))
+        sha = hashlib.sha256(open(os.path.join(ROOT, source), "rb").read()).hexdigest()
+        if vals.get("source_sha256") != sha:
+            return None
+        return float(vals["traffic_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -206,7 +222,8 @@ def main():
         "peak": PEAK_FP32_VECTOR / 1e12,
         "unit": "TFLOP/s",
         "frac": achieved_terms * flop_per_term / PEAK_FP32_VECTOR,
-        "traffic": None,
+        "traffic": measured_traffic("k_sf_adjoint_cfg2_hbm_counters.md", "paper_2009_00735_amd/csrc/refine.hip"),
+        "traffic_unit": "bytes per launch (FETCH_SIZE x2.0 + WRITE_SIZE x1.0, copy-probe scaled)",
         "terms_per_s": achieved_terms,
         "evaluated_directions": n_eval,
     }

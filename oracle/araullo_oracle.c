@@ -456,26 +456,6 @@ void orc_sf_grad_fd(const float *rel, int64_t n_w, const double *q, const float 
     }
 }
 
-/* Batched: per ROI (CSR of relative coordinates) score and FD gradient. */
-void orc_sf_batch(const float *rel, const int64_t *offsets, int64_t n_roi, const double *quats,
-                  const float *dirs, int32_t n_dir, const double *freqs /*[n_roi][n_freq]*/, int32_t n_freq,
-                  const double *targets /*[n_roi][n_freq][n_dir]*/, double h, double *score, double *grad,
-                  int32_t n_threads)
-{
-#ifdef _OPENMP
-    if (n_threads < 1) n_threads = 1;
-#pragma omp parallel for schedule(dynamic, 1) num_threads(n_threads)
-#endif
-    for (int64_t r = 0; r < n_roi; ++r) {
-        const float *x = rel + 3 * offsets[r];
-        int64_t n_w = offsets[r + 1] - offsets[r];
-        const double *f = freqs + (size_t)r * n_freq;
-        const double *T = targets + (size_t)r * n_freq * n_dir;
-        score[r] = orc_sf_score(x, n_w, quats + 4 * r, dirs, n_dir, f, n_freq, T);
-        if (grad) orc_sf_grad_fd(x, n_w, quats + 4 * r, dirs, n_dir, f, n_freq, T, h, grad + 4 * r);
-    }
-}
-
 /* Refinement trajectory (reading R11 plus the stated update rule, FP64 with
  * central-difference gradients): per iteration a trial q' = normalise(q -
  * a g/|g|) is accepted iff J(q') <= J(q) - 1e-4 a |g| (then a *= 1.5, the

@@ -68,8 +68,6 @@ def lib():
         L.orc_sf_score.argtypes = [F32P, c_i64, F64P, F32P, c_i32, F64P, c_i32, F64P]
         L.orc_sf_score.restype = c_f64
         L.orc_sf_grad_fd.argtypes = [F32P, c_i64, F64P, F32P, c_i32, F64P, c_i32, F64P, c_f64, F64P]
-        L.orc_sf_batch.argtypes = [F32P, I64P, c_i64, F64P, F32P, c_i32, F64P, c_i32, F64P, c_f64, F64P,
-                                   ctypes.c_void_p, c_i32]
         L.orc_sf_refine.argtypes = [F32P, c_i64, F64P, F32P, c_i32, F64P, c_i32, F64P, c_i32, c_f64, c_f64]
         L.orc_sf_refine.restype = c_f64
         _lib = L
@@ -243,22 +241,6 @@ def sf_grad_fd(rel, q, directions, freqs, target, h: float = 1e-6) -> np.ndarray
     g = np.zeros(4, np.float64)
     lib().orc_sf_grad_fd(rel, len(rel), _f64(q), d, len(d), f, len(f), _f64(target), h, g)
     return g
-
-
-def sf_batch(rel, offsets, quats, directions, freqs, targets, h: float = 1e-6, grad: bool = True,
-             threads: Optional[int] = None):
-    rel = _f32(rel).reshape(-1, 3)
-    off = np.ascontiguousarray(offsets, np.int64)
-    q = _f64(quats).reshape(-1, 4)
-    n = len(q)
-    d = _f32(directions)
-    f = _f64(freqs).reshape(n, -1)
-    T = _f64(targets).reshape(n, f.shape[1], len(d))
-    sc = np.zeros(n, np.float64)
-    g = np.zeros((n, 4), np.float64) if grad else None
-    lib().orc_sf_batch(rel, off, n, q, d, len(d), f, f.shape[1], T, h, sc,
-                       g.ctypes.data if grad else None, threads or default_threads())
-    return sc, g
 
 
 def sf_refine(rel, q, directions, freqs, target, steps: int = 50, a0: float = 0.01, h: float = 1e-6):

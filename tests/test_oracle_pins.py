@@ -263,6 +263,8 @@ def test_ssd_against_matmul_expansion(orc):
         assert np.allclose(sc[r], full[r, idx[r]], rtol=1e-12, atol=1e-10)
         assert np.all(np.diff(sc[r]) >= 0)
         assert set(idx[r]) == set(range(40))
+    pairs = orc.ssd_pairs(S, L, [0, 3, 4], [39, 0, 17])
+    assert np.allclose(pairs, [full[0, 39], full[3, 0], full[4, 17]], rtol=1e-12)
 
 
 def test_index_brute_force_small(orc):
@@ -445,3 +447,20 @@ def test_sf_minimum_at_true_orientation(orc):
     for ax in ([1, 0, 0], [0, 1, 1], [1, -2, 1]):
         qp = _qmul(qt, synth.quat_axis_angle(ax, 4.0))
         assert orc.sf_score(rel, qp, dirs, f, T) > j0
+
+
+def test_sf_refinement_trajectory_recovers_truth(orc):
+    """Noise-free crystal, start 3 degrees off: the FP64 backtracking descent
+    ends within 0.1 degree of the true orientation and lowers J."""
+    dirs = synth.icosphere(2)
+    f = np.array([4.2767, 4.9383, 6.9838, 8.1892])
+    ref = synth.lattice_in_ball("fcc", 0.405, np.array([1.0, 0, 0, 0]), np.zeros(3), np.zeros(3), 2.5)
+    rel0 = orc.roi_gather(ref.astype(np.float32), np.array([0.01, 0.02, -0.015], np.float32), 2.0)
+    T = orc.sf_amplitudes(rel0, np.array([1.0, 0, 0, 0]), dirs, f)
+    qt = synth.random_orientations(1, 4)[0]
+    p = synth.lattice_in_ball("fcc", 0.405, qt, np.zeros(3), np.zeros(3), 2.5)
+    rel = orc.roi_gather(p.astype(np.float32), np.zeros(3, np.float32), 2.0)
+    q0 = _qmul(qt, synth.quat_axis_angle([1, 2, -1], 3.0))
+    qr, J = orc.sf_refine(rel, q0, dirs, f, T, steps=40)
+    assert J < orc.sf_score(rel, q0, dirs, f, T)
+    assert orc.disorientation_cubic(qr, qt)[0] < 0.1
