@@ -163,6 +163,11 @@ ar_status ar_signature_plan_tune(ar_plan *plan, const float *rel, const int64_t 
 /* Chosen tile: directions per work item and atoms-per-lane register chunk. */
 ar_status ar_signature_plan_config(const ar_plan *plan, int32_t *dirs_per_item,
                                    int32_t *atoms_per_lane, int32_t *waves_per_group);
+/* Pin a tile configuration instead of tuning: directions per work item
+ * (1..n_dir), atoms per lane held in registers (8, 16, 24 or 32) and
+ * resident workgroups per compute unit (1..16). */
+ar_status ar_signature_plan_set_config(ar_plan *plan, int32_t dirs_per_item, int32_t atoms_per_lane,
+                                       int32_t blocks_per_cu);
 /* Run the batch. The host reads roi sizes once per new `offsets` pointer or
  * n_roi to order the queue (synchronises then); with use_graph != 0 the
  * launch sequence is captured once per argument set and replayed. */
@@ -211,6 +216,12 @@ ar_status index_orientations(ar_context *ctx, const float *images, int64_t n_roi
 ar_status index_orientations_ex(ar_context *ctx, const float *images, int64_t n_roi,
                                 const ar_library *lib, int32_t k, int32_t cand, int32_t *top_idx,
                                 float *top_score, int32_t *cand_idx, void *stream);
+
+/* Correlation tile of this context's index calls: each of the 4 wavefronts
+ * of a workgroup owns wtm x wtn MFMA tiles of 32x32 (workgroup tile
+ * 64 wtm x 64 wtn), K advances bk per step.  Supported: 2x2x64 (default),
+ * 2x4x32, 4x2x32, 4x4x32, 2x4x64.  Results do not depend on the tile. */
+ar_status ar_index_set_tile(ar_context *ctx, int32_t wtm, int32_t wtn, int32_t bk);
 
 /*
  * Disorientation angle in degrees under cubic symmetry (supplement,

@@ -33,8 +33,7 @@ namespace idx {
 typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
 typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16;
 
-constexpr int BM = 128, BN = 128, BK = 64;
-constexpr int LDA = BK + 8;              // padded LDS row (bf16): 144 bytes
+constexpr int kPadM = 256, kPadN = 256, kPadK = 64;   // multiples of every tile's BM, BN, BK
 constexpr int kThreads = 256;
 
 __device__ __forceinline__ uint16_t f32_to_bf16_rne(float x)
@@ -136,21 +135,41 @@ struct TopList {
 };
 
 // ------------------------------------------------------------ correlation
-// Workgroup: 4 waves as 2x2, each wave 64x64 = 2x2 MFMA 32x32 tiles.
-// grid.x = m_blocks * n_seg.  out_s/out_i: [M_pad][n_seg*2][CAND], the lists
-// of the two 64-column halves of every tile of the segment.
-// DBUF: A/B staged through two LDS buffers (one barrier per K step) when the
-// device allows 72 KiB of LDS per workgroup, else one buffer (two barriers).
-template <int CAND, bool DBUF>
+// Workgroup: 4 waves as 2x2; each wave owns WTM x WTN MFMA tiles of 32x32
+// (v_mfma_f32_32x32x16_bf16), so the workgroup tile is BM x BN =
+// (64 WTM) x (64 WTN).  K advances BK bf16 per step through LDS rows padded
+// by 16 bytes (conflict-free 16-byte fragment reads for 16 consecutive rows),
+// double-buffered (one barrier per step) when DBUF.
+// grid.x = m_blocks * n_seg.  out_s/out_i: [M_pad][n_seg * TPR][CAND] where
+// TPR = 256 / BM threads share a row in the epilogue.
+template <int WTM, int WTN, int BK> struct CorrShape {
+    static constexpr int BM = 64 * WTM, BN = 64 * WTN;
+    static constexpr int LD = BK + 8;                         // LDS row, bf16
+    static constexpr int TPR = kThreads / BM;                  // epilogue threads per row
+    static constexpr int CH_A = BM * BK / 8 / kThreads;        // 16-byte chunks per thread
+    static constexpr int CH_B = BN * BK / 8 / kThreads;
+    static constexpr int CPR = BK / 8;                         // chunks per row
+    static constexpr size_t lds(bool dbuf)
+    {
+        const size_t ab = (size_t)(dbuf ? 2 : 1) * (BM + BN) * LD * sizeof(uint16_t);
+        const size_t c = (size_t)BM * 65 * sizeof(float);
+        return ab > c ? ab : c;
+    }
+};
+
+template <int WTM, int WTN, int BK, int CAND, bool DBUF>
 __global__ __launch_bounds__(kThreads) void k_corr_topk(const uint16_t *__restrict__ A, const uint16_t *__restrict__ B,
                                                         const float *__restrict__ norm2, int64_t Kp, int m_blocks,
                                                         int n_tiles, int tiles_per_seg, int n_seg,
                                                         float *__restrict__ out_s, int32_t *__restrict__ out_i)
 {
+    using S = CorrShape<WTM, WTN, BK>;
+    constexpr int BM = S::BM, BN = S::BN, LD = S::LD, TPR = S::TPR;
     constexpr int NBUF = DBUF ? 2 : 1;
+    static_assert(TPR >= 1 && S::CH_A >= 1 && S::CH_B >= 1, "tile too small for 256 threads");
     extern __shared__ __align__(16) unsigned char smem[];
-    uint16_t *As = reinterpret_cast<uint16_t *>(smem);                 // [NBUF][BM][LDA]
-    uint16_t *Bs = As + NBUF * BM * LDA;                               // [NBUF][BN][LDA]
+    uint16_t *As = reinterpret_cast<uint16_t *>(smem);                 // [NBUF][BM][LD]
+    uint16_t *Bs = As + NBUF * BM * LD;                                // [NBUF][BN][LD]
     float *Cs = reinterpret_cast<float *>(smem);                       // [BM][65], aliases As/Bs
 
     const int tid = threadIdx.x;
@@ -173,52 +192,64 @@ __global__ __launch_bounds__(kThreads) void k_corr_topk(const uint16_t *__restri
     const int t0 = seg * tiles_per_seg;
     const int t1 = min(t0 + tiles_per_seg, n_tiles);
 
-    // epilogue ownership: thread -> (row, half)
-    const int e_row = tid & (BM - 1);
-    const int e_half = tid >> 7;
+    // epilogue ownership: thread -> (row, part of each 64-column pass)
+    const int e_row = tid % BM;
+    const int e_part = tid / BM;
     TopList<CAND> top;
     top.init();
 
     const int KT = (int)(Kp / BK);
     for (int nt = t0; nt < t1; ++nt) {
         const int64_t n0 = (int64_t)nt * BN;
-        f32x16 acc[2][2];
+        f32x16 acc[WTM][WTN];
 #pragma unroll
-        for (int a = 0; a < 2; ++a)
+        for (int a = 0; a < WTM; ++a)
 #pragma unroll
-            for (int c = 0; c < 2; ++c)
+            for (int c = 0; c < WTN; ++c)
 #pragma unroll
                 for (int r = 0; r < 16; ++r) acc[a][c][r] = 0.0f;
 
-        // global -> register staging: 4 chunks of 16 B for A and for B
-        uint4 ra0, ra1, ra2, ra3, rb0, rb1, rb2, rb3;
+        // global -> register staging in named registers (no private arrays)
+        uint4 ra0, ra1, ra2, ra3, ra4, ra5, ra6, ra7, rb0, rb1, rb2, rb3, rb4, rb5, rb6, rb7;
+        static_assert(S::CH_A <= 8 && S::CH_B <= 8, "staging holds at most 8 chunks per operand");
 #define AR_GLOAD(kt_)                                                                               \
     do {                                                                                            \
         const int64_t k0_ = (int64_t)(kt_) * BK;                                                    \
-        const uint16_t *pa_ = A + (size_t)(m0 + (tid >> 3)) * Kp + k0_ + (tid & 7) * 8;              \
-        const uint16_t *pb_ = B + (size_t)(n0 + (tid >> 3)) * Kp + k0_ + (tid & 7) * 8;              \
-        const size_t step_ = (size_t)32 * Kp; /* 256 threads cover 32 rows */                        \
-        ra0 = *reinterpret_cast<const uint4 *>(pa_);                                                \
-        ra1 = *reinterpret_cast<const uint4 *>(pa_ + step_);                                        \
-        ra2 = *reinterpret_cast<const uint4 *>(pa_ + 2 * step_);                                    \
-        ra3 = *reinterpret_cast<const uint4 *>(pa_ + 3 * step_);                                    \
-        rb0 = *reinterpret_cast<const uint4 *>(pb_);                                                \
-        rb1 = *reinterpret_cast<const uint4 *>(pb_ + step_);                                        \
-        rb2 = *reinterpret_cast<const uint4 *>(pb_ + 2 * step_);                                    \
-        rb3 = *reinterpret_cast<const uint4 *>(pb_ + 3 * step_);                                    \
+        if constexpr (0 < S::CH_A) ra0 = *reinterpret_cast<const uint4 *>(A + (size_t)(m0 + (tid + 0 * kThreads) / S::CPR) * Kp + k0_ + ((tid + 0 * kThreads) % S::CPR) * 8); \
+        if constexpr (1 < S::CH_A) ra1 = *reinterpret_cast<const uint4 *>(A + (size_t)(m0 + (tid + 1 * kThreads) / S::CPR) * Kp + k0_ + ((tid + 1 * kThreads) % S::CPR) * 8); \
+        if constexpr (2 < S::CH_A) ra2 = *reinterpret_cast<const uint4 *>(A + (size_t)(m0 + (tid + 2 * kThreads) / S::CPR) * Kp + k0_ + ((tid + 2 * kThreads) % S::CPR) * 8); \
+        if constexpr (3 < S::CH_A) ra3 = *reinterpret_cast<const uint4 *>(A + (size_t)(m0 + (tid + 3 * kThreads) / S::CPR) * Kp + k0_ + ((tid + 3 * kThreads) % S::CPR) * 8); \
+        if constexpr (4 < S::CH_A) ra4 = *reinterpret_cast<const uint4 *>(A + (size_t)(m0 + (tid + 4 * kThreads) / S::CPR) * Kp + k0_ + ((tid + 4 * kThreads) % S::CPR) * 8); \
+        if constexpr (5 < S::CH_A) ra5 = *reinterpret_cast<const uint4 *>(A + (size_t)(m0 + (tid + 5 * kThreads) / S::CPR) * Kp + k0_ + ((tid + 5 * kThreads) % S::CPR) * 8); \
+        if constexpr (6 < S::CH_A) ra6 = *reinterpret_cast<const uint4 *>(A + (size_t)(m0 + (tid + 6 * kThreads) / S::CPR) * Kp + k0_ + ((tid + 6 * kThreads) % S::CPR) * 8); \
+        if constexpr (7 < S::CH_A) ra7 = *reinterpret_cast<const uint4 *>(A + (size_t)(m0 + (tid + 7 * kThreads) / S::CPR) * Kp + k0_ + ((tid + 7 * kThreads) % S::CPR) * 8); \
+        if constexpr (0 < S::CH_B) rb0 = *reinterpret_cast<const uint4 *>(B + (size_t)(n0 + (tid + 0 * kThreads) / S::CPR) * Kp + k0_ + ((tid + 0 * kThreads) % S::CPR) * 8); \
+        if constexpr (1 < S::CH_B) rb1 = *reinterpret_cast<const uint4 *>(B + (size_t)(n0 + (tid + 1 * kThreads) / S::CPR) * Kp + k0_ + ((tid + 1 * kThreads) % S::CPR) * 8); \
+        if constexpr (2 < S::CH_B) rb2 = *reinterpret_cast<const uint4 *>(B + (size_t)(n0 + (tid + 2 * kThreads) / S::CPR) * Kp + k0_ + ((tid + 2 * kThreads) % S::CPR) * 8); \
+        if constexpr (3 < S::CH_B) rb3 = *reinterpret_cast<const uint4 *>(B + (size_t)(n0 + (tid + 3 * kThreads) / S::CPR) * Kp + k0_ + ((tid + 3 * kThreads) % S::CPR) * 8); \
+        if constexpr (4 < S::CH_B) rb4 = *reinterpret_cast<const uint4 *>(B + (size_t)(n0 + (tid + 4 * kThreads) / S::CPR) * Kp + k0_ + ((tid + 4 * kThreads) % S::CPR) * 8); \
+        if constexpr (5 < S::CH_B) rb5 = *reinterpret_cast<const uint4 *>(B + (size_t)(n0 + (tid + 5 * kThreads) / S::CPR) * Kp + k0_ + ((tid + 5 * kThreads) % S::CPR) * 8); \
+        if constexpr (6 < S::CH_B) rb6 = *reinterpret_cast<const uint4 *>(B + (size_t)(n0 + (tid + 6 * kThreads) / S::CPR) * Kp + k0_ + ((tid + 6 * kThreads) % S::CPR) * 8); \
+        if constexpr (7 < S::CH_B) rb7 = *reinterpret_cast<const uint4 *>(B + (size_t)(n0 + (tid + 7 * kThreads) / S::CPR) * Kp + k0_ + ((tid + 7 * kThreads) % S::CPR) * 8); \
     } while (0)
 #define AR_SSTORE(buf_)                                                                             \
     do {                                                                                            \
-        uint16_t *sa_ = As + (size_t)(buf_) * BM * LDA + (tid >> 3) * LDA + (tid & 7) * 8;          \
-        uint16_t *sb_ = Bs + (size_t)(buf_) * BN * LDA + (tid >> 3) * LDA + (tid & 7) * 8;          \
-        *reinterpret_cast<uint4 *>(sa_) = ra0;                                                      \
-        *reinterpret_cast<uint4 *>(sa_ + 32 * LDA) = ra1;                                           \
-        *reinterpret_cast<uint4 *>(sa_ + 64 * LDA) = ra2;                                           \
-        *reinterpret_cast<uint4 *>(sa_ + 96 * LDA) = ra3;                                           \
-        *reinterpret_cast<uint4 *>(sb_) = rb0;                                                      \
-        *reinterpret_cast<uint4 *>(sb_ + 32 * LDA) = rb1;                                           \
-        *reinterpret_cast<uint4 *>(sb_ + 64 * LDA) = rb2;                                           \
-        *reinterpret_cast<uint4 *>(sb_ + 96 * LDA) = rb3;                                           \
+        if constexpr (0 < S::CH_A) *reinterpret_cast<uint4 *>(As + (size_t)(buf_) * BM * LD + ((tid + 0 * kThreads) / S::CPR) * LD + ((tid + 0 * kThreads) % S::CPR) * 8) = ra0; \
+        if constexpr (1 < S::CH_A) *reinterpret_cast<uint4 *>(As + (size_t)(buf_) * BM * LD + ((tid + 1 * kThreads) / S::CPR) * LD + ((tid + 1 * kThreads) % S::CPR) * 8) = ra1; \
+        if constexpr (2 < S::CH_A) *reinterpret_cast<uint4 *>(As + (size_t)(buf_) * BM * LD + ((tid + 2 * kThreads) / S::CPR) * LD + ((tid + 2 * kThreads) % S::CPR) * 8) = ra2; \
+        if constexpr (3 < S::CH_A) *reinterpret_cast<uint4 *>(As + (size_t)(buf_) * BM * LD + ((tid + 3 * kThreads) / S::CPR) * LD + ((tid + 3 * kThreads) % S::CPR) * 8) = ra3; \
+        if constexpr (4 < S::CH_A) *reinterpret_cast<uint4 *>(As + (size_t)(buf_) * BM * LD + ((tid + 4 * kThreads) / S::CPR) * LD + ((tid + 4 * kThreads) % S::CPR) * 8) = ra4; \
+        if constexpr (5 < S::CH_A) *reinterpret_cast<uint4 *>(As + (size_t)(buf_) * BM * LD + ((tid + 5 * kThreads) / S::CPR) * LD + ((tid + 5 * kThreads) % S::CPR) * 8) = ra5; \
+        if constexpr (6 < S::CH_A) *reinterpret_cast<uint4 *>(As + (size_t)(buf_) * BM * LD + ((tid + 6 * kThreads) / S::CPR) * LD + ((tid + 6 * kThreads) % S::CPR) * 8) = ra6; \
+        if constexpr (7 < S::CH_A) *reinterpret_cast<uint4 *>(As + (size_t)(buf_) * BM * LD + ((tid + 7 * kThreads) / S::CPR) * LD + ((tid + 7 * kThreads) % S::CPR) * 8) = ra7; \
+        if constexpr (0 < S::CH_B) *reinterpret_cast<uint4 *>(Bs + (size_t)(buf_) * BN * LD + ((tid + 0 * kThreads) / S::CPR) * LD + ((tid + 0 * kThreads) % S::CPR) * 8) = rb0; \
+        if constexpr (1 < S::CH_B) *reinterpret_cast<uint4 *>(Bs + (size_t)(buf_) * BN * LD + ((tid + 1 * kThreads) / S::CPR) * LD + ((tid + 1 * kThreads) % S::CPR) * 8) = rb1; \
+        if constexpr (2 < S::CH_B) *reinterpret_cast<uint4 *>(Bs + (size_t)(buf_) * BN * LD + ((tid + 2 * kThreads) / S::CPR) * LD + ((tid + 2 * kThreads) % S::CPR) * 8) = rb2; \
+        if constexpr (3 < S::CH_B) *reinterpret_cast<uint4 *>(Bs + (size_t)(buf_) * BN * LD + ((tid + 3 * kThreads) / S::CPR) * LD + ((tid + 3 * kThreads) % S::CPR) * 8) = rb3; \
+        if constexpr (4 < S::CH_B) *reinterpret_cast<uint4 *>(Bs + (size_t)(buf_) * BN * LD + ((tid + 4 * kThreads) / S::CPR) * LD + ((tid + 4 * kThreads) % S::CPR) * 8) = rb4; \
+        if constexpr (5 < S::CH_B) *reinterpret_cast<uint4 *>(Bs + (size_t)(buf_) * BN * LD + ((tid + 5 * kThreads) / S::CPR) * LD + ((tid + 5 * kThreads) % S::CPR) * 8) = rb5; \
+        if constexpr (6 < S::CH_B) *reinterpret_cast<uint4 *>(Bs + (size_t)(buf_) * BN * LD + ((tid + 6 * kThreads) / S::CPR) * LD + ((tid + 6 * kThreads) % S::CPR) * 8) = rb6; \
+        if constexpr (7 < S::CH_B) *reinterpret_cast<uint4 *>(Bs + (size_t)(buf_) * BN * LD + ((tid + 7 * kThreads) / S::CPR) * LD + ((tid + 7 * kThreads) % S::CPR) * 8) = rb7; \
     } while (0)
         AR_GLOAD(0);
         __syncthreads();   // the previous tile's epilogue read Cs, which aliases As/Bs
@@ -227,25 +258,25 @@ __global__ __launch_bounds__(kThreads) void k_corr_topk(const uint16_t *__restri
         for (int kt = 0; kt < KT; ++kt) {
             const int cur = DBUF ? (kt & 1) : 0;
             if (kt + 1 < KT) AR_GLOAD(kt + 1);
-            const uint16_t *a_s = As + (size_t)cur * BM * LDA;
-            const uint16_t *b_s = Bs + (size_t)cur * BN * LDA;
+            const uint16_t *a_s = As + (size_t)cur * BM * LD;
+            const uint16_t *b_s = Bs + (size_t)cur * BN * LD;
 #pragma unroll
             for (int kk = 0; kk < BK; kk += 16) {
-                bf16x8 fa[2], fb[2];
+                bf16x8 fa[WTM], fb[WTN];
 #pragma unroll
-                for (int a = 0; a < 2; ++a) {
-                    const int row = wm * 64 + a * 32 + (lane & 31);
-                    fa[a] = *reinterpret_cast<const bf16x8 *>(a_s + row * LDA + kk + (lane >> 5) * 8);
+                for (int a = 0; a < WTM; ++a) {
+                    const int row = wm * (BM / 2) + a * 32 + (lane & 31);
+                    fa[a] = *reinterpret_cast<const bf16x8 *>(a_s + row * LD + kk + (lane >> 5) * 8);
                 }
 #pragma unroll
-                for (int c = 0; c < 2; ++c) {
-                    const int col = wn * 64 + c * 32 + (lane & 31);
-                    fb[c] = *reinterpret_cast<const bf16x8 *>(b_s + col * LDA + kk + (lane >> 5) * 8);
+                for (int c = 0; c < WTN; ++c) {
+                    const int col = wn * (BN / 2) + c * 32 + (lane & 31);
+                    fb[c] = *reinterpret_cast<const bf16x8 *>(b_s + col * LD + kk + (lane >> 5) * 8);
                 }
 #pragma unroll
-                for (int a = 0; a < 2; ++a)
+                for (int a = 0; a < WTM; ++a)
 #pragma unroll
-                    for (int c = 0; c < 2; ++c)
+                    for (int c = 0; c < WTN; ++c)
                         acc[a][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[a], fb[c], acc[a][c], 0, 0, 0);
             }
             if (DBUF) {
@@ -260,35 +291,41 @@ __global__ __launch_bounds__(kThreads) void k_corr_topk(const uint16_t *__restri
 #undef AR_GLOAD
 #undef AR_SSTORE
         __syncthreads();
-        // epilogue in two 64-column passes: the waves of column half h write
-        // their scores |L|^2 - 2<S,L> to LDS, the threads of half h scan rows
+        // epilogue in 64-column passes: the waves owning the columns write their
+        // scores |L|^2 - 2<S,L> to LDS, then every thread scans its share of a row
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            if (wn == h) {
+        for (int h = 0; h < BN / 64; ++h) {
+            constexpr int WCOLS = BN / 2;                 // columns per wave
+            const int wave_of_pass = (h * 64) / WCOLS;    // compile-time after unrolling
+            if (wn == wave_of_pass) {
+                const int c0 = (h * 64 - wave_of_pass * WCOLS) / 32;   // first 32-wide tile of the pass
 #pragma unroll
-                for (int a = 0; a < 2; ++a)
+                for (int a = 0; a < WTM; ++a)
 #pragma unroll
-                    for (int c = 0; c < 2; ++c) {
-                        const int col = c * 32 + (lane & 31);
-                        const float nrm = norm2[n0 + h * 64 + col];
+                    for (int c = 0; c < WTN; ++c) {
+                        if (c == c0 || c == c0 + 1) {
+                            const int col = (c - c0) * 32 + (lane & 31);
+                            const float nrm = norm2[n0 + h * 64 + col];
 #pragma unroll
-                        for (int r = 0; r < 16; ++r) {
-                            const int row = wm * 64 + a * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-                            Cs[row * 65 + col] = fmaf(-2.0f, acc[a][c][r], nrm);
+                            for (int r = 0; r < 16; ++r) {
+                                const int row = wm * (BM / 2) + a * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+                                Cs[row * 65 + col] = fmaf(-2.0f, acc[a][c][r], nrm);
+                            }
                         }
                     }
             }
             __syncthreads();
-            if (e_half == h) {
-                const float *crow = Cs + e_row * 65;
-                const int base = (int)(n0 + h * 64);
-#pragma unroll 8
-                for (int j = 0; j < 64; ++j) top.insert(crow[j], base + j);
+            {
+                constexpr int W = 64 / TPR;
+                const float *crow = Cs + e_row * 65 + e_part * W;
+                const int base = (int)(n0 + h * 64 + e_part * W);
+#pragma unroll 1
+                for (int j = 0; j < W; ++j) top.insert(crow[j], base + j);
             }
             __syncthreads();
         }
     }
-    const size_t o = (((size_t)(m0 + e_row)) * (n_seg * 2) + seg * 2 + e_half) * CAND;
+    const size_t o = (((size_t)(m0 + e_row)) * (n_seg * TPR) + seg * TPR + e_part) * CAND;
 #pragma unroll
     for (int j = 0; j < CAND; ++j) {
         out_s[o + j] = top.s[j];
@@ -412,41 +449,61 @@ __global__ void k_copy_cand(const int32_t *__restrict__ cand, int64_t n_rows, in
     if (i < n_rows * CAND) out[i] = cand[i];
 }
 
-size_t corr_lds_bytes(bool dbuf)
-{
-    const size_t ab = (size_t)(dbuf ? 2 : 1) * (BM + BN) * LDA * sizeof(uint16_t);
-    const size_t c = (size_t)BM * 65 * sizeof(float);
-    return ab > c ? ab : c;
-}
+// Correlation tile configurations (per-wave 32x32 tiles WTM x WTN, K step).
+struct CorrCfg {
+    int wtm, wtn, bk;
+    int bm() const { return 64 * wtm; }
+    int bn() const { return 64 * wtn; }
+};
 
-template <int CAND>
-ar_status launch_corr(ar_context *ctx, const uint16_t *A, const ar_library *lib, int m_blocks, int n_tiles,
-                      int tiles_per_seg, int n_seg, float *out_s, int32_t *out_i, hipStream_t s)
+template <int WTM, int WTN, int BK, int CAND>
+ar_status launch_corr_t(ar_context *ctx, const uint16_t *A, const ar_library *lib, int m_blocks, int n_tiles,
+                        int tiles_per_seg, int n_seg, float *out_s, int32_t *out_i, hipStream_t s)
 {
+    using S = CorrShape<WTM, WTN, BK>;
     const unsigned blocks = (unsigned)(m_blocks * n_seg);
-    const size_t big = corr_lds_bytes(true);
-    static int dbuf_ok = -1;   // per process: can a workgroup get `big` bytes of LDS?
+    const size_t big = S::lds(true);
+    static int dbuf_ok = -1;   // per instantiation: can a workgroup get `big` bytes of LDS?
     if (dbuf_ok < 0) {
         dbuf_ok = 0;
         if ((size_t)ctx->lds_per_block >= big &&
-            hipFuncSetAttribute((const void *)k_corr_topk<CAND, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                (int)big) == hipSuccess)
+            hipFuncSetAttribute((const void *)k_corr_topk<WTM, WTN, BK, CAND, true>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)big) == hipSuccess)
             dbuf_ok = 1;
         (void)hipGetLastError();
     }
     if (dbuf_ok == 1) {
-        (void)hipFuncSetAttribute((const void *)k_corr_topk<CAND, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  (int)big);
-        k_corr_topk<CAND, true><<<blocks, kThreads, big, s>>>(A, lib->bf16.as<uint16_t>(), lib->norm2.as<float>(),
-                                                              lib->Kp, m_blocks, n_tiles, tiles_per_seg, n_seg, out_s,
-                                                              out_i);
+        k_corr_topk<WTM, WTN, BK, CAND, true><<<blocks, kThreads, big, s>>>(
+            A, lib->bf16.as<uint16_t>(), lib->norm2.as<float>(), lib->Kp, m_blocks, n_tiles, tiles_per_seg, n_seg,
+            out_s, out_i);
     } else {
-        k_corr_topk<CAND, false><<<blocks, kThreads, corr_lds_bytes(false), s>>>(
+        const size_t small = S::lds(false);
+        if (small > 65536)
+            (void)hipFuncSetAttribute((const void *)k_corr_topk<WTM, WTN, BK, CAND, false>,
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)small);
+        k_corr_topk<WTM, WTN, BK, CAND, false><<<blocks, kThreads, small, s>>>(
             A, lib->bf16.as<uint16_t>(), lib->norm2.as<float>(), lib->Kp, m_blocks, n_tiles, tiles_per_seg, n_seg,
             out_s, out_i);
     }
     AR_HIP(hipGetLastError());
     return AR_OK;
+}
+
+template <int CAND>
+ar_status launch_corr(ar_context *ctx, const CorrCfg &c, const uint16_t *A, const ar_library *lib, int m_blocks,
+                      int n_tiles, int tiles_per_seg, int n_seg, float *out_s, int32_t *out_i, hipStream_t s)
+{
+#define AR_CORR_CASE(wm_, wn_, bk_)                                                                   \
+    if (c.wtm == wm_ && c.wtn == wn_ && c.bk == bk_)                                                 \
+        return launch_corr_t<wm_, wn_, bk_, CAND>(ctx, A, lib, m_blocks, n_tiles, tiles_per_seg, n_seg, out_s, \
+                                                  out_i, s);
+    AR_CORR_CASE(2, 2, 64)
+    AR_CORR_CASE(2, 4, 32)
+    AR_CORR_CASE(4, 2, 32)
+    AR_CORR_CASE(4, 4, 32)
+    AR_CORR_CASE(2, 4, 64)
+#undef AR_CORR_CASE
+    return fail(AR_EINVAL, "unsupported correlation tile %dx%dx%d", c.wtm, c.wtn, c.bk);
 }
 
 int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
@@ -480,7 +537,7 @@ ar_status ar_library_create(ar_context *ctx, const float *ref_images, int64_t n_
     *out = nullptr;
     AR_CHECK(ctx != nullptr, "context is NULL");
     AR_CHECK(ref_images != nullptr, "ref_images is NULL");
-    AR_CHECK(n_lib >= 1 && n_lib < (int64_t)INT32_MAX - idx::BN, "n_lib out of range");
+    AR_CHECK(n_lib >= 1 && n_lib < (int64_t)INT32_MAX - idx::kPadN, "n_lib out of range");
     AR_CHECK(n_win >= 1 && n_dir >= 1, "n_win and n_dir must be >= 1");
     AR_HIP(hipSetDevice(ctx->device));
     hipStream_t s = (hipStream_t)stream;
@@ -492,8 +549,8 @@ ar_status ar_library_create(ar_context *ctx, const float *ref_images, int64_t n_
     lib->n_win = n_win;
     lib->n_dir = n_dir;
     lib->K = (int64_t)n_win * n_dir;
-    lib->Kp = idx::round_up(lib->K, idx::BK);
-    lib->n_pad = idx::round_up(n_lib, idx::BN);
+    lib->Kp = idx::round_up(lib->K, idx::kPadK);
+    lib->n_pad = idx::round_up(n_lib, idx::kPadN);
     ar_status st = lib->bf16.reserve(sizeof(uint16_t) * (size_t)lib->n_pad * lib->Kp);
     if (st == AR_OK) st = lib->norm2.reserve(sizeof(float) * lib->n_pad);
     if (st == AR_OK) st = lib->inv_max.reserve(sizeof(float) * n_lib * n_win);
@@ -528,21 +585,22 @@ ar_status index_orientations_ex(ar_context *ctx, const float *images, int64_t n_
 {
     AR_CHECK(ctx && lib, "ctx/library is NULL");
     AR_CHECK(images && top_idx && top_score, "images/top_idx/top_score must not be NULL");
-    AR_CHECK(n_roi >= 1 && n_roi < (int64_t)INT32_MAX - idx::BM, "n_roi out of range");
+    AR_CHECK(n_roi >= 1 && n_roi < (int64_t)INT32_MAX - idx::kPadM, "n_roi out of range");
     AR_CHECK(cand == 16 || cand == 32, "cand must be 16 or 32, got %d", cand);
     AR_CHECK(k >= 1 && k <= cand, "k must be in [1, cand = %d], got %d", cand, k);
     AR_CHECK(lib->ctx == ctx, "library belongs to another context");
     AR_HIP(hipSetDevice(ctx->device));
     hipStream_t s = (hipStream_t)stream;
-    const int64_t m_pad = idx::round_up(n_roi, idx::BM);
-    const int m_blocks = (int)(m_pad / idx::BM);
-    const int n_tiles = (int)(lib->n_pad / idx::BN);
+    const idx::CorrCfg cfg{ctx->corr_wtm, ctx->corr_wtn, ctx->corr_bk};
+    const int64_t m_pad = idx::round_up(n_roi, idx::kPadM);
+    const int m_blocks = (int)(m_pad / cfg.bm());
+    const int n_tiles = (int)(lib->n_pad / cfg.bn());
     // segments: enough workgroups to fill the chip several times over
     const int target = 8 * ctx->cu_count;
     int n_seg = std::max(1, std::min(n_tiles, (target + m_blocks - 1) / m_blocks));
     const int tiles_per_seg = (n_tiles + n_seg - 1) / n_seg;
     n_seg = (n_tiles + tiles_per_seg - 1) / tiles_per_seg;
-    const int n_lists = 2 * n_seg;
+    const int n_lists = n_seg * (idx::kThreads / cfg.bm());
 
     AR_TRY(ctx->i_bf16.reserve(sizeof(uint16_t) * (size_t)m_pad * lib->Kp));
     AR_TRY(ctx->i_inv.reserve(sizeof(float) * (size_t)n_roi * lib->n_win));
@@ -553,8 +611,8 @@ ar_status index_orientations_ex(ar_context *ctx, const float *images, int64_t n_
     AR_TRY(idx::normalise_cast(images, n_roi, m_pad, lib->n_win, lib->n_dir, lib->Kp, ctx->i_inv.as<float>(),
                                ctx->i_bf16.as<uint16_t>(), s));
     if (cand == 16) {
-        AR_TRY(idx::launch_corr<16>(ctx, ctx->i_bf16.as<uint16_t>(), lib, m_blocks, n_tiles, tiles_per_seg, n_seg,
-                                    ctx->i_cand_score.as<float>(), ctx->i_cand_idx.as<int32_t>(), s));
+        AR_TRY(idx::launch_corr<16>(ctx, cfg, ctx->i_bf16.as<uint16_t>(), lib, m_blocks, n_tiles, tiles_per_seg,
+                                    n_seg, ctx->i_cand_score.as<float>(), ctx->i_cand_idx.as<int32_t>(), s));
         idx::k_merge<16><<<(unsigned)((n_roi + 3) / 4), 256, 0, s>>>(
             ctx->i_cand_score.as<float>(), ctx->i_cand_idx.as<int32_t>(), n_lists, n_roi, ctx->i_merge_idx.as<int32_t>());
         AR_HIP(hipGetLastError());
@@ -563,8 +621,8 @@ ar_status index_orientations_ex(ar_context *ctx, const float *images, int64_t n_
                                                           lib->n_win, lib->n_dir, lib->n_lib, k, top_idx, top_score);
         AR_HIP(hipGetLastError());
     } else {
-        AR_TRY(idx::launch_corr<32>(ctx, ctx->i_bf16.as<uint16_t>(), lib, m_blocks, n_tiles, tiles_per_seg, n_seg,
-                                    ctx->i_cand_score.as<float>(), ctx->i_cand_idx.as<int32_t>(), s));
+        AR_TRY(idx::launch_corr<32>(ctx, cfg, ctx->i_bf16.as<uint16_t>(), lib, m_blocks, n_tiles, tiles_per_seg,
+                                    n_seg, ctx->i_cand_score.as<float>(), ctx->i_cand_idx.as<int32_t>(), s));
         idx::k_merge<32><<<(unsigned)((n_roi + 3) / 4), 256, 0, s>>>(
             ctx->i_cand_score.as<float>(), ctx->i_cand_idx.as<int32_t>(), n_lists, n_roi, ctx->i_merge_idx.as<int32_t>());
         AR_HIP(hipGetLastError());
@@ -583,6 +641,19 @@ ar_status index_orientations_ex(ar_context *ctx, const float *images, int64_t n_
                                                                              cand_idx);
         AR_HIP(hipGetLastError());
     }
+    return AR_OK;
+}
+
+ar_status ar_index_set_tile(ar_context *ctx, int32_t wtm, int32_t wtn, int32_t bk)
+{
+    AR_CHECK(ctx != nullptr, "context is NULL");
+    const bool ok = (wtm == 2 && wtn == 2 && bk == 64) || (wtm == 2 && wtn == 4 && bk == 32) ||
+                    (wtm == 4 && wtn == 2 && bk == 32) || (wtm == 4 && wtn == 4 && bk == 32) ||
+                    (wtm == 2 && wtn == 4 && bk == 64);
+    AR_CHECK(ok, "unsupported correlation tile %dx%dx%d", wtm, wtn, bk);
+    ctx->corr_wtm = wtm;
+    ctx->corr_wtn = wtn;
+    ctx->corr_bk = bk;
     return AR_OK;
 }
 

@@ -77,82 +77,107 @@ template <int R> __device__ __forceinline__ void dftR(float2 *v)
     else dft2(v);
 }
 
-// One Stockham autosort pass of radix R on NC complex points held in LDS
-// (`in` -> `out`), sub-transform length NS before the pass.  Butterfly j
-// reads in[j + t NC/R], applies twiddles exp(-2 pi i t (j mod NS)/(NS R)) and
-// writes out[(j - j mod NS) R + j mod NS + t NS].  The twiddle table W holds
-// exp(-2 pi i m / NB), m < NB, NB = 2 NC.  When FROM_INT, `in` is the integer
-// histogram read as pairs (h_2n, h_2n+1) = z_n.
+// Swizzled float2 layout of the FFT buffer: element i lives at
+// i ^ h(i >> 5), h(x) = (x & 7) | (((x >> 1) & 3) << 3).  Within each aligned
+// block of 32 elements this is a bijection.  Reads of a pass touch 32
+// consecutive elements per half-wavefront (XOR by a constant: still one
+// element per bank pair); the strided writes of the first two passes land on
+// 32 distinct bank pairs (low bits taken by the stride XORed with the block
+// index), so no pass has LDS bank conflicts.
+__device__ __forceinline__ int swz(int i)
+{
+    const int x = i >> 5;
+    return i ^ ((x & 7) | (((x >> 1) & 3) << 3));
+}
+
+// One in-place Stockham autosort pass of radix R on NC complex points in
+// LDS, sub-transform length NS before the pass.  Butterfly j reads
+// element j + t NC/R, applies twiddles exp(-2 pi i t (j mod NS)/(NS R)) and
+// writes element (j - j mod NS) R + j mod NS + t NS.  Every lane loads the
+// inputs of all its butterflies before any write; LDS operations of a
+// wavefront execute in order, so the pass can overwrite its own input.  The
+// twiddle table W holds exp(-2 pi i m / NB), m < NB, NB = 2 NC.  FROM_INT:
+// the input is the integer histogram, read unswizzled as pairs
+// (h_2n, h_2n+1) = z_n.
 template <int NC, int R, int NS, bool FROM_INT>
-__device__ __forceinline__ void stockham_pass(const void *in, float2 *__restrict__ out, const float2 *__restrict__ W,
-                                              int lane)
+__device__ __forceinline__ void stockham_pass(float2 *buf, const float2 *__restrict__ W, int lane)
 {
     constexpr int NB = 2 * NC;
     constexpr int NBF = NC / R;
+    constexpr int PER = (NBF + kWave - 1) / kWave;   // butterflies per lane
+    float2 v[PER][R];
 #pragma unroll
-    for (int j0 = 0; j0 < NBF; j0 += kWave) {
-        const int j = j0 + lane;
-        if (NBF % kWave != 0 && j >= NBF) break;
-        float2 v[R];
+    for (int p = 0; p < PER; ++p) {
+        const int j = p * kWave + lane;
+        if (NBF % kWave == 0 || j < NBF) {
 #pragma unroll
-        for (int t = 0; t < R; ++t) {
-            if constexpr (FROM_INT) {
-                const int2 p = static_cast<const int2 *>(in)[j + t * NBF];
-                v[t] = make_float2((float)p.x, (float)p.y);
-            } else {
-                v[t] = static_cast<const float2 *>(in)[j + t * NBF];
+            for (int t = 0; t < R; ++t) {
+                if constexpr (FROM_INT) {
+                    const int2 q = reinterpret_cast<const int2 *>(buf)[j + t * NBF];
+                    v[p][t] = make_float2((float)q.x, (float)q.y);
+                } else {
+                    v[p][t] = buf[swz(j + t * NBF)];
+                }
             }
         }
-        const int k = j & (NS - 1);
-        if constexpr (NS > 1) {
-            constexpr int STRIDE = NB / (NS * R);
+    }
 #pragma unroll
-            for (int t = 1; t < R; ++t) v[t] = cmul(v[t], W[(t * k * STRIDE) & (NB - 1)]);
+    for (int p = 0; p < PER; ++p) {
+        const int j = p * kWave + lane;
+        if (NBF % kWave == 0 || j < NBF) {
+            const int k = j & (NS - 1);
+            if constexpr (NS > 1) {
+                constexpr int STRIDE = NB / (NS * R);
+#pragma unroll
+                for (int t = 1; t < R; ++t) v[p][t] = cmul(v[p][t], W[(t * k * STRIDE) & (NB - 1)]);
+            }
+            dftR<R>(v[p]);
+            const int base = (j - k) * R + k;
+#pragma unroll
+            for (int t = 0; t < R; ++t) buf[swz(base + t * NS)] = v[p][t];
         }
-        dftR<R>(v);
-        const int base = (j - k) * R + k;
-#pragma unroll
-        for (int t = 0; t < R; ++t) out[base + t * NS] = v[t];
     }
 }
 
-// Complex FFT of the NC = NB/2 packed points z_n = h_2n + i h_2n+1 (radix 8
-// while possible, then 4 or 2).  Returns the buffer holding Z in natural order.
+// In-place complex FFT of the NC = NB/2 packed points z_n = h_2n + i h_2n+1
+// (radix 8 while possible, then 4 or 2); Z ends in natural order, swizzled.
 template <int NC, int NS, bool FROM_INT>
-__device__ __forceinline__ float2 *fft_passes(void *in, float2 *other, const float2 *__restrict__ W, int lane)
+__device__ __forceinline__ void fft_inplace(float2 *buf, const float2 *__restrict__ W, int lane)
 {
     constexpr int REM = NC / NS;
-    if constexpr (REM == 1) {
-        return static_cast<float2 *>(in);
-    } else {
+    if constexpr (REM > 1) {
         constexpr int R = REM >= 8 ? 8 : REM;
-        stockham_pass<NC, R, NS, FROM_INT>(in, other, W, lane);
+        stockham_pass<NC, R, NS, FROM_INT>(buf, W, lane);
         wave_lds_sync();
-        return fft_passes<NC, NS * R, false>(other, static_cast<float2 *>(in), W, lane);
+        fft_inplace<NC, NS * R, false>(buf, W, lane);
     }
 }
 
-// |X_k| of the real input from the packed complex transform Z (length NC):
-// X_k = E_k + exp(-2 pi i k / NB) O_k, E_k = (Z_k + conj Z_{NC-k}) / 2,
+// |X_k| of the real input from the packed complex transform Z (length NC,
+// swizzled): X_k = E_k + exp(-2 pi i k / NB) O_k, E_k = (Z_k + conj Z_{NC-k}) / 2,
 // O_k = -i (Z_k - conj Z_{NC-k}) / 2, for 0 <= k <= NC.
 template <int NC>
 __device__ __forceinline__ float real_amplitude(const float2 *__restrict__ Z, const float2 *__restrict__ W, int k)
 {
-    const float2 zk = Z[k & (NC - 1)];
-    const float2 zm = Z[(NC - k) & (NC - 1)];
+    const float2 zk = Z[swz(k & (NC - 1))];
+    const float2 zm = Z[swz((NC - k) & (NC - 1))];
     const float2 e = make_float2(0.5f * (zk.x + zm.x), 0.5f * (zk.y - zm.y));
     const float2 o = make_float2(0.5f * (zk.y + zm.y), -0.5f * (zk.x - zm.x));
     const float2 x = cadd(e, cmul(W[k], o));
     return sqrtf(fmaf(x.x, x.x, x.y * x.y));
 }
 
-// Eq. (1) for one atom: bin index, FP32, fixed operation order.
+// Eq. (1) for one atom: bin index, FP32, fixed operation order.  The clamp
+// is applied before the conversion: trunc(clamp(t, 0, last)) equals
+// clamp(floor(t), 0, last) for every finite t (on [0, last] trunc = floor;
+// below 0 both give 0; above last both give last), and the conversion input
+// is always in range.
 __device__ __forceinline__ int eq1_bin(float vx, float vy, float vz, float dx, float dy, float dz, float shift,
                                        float scale, float last)
 {
     const float s = fmaf(vz, dz, fmaf(vy, dy, vx * dx));
     const float t = (s + shift) * scale;
-    return (int)fminf(fmaxf(floorf(t), 0.0f), last);
+    return (int)__builtin_amdgcn_fmed3f(t, 0.0f, last);
 }
 
 }  // namespace sig

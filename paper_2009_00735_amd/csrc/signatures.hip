@@ -34,7 +34,10 @@ struct Tables {
     const float2 *W;     // exp(-2 pi i m / NB), m < NB
 };
 
-template <int LOGNB> constexpr size_t lds_bytes_per_wave() { return (size_t)(1 << LOGNB) * 8; }
+// per wave: one buffer holding the histogram (NB ints), then in place the
+// FFT (NB/2 float2), followed by 64 slots that take the discarded atomics of
+// idle lanes and later the window amplitudes of up to 64 bins at a time
+template <int LOGNB> constexpr size_t lds_bytes_per_wave() { return (size_t)(1 << LOGNB) * 4 + 256; }
 template <int LOGNB> constexpr size_t lds_bytes_table() { return (size_t)(1 << LOGNB) * 8; }
 
 template <int MAXA>
@@ -56,18 +59,28 @@ struct AtomRegs {
 };
 
 // Eq. (1) histogram of `rem` atoms held in registers (lane-strided), added
-// into the wave's LDS histogram.
+// into the wave's LDS histogram.  Slots go in groups of four: one uniform
+// branch per group, the four bins formed first and the LDS atomics then issued
+// back to back (no VGPR reuse between them, so no wait on each one).  Lanes
+// past the last atom add into per-lane discard slots hist[NB + lane] instead
+// of branching.
 template <int NB, int MAXA>
 __device__ __forceinline__ void bin_atoms(const AtomRegs<MAXA> &at, int rem, float vx, float vy, float vz,
                                           BinConsts bc, int *__restrict__ hist, int lane)
 {
-    const float last = (float)(NB - 1);
+    static_assert(MAXA % 4 == 0, "register chunk must be a multiple of 4 slots");
 #pragma unroll
-    for (int a = 0; a < MAXA; ++a) {
-        if (a * kWave >= rem) break;
-        if (a * kWave + lane < rem) {
-            const int b = eq1_bin(vx, vy, vz, at.x[a], at.y[a], at.z[a], bc.shift, bc.scale, last);
-            atomicAdd(&hist[b], 1);
+    for (int g = 0; g < MAXA; g += 4) {
+        if (g * kWave < rem) {
+            int b[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int a = g + i;
+                const int bin = eq1_bin(vx, vy, vz, at.x[a], at.y[a], at.z[a], bc.shift, bc.scale, (float)(NB - 1));
+                b[i] = a * kWave + lane < rem ? bin : NB + lane;
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i) atomicAdd(&hist[b[i]], 1);
         }
     }
 }
@@ -76,8 +89,8 @@ __device__ __forceinline__ void bin_atoms(const AtomRegs<MAXA> &at, int rem, flo
 template <int LOGNB, int MAXA, bool DEBUG>
 __device__ __forceinline__ void one_direction(AtomRegs<MAXA> &at, bool resident, const float4 *__restrict__ rel,
                                               int64_t off0, int nw, float vx, float vy, float vz, BinConsts bc,
-                                              const WindowSet &ws, const float2 *__restrict__ W, int *A, float2 *B,
-                                              int lane, float *win_out /* lane w < n_win: result */,
+                                              const WindowSet &ws, const float2 *__restrict__ W, int *A, int lane,
+                                              float *win_out /* lane w < n_win: result */,
                                               int32_t *__restrict__ hist_out, float *__restrict__ amp_out)
 {
     constexpr int NB = 1 << LOGNB;
@@ -97,16 +110,15 @@ __device__ __forceinline__ void one_direction(AtomRegs<MAXA> &at, bool resident,
     wave_lds_sync();
     if constexpr (DEBUG) {
         for (int i = lane; i < NB; i += kWave) hist_out[i] = A[i];
+        wave_lds_sync();
     }
-    float2 *Z = fft_passes<NC, 1, true>(A, B, W, lane);
-    float *amp = reinterpret_cast<float *>(Z == B ? static_cast<void *>(A) : static_cast<void *>(B));
+    float2 *Z = reinterpret_cast<float2 *>(A);
+    fft_inplace<NC, 1, true>(Z, W, lane);
+    float *amp = reinterpret_cast<float *>(A + NB);     // 64 scratch slots after the buffer
     if constexpr (DEBUG) {
         for (int k = lane; k <= NC; k += kWave) amp_out[k] = real_amplitude<NC>(Z, W, k);
         wave_lds_sync();
     } else {
-        const int nk = ws.kmax - ws.kmin + 1;
-        for (int kk = lane; kk < nk; kk += kWave) amp[kk] = real_amplitude<NC>(Z, W, ws.kmin + kk);
-        wave_lds_sync();
         int lo = 0, hi = -1;
         for (int w = 0; w < ws.n; ++w)
             if (lane == w) {
@@ -114,9 +126,15 @@ __device__ __forceinline__ void one_direction(AtomRegs<MAXA> &at, bool resident,
                 hi = ws.hi[w];
             }
         float m = 0.0f;
-        for (int k = lo; k <= hi; ++k) m = fmaxf(m, amp[k - ws.kmin]);
+        for (int kc = ws.kmin; kc <= ws.kmax; kc += kWave) {
+            const int k = kc + lane;
+            if (k <= ws.kmax) amp[lane] = real_amplitude<NC>(Z, W, k);
+            wave_lds_sync();
+            const int k0 = max(lo, kc), k1 = min(hi, kc + kWave - 1);
+            for (int kk = k0; kk <= k1; ++kk) m = fmaxf(m, amp[kk - kc]);
+            wave_lds_sync();
+        }
         *win_out = m;
-        wave_lds_sync();
     }
 }
 
@@ -135,7 +153,6 @@ __global__ __launch_bounds__(256) void k_signatures_plain(
     const int nwaves = blockDim.x >> 6;
     unsigned char *mine = smem + lds_bytes_table<LOGNB>() + (size_t)wave * lds_bytes_per_wave<LOGNB>();
     int *A = reinterpret_cast<int *>(mine);
-    float2 *B = reinterpret_cast<float2 *>(mine + NB * 4);
     for (int i = threadIdx.x; i < NB; i += blockDim.x) W[i] = Wg[i];
     __syncthreads();
 
@@ -152,7 +169,7 @@ __global__ __launch_bounds__(256) void k_signatures_plain(
         const float vx = dirs[3 * v], vy = dirs[3 * v + 1], vz = dirs[3 * v + 2];
         float m;
         const size_t dbg = ((size_t)r * n_dir + v);
-        one_direction<LOGNB, MAXA, DEBUG>(at, resident, rel, off0, nw, vx, vy, vz, bc, ws, W, A, B, lane, &m,
+        one_direction<LOGNB, MAXA, DEBUG>(at, resident, rel, off0, nw, vx, vy, vz, bc, ws, W, A, lane, &m,
                                           DEBUG ? hist_out + dbg * NB : nullptr,
                                           DEBUG ? amp_out + dbg * (NB / 2 + 1) : nullptr);
         if (!DEBUG && lane < ws.n) images[((size_t)r * ws.n + lane) * n_dir + v] = m;
@@ -176,7 +193,6 @@ __global__ __launch_bounds__(256) void k_signatures_persistent(
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     unsigned char *mine = smem + lds_bytes_table<LOGNB>() + (size_t)wave * lds_bytes_per_wave<LOGNB>();
     int *A = reinterpret_cast<int *>(mine);
-    float2 *B = reinterpret_cast<float2 *>(mine + NB * 4);
     for (int i = threadIdx.x; i < NB; i += blockDim.x) W[i] = Wg[i];
     __syncthreads();
 
@@ -204,7 +220,7 @@ __global__ __launch_bounds__(256) void k_signatures_persistent(
         for (int v = v0; v < v1; ++v) {
             const float vx = dirs[3 * v], vy = dirs[3 * v + 1], vz = dirs[3 * v + 2];
             float m;
-            one_direction<LOGNB, MAXA, false>(at, resident, rel, off0, nw, vx, vy, vz, bc, ws, W, A, B, lane, &m,
+            one_direction<LOGNB, MAXA, false>(at, resident, rel, off0, nw, vx, vy, vz, bc, ws, W, A, lane, &m,
                                               nullptr, nullptr);
             if (lane < ws.n) images[((size_t)r * ws.n + lane) * n_dir + v] = m;
         }
@@ -263,10 +279,10 @@ PersFn pers_kernel(int lognb, int maxa)
     }
 }
 
-// Waves per workgroup: keep the workgroup's LDS (table + per-wave buffers)
-// at or below 64 KiB.
-int waves_for(int nbins) { return nbins <= 1024 ? 4 : (nbins == 2048 ? 2 : 1); }
-size_t lds_for(int nbins, int waves) { return (size_t)nbins * 8 * (1 + waves); }
+// Waves per workgroup: keep the workgroup's LDS (twiddle table + per-wave
+// buffers) at or below 64 KiB.
+int waves_for(int nbins) { return nbins <= 2048 ? 4 : 1; }
+size_t lds_for(int nbins, int waves) { return (size_t)nbins * 8 + (size_t)waves * ((size_t)nbins * 4 + 256); }
 
 }  // namespace sig
 
@@ -558,6 +574,22 @@ ar_status ar_signature_plan_tune(ar_plan *p, const float *rel, const int64_t *of
     p->tuned = true;
     p->have_key = false;
     return ar::plan_launch(p, rel, offsets, n_roi, radius, directions, ws, images, s);
+}
+
+ar_status ar_signature_plan_set_config(ar_plan *p, int32_t dirs_per_item, int32_t atoms_per_lane,
+                                       int32_t blocks_per_cu)
+{
+    AR_CHECK(p != nullptr, "plan is NULL");
+    AR_CHECK(dirs_per_item >= 1 && dirs_per_item <= p->n_dir, "dirs_per_item must be in [1, n_dir]");
+    AR_CHECK(atoms_per_lane == 8 || atoms_per_lane == 16 || atoms_per_lane == 24 || atoms_per_lane == 32,
+             "atoms_per_lane must be 8, 16, 24 or 32");
+    AR_CHECK(blocks_per_cu >= 1 && blocks_per_cu <= 16, "blocks_per_cu must be in [1, 16]");
+    p->dpi = dirs_per_item;
+    p->maxa = atoms_per_lane;
+    p->blocks_per_cu = blocks_per_cu;
+    p->tuned = true;
+    p->have_key = false;
+    return AR_OK;
 }
 
 ar_status ar_signature_plan_config(const ar_plan *p, int32_t *dirs_per_item, int32_t *atoms_per_lane,

@@ -38,10 +38,12 @@ _SIGS = {
     "ar_signature_plan_destroy": ([vp], ctypes.c_int),
     "ar_signature_plan_tune": ([vp, vp, vp, i64, f32, vp, vp, vp, vp], ctypes.c_int),
     "ar_signature_plan_config": ([vp, P(i32), P(i32), P(i32)], ctypes.c_int),
+    "ar_signature_plan_set_config": ([vp, i32, i32, i32], ctypes.c_int),
     "ar_signature_plan_run": ([vp, vp, vp, i64, f32, vp, vp, vp, i32, vp], ctypes.c_int),
     "ar_library_create": ([vp, vp, i64, i32, i32, vp, P(vp)], ctypes.c_int),
     "ar_library_destroy": ([vp], ctypes.c_int),
     "index_orientations": ([vp, vp, i64, vp, i32, vp, vp, vp], ctypes.c_int),
+    "ar_index_set_tile": ([vp, i32, i32, i32], ctypes.c_int),
     "index_orientations_ex": ([vp, vp, i64, vp, i32, i32, vp, vp, vp, vp], ctypes.c_int),
     "ar_disorientation_cubic": ([vp, vp, i64, vp, vp], ctypes.c_int),
     "ar_rotate_reference": ([vp, vp, i32, i32, vp, i32, vp, vp, i64, vp, vp], ctypes.c_int),
@@ -234,6 +236,9 @@ class SignaturePlan:
         _call("ar_signature_plan_config", self.handle, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c))
         return a.value, b.value, c.value
 
+    def set_config(self, dirs_per_item: int, atoms_per_lane: int, blocks_per_cu: int):
+        _call("ar_signature_plan_set_config", self.handle, dirs_per_item, atoms_per_lane, blocks_per_cu)
+
     def run(self, rel, offsets, radius, directions, windows, out=None, use_graph: bool = True):
         images = self._out(offsets, out)
         w = _host_windows(windows)
@@ -278,6 +283,10 @@ class Library:
             self.close()
         except Exception:
             pass
+
+
+def ar_index_set_tile(ctx: Context, wtm: int, wtn: int, bk: int) -> None:
+    _call("ar_index_set_tile", ctx.handle, wtm, wtn, bk)
 
 
 def index_orientations(ctx: Context, images: torch.Tensor, library: Library, k: int = 16):
