@@ -261,7 +261,8 @@ def main():
                                "20000-orientation library; 50-step refinement",
                    "n_roi": n_roi, "n_dir": n_dir, "nbins": nb, "n_win": n_win, "n_lib": n_lib,
                    "mean_atoms_per_roi": n_w_mean, "refine_steps": args.refine_steps,
-                   "signature_plan": dict(zip(["dirs_per_item", "atoms_per_lane", "waves"], plan.config()))},
+                   "signature_plan": dict(zip(["dirs_per_item", "atoms_per_stage", "blocks_per_cu", "min_waves"],
+                                             plan.config()))},
         "indexed_rois_per_s": n_roi / (ms_step / 1e3),
         "stage_ms": stage_ms,
         "stage_rates": {

@@ -108,8 +108,9 @@ ar_status ar_roi_gather(ar_context *ctx, const float *positions, int64_t n_atoms
  *              k_hi <= nbins/2, n_win in [1, 16]
  *   images     device float [n_roi][n_win][n_dir], out
  *   roi_counts device int32 [n_roi] or NULL, out: atoms per ROI
- * ROIs with no atoms get zero images.  Any atom count is accepted (atoms are
- * streamed through registers in chunks).  Synchronises (ROI query).
+ * ROIs with no atoms get zero images.  Any atom count is accepted (a ROI
+ * larger than the LDS atom stage is streamed through it in chunks).
+ * Synchronises (ROI query).
  */
 ar_status araullo_signatures(ar_context *ctx, const float *positions, int64_t n_atoms,
                              const float *centres, int64_t n_roi, float radius,
@@ -160,14 +161,19 @@ ar_status ar_signature_plan_destroy(ar_plan *plan);
 ar_status ar_signature_plan_tune(ar_plan *plan, const float *rel, const int64_t *offsets,
                                  int64_t n_roi, float radius, const float *directions,
                                  const int32_t *windows, float *images, void *stream);
-/* Chosen tile: directions per work item and atoms-per-lane register chunk. */
+/* Chosen configuration (any out pointer may be NULL): directions per work
+ * item, atoms per LDS stage, workgroups launched per compute unit, and the
+ * register form (1: as allocated, 4: at most 128 VGPRs per lane so four
+ * wavefronts share a SIMD). */
 ar_status ar_signature_plan_config(const ar_plan *plan, int32_t *dirs_per_item,
-                                   int32_t *atoms_per_lane, int32_t *waves_per_group);
-/* Pin a tile configuration instead of tuning: directions per work item
- * (1..n_dir), atoms per lane held in registers (8, 16, 24 or 32) and
- * resident workgroups per compute unit (1..16). */
-ar_status ar_signature_plan_set_config(ar_plan *plan, int32_t dirs_per_item, int32_t atoms_per_lane,
-                                       int32_t blocks_per_cu);
+                                   int32_t *atoms_per_stage, int32_t *blocks_per_cu,
+                                   int32_t *min_waves);
+/* Pin a configuration instead of tuning: directions per work item
+ * (1..n_dir), atoms per LDS stage (a multiple of 256 in [256, 4096]; larger
+ * ROIs are streamed through it), workgroups per compute unit (1..16) and
+ * min_waves 1, or 4 for nbins <= 1024. */
+ar_status ar_signature_plan_set_config(ar_plan *plan, int32_t dirs_per_item, int32_t atoms_per_stage,
+                                       int32_t blocks_per_cu, int32_t min_waves);
 /* Run the batch. The host reads roi sizes once per new `offsets` pointer or
  * n_roi to order the queue (synchronises then); with use_graph != 0 the
  * launch sequence is captured once per argument set and replayed. */
@@ -219,8 +225,8 @@ ar_status index_orientations_ex(ar_context *ctx, const float *images, int64_t n_
 
 /* Correlation tile of this context's index calls: each of the 4 wavefronts
  * of a workgroup owns wtm x wtn MFMA tiles of 32x32 (workgroup tile
- * 64 wtm x 64 wtn), K advances bk per step.  Supported: 2x2x64 (default),
- * 2x4x32, 4x2x32, 4x4x32, 2x4x64.  Results do not depend on the tile. */
+ * 64 wtm x 64 wtn), K advances bk per step.  Supported: 2x2x64, 2x4x32,
+ * 4x2x32, 4x4x32, 2x4x64 (default).  Results do not depend on the tile. */
 ar_status ar_index_set_tile(ar_context *ctx, int32_t wtm, int32_t wtn, int32_t bk);
 
 /*

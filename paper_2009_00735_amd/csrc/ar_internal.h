@@ -57,6 +57,7 @@ constexpr int kMaxWindows = 16;
 struct WindowSet {
     int n;
     int kmin, kmax;          // union of all windows
+    int rows;                // 1: n <= 4, kmax - kmin < 64 and every window at most 16 bins wide
     int lo[kMaxWindows];
     int hi[kMaxWindows];
 };
@@ -77,7 +78,7 @@ struct ar_context {
     // gathered CSR used by the position-taking signature entry points
     ar::DeviceBuffer s_rel;
     // correlation tile: per-wave 32x32 MFMA tiles (wtm x wtn) and K step
-    int corr_wtm = 2, corr_wtn = 2, corr_bk = 64;
+    int corr_wtm = 2, corr_wtn = 4, corr_bk = 64;
     // indexing workspace
     ar::DeviceBuffer i_bf16, i_inv, i_cand_idx, i_cand_score, i_merge_idx;
     // refinement workspace

@@ -84,6 +84,9 @@ ar_status make_windows(const int32_t *windows, int32_t n_win, int32_t nbins, Win
         if (hi > ws->kmax) ws->kmax = hi;
     }
     for (int w = n_win; w < kMaxWindows; ++w) ws->lo[w] = ws->hi[w] = 0;
+    ws->rows = n_win <= 4 && ws->kmax - ws->kmin < 64;
+    for (int w = 0; w < n_win; ++w)
+        if (ws->hi[w] - ws->lo[w] >= 16) ws->rows = 0;
     return AR_OK;
 }
 

@@ -3,19 +3,21 @@
 // reconstruction parameters): per (ROI, direction) an Eq. (1) histogram,
 // its Fourier amplitude spectrum and the maximum amplitude in each window.
 //
-// gfx950 design.  Every wavefront works alone on whole directions: the ROI's
-// relative coordinates sit in VGPRs (MAXA atoms per lane, more atoms are
-// streamed in chunks of 64*MAXA), the direction is wave-uniform (SGPRs), the
-// histogram is a wave-private LDS array filled with LDS atomics, the
-// 2^m-point real FFT is one 2^(m-1)-point complex Stockham FFT in the same
-// LDS (radix-8 passes, ping-pong between the histogram array and a second
-// array, twiddles from a per-workgroup LDS table), and only the window bins of
-// the one-sided spectrum are formed.  No workgroup barrier is needed after
-// the twiddle table is loaded.
+// gfx950 design.  A workgroup of four wavefronts works on one ROI at a time:
+// the ROI's relative coordinates are staged once in LDS (larger ROIs in
+// chunks), each wavefront takes whole directions (wave-uniform, in SGPRs)
+// and reads every atom from the stage with one 16-byte LDS load.  The
+// histogram is a wave-private int32 array in LDS filled with LDS integer
+// atomics.  The 2^m-point real FFT is one 2^(m-1)-point complex
+// Stockham FFT in place in the same LDS (radix-8 passes, twiddle factors per
+// lane in registers), and its last stage is evaluated only for the spectrum
+// bins the windows cover, fused with the real-input post-processing and
+// |X_k|.  Window maxima are a 16-lane DPP reduction.  No workgroup barrier is
+// needed for a ROI whose atoms fit the stage.
 //
 // Two launch forms share that per-direction code:
 //   plain       one workgroup per (ROI, direction tile), hardware dispatch;
-//   persistent  CU-filling grid whose wavefronts pull (ROI, direction chunk)
+//   persistent  CU-filling grid whose workgroups pull (ROI, direction chunk)
 //               items from a device counter, ROIs ordered by decreasing atom
 //               count, replayed as a captured HIP graph.
 #include <math.h>
@@ -30,131 +32,217 @@
 namespace ar {
 namespace sig {
 
-struct Tables {
-    const float2 *W;     // exp(-2 pi i m / NB), m < NB
-};
+constexpr int kWaves = 4;             // wavefronts per workgroup
+constexpr int kStageMult = 256;       // stage capacity granularity (atoms)
+constexpr int kStageMax = 4096;
 
-// per wave: one buffer holding the histogram (NB ints), then in place the
-// FFT (NB/2 float2), followed by 64 slots that take the discarded atomics of
-// idle lanes and later the window amplitudes of up to 64 bins at a time
-template <int LOGNB> constexpr size_t lds_bytes_per_wave() { return (size_t)(1 << LOGNB) * 4 + 256; }
-template <int LOGNB> constexpr size_t lds_bytes_table() { return (size_t)(1 << LOGNB) * 8; }
+// LDS: the atom stage (cap float4), per wavefront the histogram / FFT buffer
+// (NB floats) and 64 scratch floats (discarded atomics of idle lanes, window
+// amplitudes), then a 16-byte item slot.
+constexpr size_t wave_bytes(int nb) { return (size_t)nb * 4 + 256; }
+__host__ __device__ constexpr size_t slot_offset(int nb, int cap) { return (size_t)cap * 16 + (size_t)kWaves * wave_bytes(nb); }
+size_t lds_for(int nbins, int cap) { return slot_offset(nbins, cap) + 16; }
 
-template <int MAXA>
-struct AtomRegs {
-    float x[MAXA], y[MAXA], z[MAXA];
+// Per-lane constants of the transform, loaded once per kernel.
+template <int LOGNB> struct LaneConsts {
+    static constexpr int NB = 1 << LOGNB;
+    static constexpr int NC = NB / 2;
+    static constexpr int R_LAST = FftPlan<NC>::R_LAST;
+    PassTwiddles<NB, 8> tw8;
+    PassTwiddles<NB, 64> tw64;
+    float2 ftw[R_LAST - 1];   // w^(t k), w = exp(-2 pi i / NC), k = this lane's bin
+    float2 wk;                // exp(-2 pi i k / NB)
+    int mm1, mm2;             // last-stage base indices of k and NC - k
+    int rd;                   // row reduction: scratch slot read by this lane
 
-    __device__ __forceinline__ void load(const float4 *__restrict__ rel, int64_t off0, int first, int nw, int lane)
+    __device__ __forceinline__ void load_bin(const float2 *__restrict__ Wg, int kk)
     {
+        constexpr int NS = FftPlan<NC>::NS_LAST;
+        mm1 = last_base<NS>(kk & (NS - 1));
+        mm2 = last_base<NS>((NC - kk) & (NS - 1));
 #pragma unroll
-        for (int a = 0; a < MAXA; ++a) {
-            const int i = first + a * kWave + lane;
-            float4 p = make_float4(0.f, 0.f, 0.f, 0.f);
-            if (i < nw) p = rel[off0 + i];
-            x[a] = p.x;
-            y[a] = p.y;
-            z[a] = p.z;
-        }
+        for (int t = 1; t < R_LAST; ++t) ftw[t - 1] = Wg[(2 * t * kk) & (NB - 1)];
+        wk = Wg[kk];
+    }
+
+    __device__ __forceinline__ void load(const float2 *__restrict__ Wg, const WindowSet &ws, int lane)
+    {
+        if constexpr (FftPlan<NC>::NS_LAST > 8) tw8.load(Wg, lane);
+        if constexpr (FftPlan<NC>::NS_LAST > 64) tw64.load(Wg, lane);
+        load_bin(Wg, min(ws.kmin + lane, ws.kmax));
+        // row w = lane / 16 reads window w, bin lo_w + min(lane % 16, width - 1)
+        rd = 0;
+        const int w = lane >> 4, i = lane & 15;
+        for (int u = 0; u < ws.n && u < 4; ++u)
+            if (w == u) rd = ws.lo[u] - ws.kmin + min(i, ws.hi[u] - ws.lo[u]);
     }
 };
 
-// Eq. (1) histogram of `rem` atoms held in registers (lane-strided), added
-// into the wave's LDS histogram.  Slots go in groups of four: one uniform
-// branch per group, the four bins formed first and the LDS atomics then issued
-// back to back (no VGPR reuse between them, so no wait on each one).  Lanes
-// past the last atom add into per-lane discard slots hist[NB + lane] instead
-// of branching.
-template <int NB, int MAXA>
-__device__ __forceinline__ void bin_atoms(const AtomRegs<MAXA> &at, int rem, float vx, float vy, float vz,
-                                          BinConsts bc, int *__restrict__ hist, int lane)
+// Stage atoms [first, first + n) of a ROI into LDS (all threads of the
+// workgroup; the caller synchronises).
+__device__ __forceinline__ void stage_atoms(float4 *xs, const float4 *__restrict__ rel, int64_t first, int n)
 {
-    static_assert(MAXA % 4 == 0, "register chunk must be a multiple of 4 slots");
+    for (int i = threadIdx.x; i < n; i += blockDim.x) xs[i] = rel[first + i];
+}
+
+// Eq. (1) histogram of n staged atoms (slot a * 64 + lane), added into the
+// wave's LDS histogram.  Slots go in groups of four: the four bins are formed
+// first and the LDS atomics then issued back to back.  Full groups need no
+// test; in the last group lanes past the end add into their discard slot
+// hist[NB + lane].  The stage holds a multiple of 256 atoms, so the reads of
+// the last group stay inside it.
+template <int NB>
+__device__ __forceinline__ void bin_staged(const float4 *xs, int n, float vx, float vy, float vz, BinConsts bc,
+                                           int *hist, int lane)
+{
+    constexpr float last = (float)(NB - 1);
+    const float4 *p = xs + lane;
+    int g = 0;
+    for (; (g + 4) * kWave <= n; g += 4, p += 4 * kWave) {
+        int b[4];
 #pragma unroll
-    for (int g = 0; g < MAXA; g += 4) {
-        if (g * kWave < rem) {
-            int b[4];
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int a = g + i;
-                const int bin = eq1_bin(vx, vy, vz, at.x[a], at.y[a], at.z[a], bc.shift, bc.scale, (float)(NB - 1));
-                b[i] = a * kWave + lane < rem ? bin : NB + lane;
-            }
-#pragma unroll
-            for (int i = 0; i < 4; ++i) atomicAdd(&hist[b[i]], 1);
+        for (int i = 0; i < 4; ++i) {
+            const float4 x = p[i * kWave];
+            b[i] = eq1_bin(vx, vy, vz, x.x, x.y, x.z, bc.shift, bc.scale, last);
         }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) atomicAdd(&hist[b[i]], 1);
+    }
+    if (g * kWave < n) {
+        int b[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const float4 x = p[i * kWave];
+            const int bin = eq1_bin(vx, vy, vz, x.x, x.y, x.z, bc.shift, bc.scale, last);
+            b[i] = (g + i) * kWave + lane < n ? bin : NB + lane;
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) atomicAdd(&hist[b[i]], 1);
     }
 }
 
-// One direction, from zeroing the histogram to the window maxima / debug dump.
-template <int LOGNB, int MAXA, bool DEBUG>
-__device__ __forceinline__ void one_direction(AtomRegs<MAXA> &at, bool resident, const float4 *__restrict__ rel,
-                                              int64_t off0, int nw, float vx, float vy, float vz, BinConsts bc,
-                                              const WindowSet &ws, const float2 *__restrict__ W, int *A, int lane,
-                                              float *win_out /* lane w < n_win: result */,
-                                              int32_t *__restrict__ hist_out, float *__restrict__ amp_out)
+template <int NB> __device__ __forceinline__ void zero_hist(float *A, int lane)
+{
+#pragma unroll
+    for (int i = 0; i < NB / 4 / kWave; ++i) reinterpret_cast<int4 *>(A)[i * kWave + lane] = make_int4(0, 0, 0, 0);
+    wave_lds_sync();
+}
+
+// Transform the finished histogram of direction v of ROI r and write its
+// window maxima (or, DEBUG, the histogram and the whole spectrum).
+template <int LOGNB, bool DEBUG>
+__device__ __forceinline__ void finish_direction(float *A, LaneConsts<LOGNB> &lc, const WindowSet &ws,
+                                                 const float2 *__restrict__ Wg, int lane, int64_t r, int v,
+                                                 int n_dir, float *__restrict__ images,
+                                                 int32_t *__restrict__ hist_out, float *__restrict__ amp_out)
 {
     constexpr int NB = 1 << LOGNB;
     constexpr int NC = NB / 2;
-    constexpr int CH = MAXA * kWave;
-#pragma unroll
-    for (int i = lane; i < NB / 4; i += kWave) reinterpret_cast<int4 *>(A)[i] = make_int4(0, 0, 0, 0);
     wave_lds_sync();
-    if (resident) {
-        bin_atoms<NB, MAXA>(at, nw, vx, vy, vz, bc, A, lane);
-    } else {
-        for (int c = 0; c < nw; c += CH) {
-            at.load(rel, off0, c, nw, lane);
-            bin_atoms<NB, MAXA>(at, nw - c, vx, vy, vz, bc, A, lane);
-        }
-    }
-    wave_lds_sync();
-    if constexpr (DEBUG) {
-        for (int i = lane; i < NB; i += kWave) hist_out[i] = A[i];
-        wave_lds_sync();
-    }
     float2 *Z = reinterpret_cast<float2 *>(A);
-    fft_inplace<NC, 1, true>(Z, W, lane);
-    float *amp = reinterpret_cast<float *>(A + NB);     // 64 scratch slots after the buffer
+    float *scratch = A + NB;
     if constexpr (DEBUG) {
-        for (int k = lane; k <= NC; k += kWave) amp_out[k] = real_amplitude<NC>(Z, W, k);
+        const size_t d = (size_t)r * n_dir + v;
+        for (int i = lane; i < NB; i += kWave) hist_out[d * NB + i] = reinterpret_cast<const int32_t *>(A)[i];
         wave_lds_sync();
-    } else {
-        int lo = 0, hi = -1;
-        for (int w = 0; w < ws.n; ++w)
-            if (lane == w) {
-                lo = ws.lo[w];
-                hi = ws.hi[w];
-            }
-        float m = 0.0f;
-        for (int kc = ws.kmin; kc <= ws.kmax; kc += kWave) {
-            const int k = kc + lane;
-            if (k <= ws.kmax) amp[lane] = real_amplitude<NC>(Z, W, k);
-            wave_lds_sync();
-            const int k0 = max(lo, kc), k1 = min(hi, kc + kWave - 1);
-            for (int kk = k0; kk <= k1; ++kk) m = fmaxf(m, amp[kk - kc]);
-            wave_lds_sync();
+        fft_head<NB, NC, 1, true>(Z, lc.tw8, lc.tw64, lane);
+        stockham_last_full<NB, NC, FftPlan<NC>::R_LAST, FftPlan<NC>::NS_LAST>(Z, Wg, lane);
+        wave_lds_sync();
+        for (int k = lane; k <= NC; k += kWave) amp_out[d * (NC + 1) + k] = real_amplitude<NC>(Z, Wg, k);
+        wave_lds_sync();
+        return;
+    }
+    fft_head<NB, NC, 1, true>(Z, lc.tw8, lc.tw64, lane);
+    wave_lds_sync();
+    if (ws.rows) {
+        scratch[lane] = bin_amplitude<NC>(Z, lc.mm1, lc.mm2, lc.ftw, lc.wk);
+        wave_lds_sync();
+        const float m = row_max16(scratch[lc.rd]);
+        const int w = lane >> 4;
+        if ((lane & 15) == 0 && w < ws.n) images[((size_t)r * ws.n + w) * n_dir + v] = m;
+        wave_lds_sync();
+        return;
+    }
+    // general windows: bins in chunks of 64, per-lane maxima
+    int lo = 0, hi = -1;
+    for (int w = 0; w < ws.n; ++w)
+        if (lane == w) {
+            lo = ws.lo[w];
+            hi = ws.hi[w];
         }
-        *win_out = m;
+    float m = 0.0f;
+    for (int kc = ws.kmin; kc <= ws.kmax; kc += kWave) {
+        if (kc != ws.kmin) lc.load_bin(Wg, min(kc + lane, ws.kmax));
+        scratch[lane] = bin_amplitude<NC>(Z, lc.mm1, lc.mm2, lc.ftw, lc.wk);
+        wave_lds_sync();
+        const int k0 = max(lo, kc), k1 = min(hi, kc + kWave - 1);
+        for (int kk = k0; kk <= k1; ++kk) m = fmaxf(m, scratch[kk - kc]);
+        wave_lds_sync();
+    }
+    if (ws.kmax - ws.kmin >= kWave) lc.load_bin(Wg, min(ws.kmin + lane, ws.kmax));
+    if (lane < ws.n) images[((size_t)r * ws.n + lane) * n_dir + v] = m;
+}
+
+// Directions [v0, v1) of ROI r (atoms [off0, off0 + nw)) by the four
+// wavefronts of the workgroup.  If the ROI fits the stage the caller has
+// staged it (staged == true) and the wavefronts run independently; otherwise
+// every direction round streams the atoms through the stage in chunks, with
+// workgroup barriers around each refill (the round count is uniform, so all
+// wavefronts meet every barrier).
+template <int LOGNB, bool DEBUG>
+__device__ __forceinline__ void process_item(const float4 *__restrict__ rel, int64_t off0, int nw, int64_t r,
+                                             int v0, int v1, const float *__restrict__ dirs, int n_dir,
+                                             BinConsts bc, const WindowSet &ws, LaneConsts<LOGNB> &lc,
+                                             const float2 *__restrict__ Wg, float4 *xs, int cap, float *A,
+                                             int wave, int lane, float *__restrict__ images,
+                                             int32_t *__restrict__ hist_out, float *__restrict__ amp_out)
+{
+    constexpr int NB = 1 << LOGNB;
+    if (nw <= cap) {
+        for (int v = v0 + wave; v < v1; v += kWaves) {
+            const float vx = dirs[3 * v], vy = dirs[3 * v + 1], vz = dirs[3 * v + 2];
+            zero_hist<NB>(A, lane);
+            bin_staged<NB>(xs, nw, vx, vy, vz, bc, reinterpret_cast<int *>(A), lane);
+            finish_direction<LOGNB, DEBUG>(A, lc, ws, Wg, lane, r, v, n_dir, images, hist_out, amp_out);
+        }
+        return;
+    }
+    for (int vr = v0; vr < v1; vr += kWaves) {
+        const int v = vr + wave;
+        const bool active = v < v1;
+        float vx = 0.f, vy = 0.f, vz = 0.f;
+        if (active) {
+            vx = dirs[3 * v];
+            vy = dirs[3 * v + 1];
+            vz = dirs[3 * v + 2];
+            zero_hist<NB>(A, lane);
+        }
+        for (int c0 = 0; c0 < nw; c0 += cap) {
+            const int n = min(cap, nw - c0);
+            __syncthreads();
+            stage_atoms(xs, rel, off0 + c0, n);
+            __syncthreads();
+            if (active) bin_staged<NB>(xs, n, vx, vy, vz, bc, reinterpret_cast<int *>(A), lane);
+        }
+        if (active) finish_direction<LOGNB, DEBUG>(A, lc, ws, Wg, lane, r, v, n_dir, images, hist_out, amp_out);
     }
 }
 
 // ---------------------------------------------------------------- plain form
-template <int LOGNB, int MAXA, bool DEBUG>
+template <int LOGNB, bool DEBUG>
 __global__ __launch_bounds__(256) void k_signatures_plain(
     const float4 *__restrict__ rel, const int64_t *__restrict__ offsets, const float *__restrict__ dirs, int n_dir,
-    int dirs_per_block, int n_tiles, const float2 *__restrict__ Wg, BinConsts bc, WindowSet ws,
+    int dirs_per_block, int n_tiles, const float2 *__restrict__ Wg, BinConsts bc, WindowSet ws, int cap,
     float *__restrict__ images, int32_t *__restrict__ hist_out, float *__restrict__ amp_out)
 {
     constexpr int NB = 1 << LOGNB;
     extern __shared__ __align__(16) unsigned char smem[];
-    float2 *W = reinterpret_cast<float2 *>(smem);
+    float4 *xs = reinterpret_cast<float4 *>(smem);
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int nwaves = blockDim.x >> 6;
-    unsigned char *mine = smem + lds_bytes_table<LOGNB>() + (size_t)wave * lds_bytes_per_wave<LOGNB>();
-    int *A = reinterpret_cast<int *>(mine);
-    for (int i = threadIdx.x; i < NB; i += blockDim.x) W[i] = Wg[i];
-    __syncthreads();
+    float *A = reinterpret_cast<float *>(smem + (size_t)cap * 16 + (size_t)wave * wave_bytes(NB));
+    LaneConsts<LOGNB> lc;
+    lc.load(Wg, ws, lane);
 
     const int64_t r = (int64_t)blockIdx.x / n_tiles;
     const int tile = (int)((int64_t)blockIdx.x - r * n_tiles);
@@ -162,68 +250,58 @@ __global__ __launch_bounds__(256) void k_signatures_plain(
     const int nw = (int)(offsets[r + 1] - off0);
     const int v0 = tile * dirs_per_block;
     const int v1 = min(v0 + dirs_per_block, n_dir);
-    AtomRegs<MAXA> at;
-    const bool resident = nw <= MAXA * kWave;
-    if (resident) at.load(rel, off0, 0, nw, lane);
-    for (int v = v0 + wave; v < v1; v += nwaves) {
-        const float vx = dirs[3 * v], vy = dirs[3 * v + 1], vz = dirs[3 * v + 2];
-        float m;
-        const size_t dbg = ((size_t)r * n_dir + v);
-        one_direction<LOGNB, MAXA, DEBUG>(at, resident, rel, off0, nw, vx, vy, vz, bc, ws, W, A, lane, &m,
-                                          DEBUG ? hist_out + dbg * NB : nullptr,
-                                          DEBUG ? amp_out + dbg * (NB / 2 + 1) : nullptr);
-        if (!DEBUG && lane < ws.n) images[((size_t)r * ws.n + lane) * n_dir + v] = m;
+    if (nw <= cap) {
+        stage_atoms(xs, rel, off0, nw);
+        __syncthreads();
     }
+    process_item<LOGNB, DEBUG>(rel, off0, nw, r, v0, v1, dirs, n_dir, bc, ws, lc, Wg, xs, cap, A, wave, lane,
+                               images, hist_out, amp_out);
 }
 
 // ---------------------------------------------------------- persistent form
 // Item i covers ROI order[i / chunks] and directions
-// [(i % chunks) * dpi, +dpi).  Wavefronts fetch items from *counter until the
-// queue is empty; every wavefront exits after at most n_items + 1 fetches.
-template <int LOGNB, int MAXA>
-__global__ __launch_bounds__(256) void k_signatures_persistent(
+// [(i % chunks) * dpi, +dpi).  Workgroups fetch items from *counter until
+// the queue is empty; every workgroup exits after at most n_items + 1
+// fetches.  A ROI that fits the stage is staged once per run of items on it.
+template <int LOGNB, int MINW>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MINW, 8))) void k_signatures_persistent(
     const float4 *__restrict__ rel, const int64_t *__restrict__ offsets, const int32_t *__restrict__ order,
     int64_t n_items, int chunks, int dpi, const float *__restrict__ dirs, int n_dir, const float2 *__restrict__ Wg,
-    BinConsts bc, WindowSet ws, float *__restrict__ images, unsigned long long *__restrict__ counter)
+    BinConsts bc, WindowSet ws, int cap, float *__restrict__ images, unsigned long long *__restrict__ counter)
 {
     constexpr int NB = 1 << LOGNB;
     extern __shared__ __align__(16) unsigned char smem[];
-    float2 *W = reinterpret_cast<float2 *>(smem);
+    // the item slot lies after the stage and the wave buffers: staging may
+    // start while other wavefronts still read the slot
+    unsigned long long *slot = reinterpret_cast<unsigned long long *>(smem + slot_offset(NB, cap));
+    float4 *xs = reinterpret_cast<float4 *>(smem);
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    unsigned char *mine = smem + lds_bytes_table<LOGNB>() + (size_t)wave * lds_bytes_per_wave<LOGNB>();
-    int *A = reinterpret_cast<int *>(mine);
-    for (int i = threadIdx.x; i < NB; i += blockDim.x) W[i] = Wg[i];
-    __syncthreads();
+    float *A = reinterpret_cast<float *>(smem + (size_t)cap * 16 + (size_t)wave * wave_bytes(NB));
+    LaneConsts<LOGNB> lc;
+    lc.load(Wg, ws, lane);
 
-    AtomRegs<MAXA> at;
     int64_t cur = -1;
-    bool resident = false;
-    int64_t off0 = 0;
-    int nw = 0;
     for (;;) {
-        unsigned long long item = 0;
-        if (lane == 0) item = atomicAdd(counter, 1ull);
-        item = __builtin_amdgcn_readfirstlane((unsigned)item) |
-               ((unsigned long long)__builtin_amdgcn_readfirstlane((unsigned)(item >> 32)) << 32);
-        if ((int64_t)item >= n_items) break;
-        const int64_t r = order[(int64_t)item / chunks];
-        const int c = (int)((int64_t)item % chunks);
-        if (r != cur) {
-            cur = r;
-            off0 = offsets[r];
-            nw = (int)(offsets[r + 1] - off0);
-            resident = nw <= MAXA * kWave;
-            if (resident) at.load(rel, off0, 0, nw, lane);
+        if (threadIdx.x == 0) *slot = atomicAdd(counter, 1ull);
+        __syncthreads();
+        const unsigned long long it = *slot;
+        const int64_t item = (int64_t)(__builtin_amdgcn_readfirstlane((unsigned)it) |
+                                       ((unsigned long long)__builtin_amdgcn_readfirstlane((unsigned)(it >> 32)) << 32));
+        if ((unsigned long long)item >= (unsigned long long)n_items) break;
+        const int64_t r = order[item / chunks];
+        const int c = (int)(item % chunks);
+        const int64_t off0 = offsets[r];
+        const int nw = (int)(offsets[r + 1] - off0);
+        if (nw <= cap && r != cur) {
+            stage_atoms(xs, rel, off0, nw);
+            __syncthreads();
         }
+        cur = nw <= cap ? r : -1;
         const int v0 = c * dpi, v1 = min(v0 + dpi, n_dir);
-        for (int v = v0; v < v1; ++v) {
-            const float vx = dirs[3 * v], vy = dirs[3 * v + 1], vz = dirs[3 * v + 2];
-            float m;
-            one_direction<LOGNB, MAXA, false>(at, resident, rel, off0, nw, vx, vy, vz, bc, ws, W, A, lane, &m,
-                                              nullptr, nullptr);
-            if (lane < ws.n) images[((size_t)r * ws.n + lane) * n_dir + v] = m;
-        }
+        process_item<LOGNB, false>(rel, off0, nw, r, v0, v1, dirs, n_dir, bc, ws, lc, Wg, xs, cap, A, wave, lane,
+                                   images, nullptr, nullptr);
+        __syncthreads();
     }
 }
 
@@ -231,58 +309,49 @@ __global__ void k_zero_counter(unsigned long long *c) { *c = 0ull; }
 
 // ------------------------------------------------------------ dispatch
 using PlainFn = void (*)(const float4 *, const int64_t *, const float *, int, int, int, const float2 *, BinConsts,
-                         WindowSet, float *, int32_t *, float *);
+                         WindowSet, int, float *, int32_t *, float *);
 using PersFn = void (*)(const float4 *, const int64_t *, const int32_t *, int64_t, int, int, const float *, int,
-                        const float2 *, BinConsts, WindowSet, float *, unsigned long long *);
+                        const float2 *, BinConsts, WindowSet, int, float *, unsigned long long *);
 
-static const int kMaxaOptions[] = {8, 16, 24, 32};
-
-template <int LOGNB, bool DEBUG> PlainFn plain_for_maxa(int maxa)
-{
-    switch (maxa) {
-    case 8: return k_signatures_plain<LOGNB, 8, DEBUG>;
-    case 16: return k_signatures_plain<LOGNB, 16, DEBUG>;
-    case 24: return k_signatures_plain<LOGNB, 24, DEBUG>;
-    default: return k_signatures_plain<LOGNB, 32, DEBUG>;
-    }
-}
-
-template <bool DEBUG> PlainFn plain_kernel(int lognb, int maxa)
+template <bool DEBUG> PlainFn plain_kernel(int lognb)
 {
     switch (lognb) {
-    case 8: return plain_for_maxa<8, DEBUG>(maxa);
-    case 9: return plain_for_maxa<9, DEBUG>(maxa);
-    case 10: return plain_for_maxa<10, DEBUG>(maxa);
-    case 11: return plain_for_maxa<11, DEBUG>(maxa);
-    default: return plain_for_maxa<12, DEBUG>(maxa);
+    case 8: return k_signatures_plain<8, DEBUG>;
+    case 9: return k_signatures_plain<9, DEBUG>;
+    case 10: return k_signatures_plain<10, DEBUG>;
+    case 11: return k_signatures_plain<11, DEBUG>;
+    default: return k_signatures_plain<12, DEBUG>;
     }
 }
 
-template <int LOGNB> PersFn pers_for_maxa(int maxa)
-{
-    switch (maxa) {
-    case 8: return k_signatures_persistent<LOGNB, 8>;
-    case 16: return k_signatures_persistent<LOGNB, 16>;
-    case 24: return k_signatures_persistent<LOGNB, 24>;
-    default: return k_signatures_persistent<LOGNB, 32>;
-    }
-}
-
-PersFn pers_kernel(int lognb, int maxa)
+// occ: 0 = registers as the compiler allocates them, 4 = at most 128 VGPRs
+// (four wavefronts per SIMD; may spill).  Only histograms up to 1024 bins
+// have the second form.
+PersFn pers_kernel(int lognb, int occ)
 {
     switch (lognb) {
-    case 8: return pers_for_maxa<8>(maxa);
-    case 9: return pers_for_maxa<9>(maxa);
-    case 10: return pers_for_maxa<10>(maxa);
-    case 11: return pers_for_maxa<11>(maxa);
-    default: return pers_for_maxa<12>(maxa);
+    case 8: return occ == 4 ? k_signatures_persistent<8, 4> : k_signatures_persistent<8, 1>;
+    case 9: return occ == 4 ? k_signatures_persistent<9, 4> : k_signatures_persistent<9, 1>;
+    case 10: return occ == 4 ? k_signatures_persistent<10, 4> : k_signatures_persistent<10, 1>;
+    case 11: return k_signatures_persistent<11, 1>;
+    default: return k_signatures_persistent<12, 1>;
     }
 }
 
-// Waves per workgroup: keep the workgroup's LDS (twiddle table + per-wave
-// buffers) at or below 64 KiB.
-int waves_for(int nbins) { return nbins <= 2048 ? 4 : 1; }
-size_t lds_for(int nbins, int waves) { return (size_t)nbins * 8 + (size_t)waves * ((size_t)nbins * 4 + 256); }
+// Workgroups above 64 KiB of LDS must be allowed explicitly.
+template <typename Fn> ar_status allow_lds(Fn fn, size_t lds)
+{
+    if (lds > 65536) AR_HIP(hipFuncSetAttribute((const void *)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    return AR_OK;
+}
+
+// Stage capacity for a largest ROI of `big` atoms: the next multiple of 256,
+// at most kStageMax (larger ROIs are streamed through the stage).
+int stage_for(int64_t big)
+{
+    const int64_t c = (std::max<int64_t>(big, 1) + kStageMult - 1) / kStageMult * kStageMult;
+    return (int)std::min<int64_t>(c, kStageMax);
+}
 
 }  // namespace sig
 
@@ -300,20 +369,22 @@ ar_status check_sig_args(ar_context *ctx, int64_t n_roi, float radius, const flo
 
 ar_status launch_plain(ar_context *ctx, const float *rel, const int64_t *offsets, int64_t n_roi, float radius,
                        const float *directions, int32_t n_dir, int32_t nbins, const WindowSet &ws, float *images,
-                       int32_t *hist, float *amp, int maxa, int dirs_per_block, hipStream_t stream)
+                       int32_t *hist, float *amp, int cap, int dirs_per_block, hipStream_t stream)
 {
     const float2 *W = nullptr;
     AR_TRY(ctx->twiddle_table(nbins, &W));
     const BinConsts bc = bin_consts(radius, nbins);
     const bool debug = hist != nullptr || amp != nullptr;
-    const int waves = sig::waves_for(nbins);
     const int n_tiles = (n_dir + dirs_per_block - 1) / dirs_per_block;
     const int64_t blocks = n_roi * (int64_t)n_tiles;
     AR_CHECK(blocks < (int64_t)INT32_MAX, "too many workgroups (%lld)", (long long)blocks);
-    const size_t lds = sig::lds_for(nbins, waves);
-    sig::PlainFn fn = debug ? sig::plain_kernel<true>(log2i(nbins), maxa) : sig::plain_kernel<false>(log2i(nbins), maxa);
-    fn<<<(unsigned)blocks, waves * 64, lds, stream>>>((const float4 *)rel, offsets, directions, n_dir, dirs_per_block,
-                                                     n_tiles, W, bc, ws, images, hist, amp);
+    AR_CHECK(cap % sig::kStageMult == 0 && cap >= sig::kStageMult && cap <= sig::kStageMax, "bad stage size %d", cap);
+    const size_t lds = sig::lds_for(nbins, cap);
+    sig::PlainFn fn = debug ? sig::plain_kernel<true>(log2i(nbins)) : sig::plain_kernel<false>(log2i(nbins));
+    AR_TRY(sig::allow_lds(fn, lds));
+    fn<<<(unsigned)blocks, sig::kWaves * 64, lds, stream>>>((const float4 *)rel, offsets, directions, n_dir,
+                                                           dirs_per_block, n_tiles, W, bc, ws, cap, images, hist,
+                                                           amp);
     AR_HIP(hipGetLastError());
     return AR_OK;
 }
@@ -326,8 +397,9 @@ struct ar_plan {
     int64_t max_roi = 0, max_total = 0;
     int32_t n_dir = 0, nbins = 0, n_win = 0;
     // tuned configuration
-    int dpi = 32, maxa = 16, waves = 4, blocks_per_cu = 4;
+    int dpi = 32, cap = 1024, blocks_per_cu = 4, min_waves = 1;
     bool tuned = false;
+    int64_t big = 0;          // largest ROI of the ordered batch
     // queue
     ar::DeviceBuffer order, counter;
     const int64_t *order_for = nullptr;
@@ -339,7 +411,7 @@ struct ar_plan {
         const void *rel, *offsets, *dirs, *images;
         int64_t n_roi;
         float radius;
-        int dpi, maxa, waves, blocks;
+        int dpi, cap, blocks, min_waves;
         ar::WindowSet ws;
     } key;
     bool have_key = false;
@@ -364,6 +436,8 @@ static ar_status plan_order(ar_plan *p, const int64_t *offsets, int64_t n_roi, h
     std::stable_sort(ord.begin(), ord.end(), [&](int32_t a, int32_t b) {
         return off[a + 1] - off[a] > off[b + 1] - off[b];
     });
+    p->big = n_roi > 0 ? off[ord[0] + 1] - off[ord[0]] : 0;
+    if (!p->tuned) p->cap = sig::stage_for(p->big);
     AR_TRY(p->order.reserve(sizeof(int32_t) * n_roi));
     AR_HIP(hipMemcpyAsync(p->order.ptr, ord.data(), sizeof(int32_t) * n_roi, hipMemcpyHostToDevice, stream));
     AR_HIP(hipStreamSynchronize(stream));
@@ -381,14 +455,15 @@ static ar_status plan_launch(ar_plan *p, const float *rel, const int64_t *offset
     const BinConsts bc = bin_consts(radius, p->nbins);
     const int chunks = (p->n_dir + p->dpi - 1) / p->dpi;
     const int64_t n_items = n_roi * (int64_t)chunks;
-    const size_t lds = sig::lds_for(p->nbins, p->waves);
+    const size_t lds = sig::lds_for(p->nbins, p->cap);
     const int blocks = ctx->cu_count * p->blocks_per_cu;
     sig::k_zero_counter<<<1, 1, 0, stream>>>(p->counter.as<unsigned long long>());
     AR_HIP(hipGetLastError());
-    sig::PersFn fn = sig::pers_kernel(log2i(p->nbins), p->maxa);
-    fn<<<blocks, p->waves * 64, lds, stream>>>((const float4 *)rel, offsets, p->order.as<int32_t>(), n_items, chunks,
-                                              p->dpi, directions, p->n_dir, W, bc, ws, images,
-                                              p->counter.as<unsigned long long>());
+    sig::PersFn fn = sig::pers_kernel(log2i(p->nbins), p->min_waves);
+    AR_TRY(sig::allow_lds(fn, lds));
+    fn<<<blocks, sig::kWaves * 64, lds, stream>>>((const float4 *)rel, offsets, p->order.as<int32_t>(), n_items,
+                                                 chunks, p->dpi, directions, p->n_dir, W, bc, ws, p->cap, images,
+                                                 p->counter.as<unsigned long long>());
     AR_HIP(hipGetLastError());
     return AR_OK;
 }
@@ -407,7 +482,7 @@ ar_status araullo_signatures_csr(ar_context *ctx, const float *rel, const int64_
     AR_TRY(ar::make_windows(windows, n_win, nbins, &ws));
     AR_HIP(hipSetDevice(ctx->device));
     return ar::launch_plain(ctx, rel, offsets, n_roi, radius, directions, n_dir, nbins, ws, images, nullptr, nullptr,
-                            16, 256, (hipStream_t)stream);
+                            1024, 256, (hipStream_t)stream);
 }
 
 static ar_status gather_into_ctx(ar_context *ctx, const float *positions, int64_t n_atoms, const float *centres,
@@ -442,12 +517,7 @@ ar_status araullo_signatures(ar_context *ctx, const float *positions, int64_t n_
     AR_HIP(hipStreamSynchronize(s));
     int64_t big = 0;
     for (int64_t r = 0; r < n_roi; ++r) big = std::max(big, off[r + 1] - off[r]);
-    int maxa = 32;
-    for (int m : ar::sig::kMaxaOptions)
-        if ((int64_t)m * 64 >= big) {
-            maxa = m;
-            break;
-        }
+    const int cap = ar::sig::stage_for(big);
     if (roi_counts) {
         std::vector<int32_t> cnt(n_roi);
         for (int64_t r = 0; r < n_roi; ++r) cnt[r] = (int32_t)(off[r + 1] - off[r]);
@@ -455,7 +525,7 @@ ar_status araullo_signatures(ar_context *ctx, const float *positions, int64_t n_
         AR_HIP(hipStreamSynchronize(s));
     }
     return ar::launch_plain(ctx, ctx->s_rel.as<float>(), ctx->g_offsets.as<int64_t>(), n_roi, radius, directions,
-                            n_dir, nbins, ws, images, nullptr, nullptr, maxa, 256, s);
+                            n_dir, nbins, ws, images, nullptr, nullptr, cap, 256, s);
 }
 
 ar_status araullo_sdm(ar_context *ctx, const float *positions, int64_t n_atoms, const float *centres, int64_t n_roi,
@@ -471,7 +541,7 @@ ar_status araullo_sdm(ar_context *ctx, const float *positions, int64_t n_atoms, 
     ar::WindowSet ws;
     memset(&ws, 0, sizeof(ws));
     return ar::launch_plain(ctx, ctx->s_rel.as<float>(), ctx->g_offsets.as<int64_t>(), n_roi, radius, directions,
-                            n_dir, nbins, ws, nullptr, hist, amp, 8, 64, s);
+                            n_dir, nbins, ws, nullptr, hist, amp, 1024, 64, s);
 }
 
 ar_status ar_signature_plan_create(ar_context *ctx, int64_t max_roi, int64_t max_total, int32_t n_dir, int32_t nbins,
@@ -492,7 +562,6 @@ ar_status ar_signature_plan_create(ar_context *ctx, int64_t max_roi, int64_t max
     p->n_dir = n_dir;
     p->nbins = nbins;
     p->n_win = n_win;
-    p->waves = ar::sig::waves_for(nbins);
     ar_status s = p->order.reserve(sizeof(int32_t) * max_roi);
     if (s == AR_OK) s = p->counter.reserve(sizeof(unsigned long long));
     if (s != AR_OK) {
@@ -530,75 +599,88 @@ ar_status ar_signature_plan_tune(ar_plan *p, const float *rel, const int64_t *of
     AR_TRY(plan_check(p, rel, offsets, n_roi, radius, directions, windows, images, &ws));
     AR_HIP(hipSetDevice(p->ctx->device));
     hipStream_t s = (hipStream_t)stream;
+    p->tuned = false;
     AR_TRY(ar::plan_order(p, offsets, n_roi, s));
     hipEvent_t e0, e1;
     AR_HIP(hipEventCreate(&e0));
     AR_HIP(hipEventCreate(&e1));
     float best = INFINITY;
-    int bd = p->dpi, bm = p->maxa, bb = p->blocks_per_cu;
-    const int dpis[] = {8, 16, 32, 64};
-    const int bpcs[] = {2, 4, 8};
-    // register chunks below the largest ROI would stream atoms: only try
-    // chunks that hold it, plus the next smaller one
-    std::vector<int64_t> off(n_roi + 1);
-    AR_HIP(hipMemcpyAsync(off.data(), offsets, sizeof(int64_t) * (n_roi + 1), hipMemcpyDeviceToHost, s));
-    AR_HIP(hipStreamSynchronize(s));
-    int64_t big = 0;
-    for (int64_t r = 0; r < n_roi; ++r) big = std::max(big, off[r + 1] - off[r]);
-    for (int maxa : ar::sig::kMaxaOptions)
+    int bd = p->dpi, bc = p->cap, bb = p->blocks_per_cu, bw = p->min_waves;
+    const int dpis[] = {16, 32, 64, 128};
+    const int bpcs[] = {2, 3, 4, 6};
+    std::vector<int> occs = {1};
+    if (p->nbins <= 1024) occs.push_back(4);
+    // stage sizes: one that holds the largest ROI, and smaller ones that let
+    // more workgroups share a compute unit (larger ROIs are then streamed)
+    std::vector<int> caps = {ar::sig::stage_for(p->big)};
+    for (int c : {2048, 1024})
+        if (c < caps[0]) caps.push_back(c);
+    ar_status st = AR_OK;
+    for (int occ : occs)
+    for (int cap : caps)
         for (int dpi : dpis)
             for (int bpc : bpcs) {
-                if ((int64_t)maxa * 64 * 2 < big) continue;
-                p->maxa = maxa;
-                p->dpi = dpi;
+                if (st != AR_OK) break;
+                p->min_waves = occ;
+                p->cap = cap;
+                p->dpi = std::min(dpi, p->n_dir);
                 p->blocks_per_cu = bpc;
-                AR_TRY(ar::plan_launch(p, rel, offsets, n_roi, radius, directions, ws, images, s));  // warm
-                AR_HIP(hipEventRecord(e0, s));
-                AR_TRY(ar::plan_launch(p, rel, offsets, n_roi, radius, directions, ws, images, s));
-                AR_HIP(hipEventRecord(e1, s));
-                AR_HIP(hipEventSynchronize(e1));
+                st = ar::plan_launch(p, rel, offsets, n_roi, radius, directions, ws, images, s);  // warm
+                if (st == AR_OK && hipEventRecord(e0, s) != hipSuccess) st = ar::fail(AR_EDEVICE, "event record failed");
+                if (st == AR_OK) st = ar::plan_launch(p, rel, offsets, n_roi, radius, directions, ws, images, s);
+                if (st == AR_OK && hipEventRecord(e1, s) != hipSuccess) st = ar::fail(AR_EDEVICE, "event record failed");
+                if (st == AR_OK && hipEventSynchronize(e1) != hipSuccess) st = ar::fail(AR_EDEVICE, "event sync failed");
                 float ms = 0.f;
-                AR_HIP(hipEventElapsedTime(&ms, e0, e1));
-                if (ms < best) {
+                if (st == AR_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) st = ar::fail(AR_EDEVICE, "event time failed");
+                if (st == AR_OK && ms < best) {
                     best = ms;
-                    bd = dpi;
-                    bm = maxa;
+                    bd = p->dpi;
+                    bc = cap;
                     bb = bpc;
+                    bw = occ;
                 }
             }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
+    AR_TRY(st);
     p->dpi = bd;
-    p->maxa = bm;
+    p->cap = bc;
     p->blocks_per_cu = bb;
+    p->min_waves = bw;
     p->tuned = true;
     p->have_key = false;
     return ar::plan_launch(p, rel, offsets, n_roi, radius, directions, ws, images, s);
 }
 
-ar_status ar_signature_plan_set_config(ar_plan *p, int32_t dirs_per_item, int32_t atoms_per_lane,
-                                       int32_t blocks_per_cu)
+ar_status ar_signature_plan_set_config(ar_plan *p, int32_t dirs_per_item, int32_t atoms_per_stage,
+                                       int32_t blocks_per_cu, int32_t min_waves)
 {
     AR_CHECK(p != nullptr, "plan is NULL");
     AR_CHECK(dirs_per_item >= 1 && dirs_per_item <= p->n_dir, "dirs_per_item must be in [1, n_dir]");
-    AR_CHECK(atoms_per_lane == 8 || atoms_per_lane == 16 || atoms_per_lane == 24 || atoms_per_lane == 32,
-             "atoms_per_lane must be 8, 16, 24 or 32");
+    AR_CHECK(atoms_per_stage >= ar::sig::kStageMult && atoms_per_stage <= ar::sig::kStageMax &&
+                 atoms_per_stage % ar::sig::kStageMult == 0,
+             "atoms_per_stage must be a multiple of %d in [%d, %d]", ar::sig::kStageMult, ar::sig::kStageMult,
+             ar::sig::kStageMax);
     AR_CHECK(blocks_per_cu >= 1 && blocks_per_cu <= 16, "blocks_per_cu must be in [1, 16]");
+    AR_CHECK(min_waves == 1 || (min_waves == 4 && p->nbins <= 1024),
+             "min_waves must be 1, or 4 for nbins <= 1024");
+    p->min_waves = min_waves;
     p->dpi = dirs_per_item;
-    p->maxa = atoms_per_lane;
+    p->cap = atoms_per_stage;
     p->blocks_per_cu = blocks_per_cu;
     p->tuned = true;
     p->have_key = false;
     return AR_OK;
 }
 
-ar_status ar_signature_plan_config(const ar_plan *p, int32_t *dirs_per_item, int32_t *atoms_per_lane,
-                                   int32_t *waves_per_group)
+ar_status ar_signature_plan_config(const ar_plan *p, int32_t *dirs_per_item, int32_t *atoms_per_stage,
+                                   int32_t *blocks_per_cu, int32_t *min_waves)
 {
     AR_CHECK(p != nullptr, "plan is NULL");
     if (dirs_per_item) *dirs_per_item = p->dpi;
-    if (atoms_per_lane) *atoms_per_lane = p->maxa;
-    if (waves_per_group) *waves_per_group = p->waves;
+    if (atoms_per_stage) *atoms_per_stage = p->cap;
+    if (blocks_per_cu) *blocks_per_cu = p->blocks_per_cu;
+    if (min_waves) *min_waves = p->min_waves;
     return AR_OK;
 }
 
@@ -621,8 +703,8 @@ ar_status ar_signature_plan_run(ar_plan *p, const float *rel, const int64_t *off
     k.n_roi = n_roi;
     k.radius = radius;
     k.dpi = p->dpi;
-    k.maxa = p->maxa;
-    k.waves = p->waves;
+    k.cap = p->cap;
+    k.min_waves = p->min_waves;
     k.blocks = p->blocks_per_cu;
     k.ws = ws;
     if (!p->have_key || memcmp(&k, &p->key, sizeof(k)) != 0) {

@@ -37,8 +37,8 @@ _SIGS = {
     "ar_signature_plan_create": ([vp, i64, i64, i32, i32, i32, P(vp)], ctypes.c_int),
     "ar_signature_plan_destroy": ([vp], ctypes.c_int),
     "ar_signature_plan_tune": ([vp, vp, vp, i64, f32, vp, vp, vp, vp], ctypes.c_int),
-    "ar_signature_plan_config": ([vp, P(i32), P(i32), P(i32)], ctypes.c_int),
-    "ar_signature_plan_set_config": ([vp, i32, i32, i32], ctypes.c_int),
+    "ar_signature_plan_config": ([vp, P(i32), P(i32), P(i32), P(i32)], ctypes.c_int),
+    "ar_signature_plan_set_config": ([vp, i32, i32, i32, i32], ctypes.c_int),
     "ar_signature_plan_run": ([vp, vp, vp, i64, f32, vp, vp, vp, i32, vp], ctypes.c_int),
     "ar_library_create": ([vp, vp, i64, i32, i32, vp, P(vp)], ctypes.c_int),
     "ar_library_destroy": ([vp], ctypes.c_int),
@@ -231,13 +231,16 @@ class SignaturePlan:
         _call("ar_signature_plan_tune", self.handle, r, o, n, radius, dp, w.data_ptr(), ip, _stream(self.ctx.device))
         return images
 
-    def config(self) -> Tuple[int, int, int]:
-        a, b, c = i32(), i32(), i32()
-        _call("ar_signature_plan_config", self.handle, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c))
-        return a.value, b.value, c.value
+    def config(self) -> Tuple[int, int, int, int]:
+        """(dirs_per_item, atoms_per_stage, blocks_per_cu, min_waves)."""
+        a, b, c, d = i32(), i32(), i32(), i32()
+        _call("ar_signature_plan_config", self.handle, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c),
+              ctypes.byref(d))
+        return a.value, b.value, c.value, d.value
 
-    def set_config(self, dirs_per_item: int, atoms_per_lane: int, blocks_per_cu: int):
-        _call("ar_signature_plan_set_config", self.handle, dirs_per_item, atoms_per_lane, blocks_per_cu)
+    def set_config(self, dirs_per_item: int, atoms_per_stage: int, blocks_per_cu: int, min_waves: int = 1):
+        _call("ar_signature_plan_set_config", self.handle, dirs_per_item, atoms_per_stage, blocks_per_cu,
+              min_waves)
 
     def run(self, rel, offsets, radius, directions, windows, out=None, use_graph: bool = True):
         images = self._out(offsets, out)

@@ -42,8 +42,8 @@ def test_plan_equals_plain_and_replays(nat, ctx, cfg3):
     assert torch.equal(img, plain)
     tuned = plan.tune(rel, off, s.radius, dirs, w)
     assert torch.equal(tuned, plain)
-    dpi, maxa, waves = plan.config()
-    assert dpi >= 1 and maxa in (8, 16, 24, 32) and waves >= 1
+    dpi, cap, bpc, occ = plan.config()
+    assert dpi >= 1 and cap % 256 == 0 and 256 <= cap <= 4096 and bpc >= 1 and occ in (1, 4)
     out = torch.empty_like(plain)
     for rep in range(3):
         out.fill_(-1.0)
@@ -52,6 +52,23 @@ def test_plan_equals_plain_and_replays(nat, ctx, cfg3):
         assert torch.equal(out, plain), rep
         # unrelated eager work between replays
         _ = (plain * 2.0).sum().item()
+
+
+@pytest.mark.parametrize("dpi,cap,bpc,occ", [(7, 256, 2, 1), (64, 512, 4, 4), (33, 1024, 3, 1), (128, 4096, 1, 4)])
+def test_every_plan_configuration_is_bit_identical(nat, ctx, cfg3, dpi, cap, bpc, occ):
+    """Stages smaller than the largest ROI stream atoms in chunks (workgroup
+    barriers per refill); direction chunks that do not divide the mesh leave
+    idle wavefronts in the last round.  Histograms are exact and the
+    transform code is shared, so every configuration writes the same bits."""
+    s, pos, cen, dirs, off, rel, w = cfg3
+    plain = nat.araullo_signatures_csr(ctx, rel, off, s.radius, dirs, s.nbins, w)
+    plan = nat.SignaturePlan(ctx, len(s.centres), int(off[-1]), len(s.directions), s.nbins, len(w))
+    plan.set_config(dpi, cap, bpc, occ)
+    assert plan.config() == (dpi, cap, bpc, occ)
+    for graph in (False, True):
+        img = plan.run(rel, off, s.radius, dirs, w, use_graph=graph)
+        torch.cuda.synchronize()
+        assert torch.equal(img, plain), graph
 
 
 def test_plan_sampled_oracle_parity(nat, ctx, orc, cfg3):
@@ -74,3 +91,6 @@ def test_plan_argument_checks(nat, ctx, cfg3):
     plan = nat.SignaturePlan(ctx, 10, 100, len(s.directions), s.nbins, len(w))
     with pytest.raises(nat.AraulloError):
         plan.run(rel, off, s.radius, dirs, w, use_graph=False)      # n_roi above the plan capacity
+    for bad in [(0, 256, 4, 1), (32, 300, 4, 1), (32, 8192, 4, 1), (32, 256, 0, 1), (32, 256, 4, 2)]:
+        with pytest.raises(nat.AraulloError):
+            plan.set_config(*bad)

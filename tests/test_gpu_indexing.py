@@ -187,12 +187,12 @@ def test_every_correlation_tile_gives_identical_results(nat, ctx, tile):
     S, L, truth = synth.planted_images(333, 1500, 4, 300, seed=21)
     lib = nat.Library(ctx, dev(L))
     nat.ar_index_set_tile(ctx, 2, 2, 64)
-    ref = nat.index_orientations_ex(ctx, dev(S), lib, 16, 16)
-    nat.ar_index_set_tile(ctx, *tile)
     try:
+        ref = nat.index_orientations_ex(ctx, dev(S), lib, 16, 16)
+        nat.ar_index_set_tile(ctx, *tile)
         got = nat.index_orientations_ex(ctx, dev(S), lib, 16, 16)
     finally:
-        nat.ar_index_set_tile(ctx, 2, 2, 64)
+        nat.ar_index_set_tile(ctx, 2, 4, 64)
     for a, b in zip(ref, got):
         assert torch.equal(a, b)
     assert np.array_equal(got[0][:, 0].cpu().numpy(), truth)
