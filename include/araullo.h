@@ -313,6 +313,34 @@ ar_status ar_refine_orientations(ar_context *ctx, const float *rel, const int64_
                                  const float *targets, int32_t n_phase, int32_t n_freq,
                                  int32_t steps, float a0, float *score, void *stream);
 
+/*
+ * Measured peak rates of the units the kernels are bound by, the
+ * denominators of their roofline fractions (not part of the method).  Each
+ * probe is a fixed loop on eight workgroups per compute unit, timed on the
+ * null stream after one warm-up launch:
+ *   out[AR_PEAK_HBM_BYTES]        device copy, bytes read + written per second (1 GiB each way)
+ *   out[AR_PEAK_LDS_BYTES]        16-byte LDS reads without bank conflicts, bytes per second
+ *   out[AR_PEAK_LDS_ATOMICS]      LDS integer atomics without return, one bank per lane, per second
+ *   out[AR_PEAK_FP32_FMA_FLOPS]   non-packed FP32 FMA, flop per second (FMA = 2)
+ *   out[AR_PEAK_SIN]              v_sin_f32 per second
+ *   out[AR_PEAK_SIN_OVERLAP]      time of 16 FMA chains / time of the same with 4 sin chains beside
+ *                                 them (1 = the transcendental unit runs beside the FMA pipeline)
+ *   out[AR_PEAK_BF16_MFMA_FLOPS]  v_mfma_f32_32x32x16_bf16, flop per second
+ *   out    host double [n_out], n_out >= AR_PEAK_COUNT
+ * Allocates 2 GiB of device memory for the copy and frees it.  Synchronises.
+ */
+enum {
+    AR_PEAK_HBM_BYTES = 0,
+    AR_PEAK_LDS_BYTES = 1,
+    AR_PEAK_LDS_ATOMICS = 2,
+    AR_PEAK_FP32_FMA_FLOPS = 3,
+    AR_PEAK_SIN = 4,
+    AR_PEAK_SIN_OVERLAP = 5,
+    AR_PEAK_BF16_MFMA_FLOPS = 6,
+    AR_PEAK_COUNT = 7
+};
+ar_status ar_measure_peaks(ar_context *ctx, double *out, int32_t n_out);
+
 #ifdef __cplusplus
 }
 #endif

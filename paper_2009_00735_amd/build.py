@@ -21,7 +21,8 @@ BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libaraullo.so")
 ARCH = os.environ.get("ARAULLO_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["context.hip", "gather.hip", "signatures.hip", "indexing.hip", "orientation.hip", "refine.hip"]
+SOURCES = ["context.hip", "gather.hip", "signatures.hip", "indexing.hip", "orientation.hip", "refine.hip",
+           "peaks.hip"]
 
 COMMON = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",

@@ -52,6 +52,7 @@ _SIGS = {
     "ar_sf_amplitudes": ([vp, vp, vp, i64, vp, vp, vp, i32, vp, i32, i32, vp, vp], ctypes.c_int),
     "ar_refine_orientations": ([vp, vp, vp, i64, vp, vp, vp, i32, vp, vp, i32, i32, i32, f32, vp, vp],
                                ctypes.c_int),
+    "ar_measure_peaks": ([vp, P(ctypes.c_double), i32], ctypes.c_int),
 }
 for _name, (_args, _res) in _SIGS.items():
     _fn = getattr(_L, _name)
@@ -392,3 +393,14 @@ def ar_refine_orientations(ctx: Context, rel, offsets, quats, phase, directions,
           _dev(freqs, torch.float32, d, "freqs"), _dev(targets, torch.float32, d, "targets"), n_phase, n_freq, steps,
           a0, score.data_ptr(), _stream(d))
     return score
+
+
+PEAK_NAMES = ("hbm_bytes_per_s", "lds_bytes_per_s", "lds_atomics_per_s", "fp32_fma_flop_per_s", "sin_per_s",
+              "sin_beside_fma_time_ratio", "bf16_mfma_flop_per_s")
+
+
+def ar_measure_peaks(ctx: Context) -> dict:
+    """Measured peak rates (see include/araullo.h), keyed by PEAK_NAMES."""
+    out = (ctypes.c_double * len(PEAK_NAMES))()
+    _call("ar_measure_peaks", ctx.handle, out, len(PEAK_NAMES))
+    return dict(zip(PEAK_NAMES, list(out)))
