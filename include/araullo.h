@@ -223,11 +223,13 @@ ar_status index_orientations_ex(ar_context *ctx, const float *images, int64_t n_
                                 const ar_library *lib, int32_t k, int32_t cand, int32_t *top_idx,
                                 float *top_score, int32_t *cand_idx, void *stream);
 
-/* Correlation tile of this context's index calls: each of the 4 wavefronts
- * of a workgroup owns wtm x wtn MFMA tiles of 32x32 (workgroup tile
- * 64 wtm x 64 wtn), K advances bk per step.  Supported: 2x2x64, 2x4x32,
- * 4x2x32, 4x4x32, 2x4x64 (default).  Results do not depend on the tile. */
-ar_status ar_index_set_tile(ar_context *ctx, int32_t wtm, int32_t wtn, int32_t bk);
+/* Correlation tile of this context's index calls: a workgroup of `waves`
+ * wavefronts (4 as a 2x2 grid, 8 as 2x4), each owning wtm x wtn MFMA tiles of
+ * 32x32 (workgroup tile 64 wtm x 32 wtn (waves/2)); K advances bk = 32 per
+ * step.  Supported (waves, wtm, wtn, bk): (4,2,2,32) (4,2,4,32) (4,4,2,32)
+ * (8,2,2,32) (8,4,2,32); default (8,4,2,32), a 256 x 256 tile.  Results do not depend on the
+ * tile: every score accumulates K in the same order. */
+ar_status ar_index_set_tile(ar_context *ctx, int32_t waves, int32_t wtm, int32_t wtn, int32_t bk);
 
 /*
  * Disorientation angle in degrees under cubic symmetry (supplement,

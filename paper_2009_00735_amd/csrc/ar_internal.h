@@ -78,7 +78,7 @@ struct ar_context {
     // gathered CSR used by the position-taking signature entry points
     ar::DeviceBuffer s_rel;
     // correlation tile: per-wave 32x32 MFMA tiles (wtm x wtn) and K step
-    int corr_wtm = 2, corr_wtn = 4, corr_bk = 64;
+    int corr_waves = 8, corr_wtm = 4, corr_wtn = 2, corr_bk = 32;
     // indexing workspace
     ar::DeviceBuffer i_bf16, i_inv, i_cand_idx, i_cand_score, i_merge_idx;
     // refinement workspace

@@ -33,8 +33,7 @@ namespace idx {
 typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
 typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16;
 
-constexpr int kPadM = 256, kPadN = 256, kPadK = 64;   // multiples of every tile's BM, BN, BK
-constexpr int kThreads = 256;
+constexpr int kPadM = 256, kPadN = 256, kPadK = 64;   // multiples of every tile's BM, BN and K step
 
 __device__ __forceinline__ uint16_t f32_to_bf16_rne(float x)
 {
@@ -135,47 +134,117 @@ struct TopList {
 };
 
 // ------------------------------------------------------------ correlation
-// Workgroup: 4 waves as 2x2; each wave owns WTM x WTN MFMA tiles of 32x32
-// (v_mfma_f32_32x32x16_bf16), so the workgroup tile is BM x BN =
-// (64 WTM) x (64 WTN).  K advances BK bf16 per step through LDS rows padded
-// by 16 bytes (conflict-free 16-byte fragment reads for 16 consecutive rows),
-// double-buffered (one barrier per step) when DBUF.
+// Workgroup: WGM x WGN waves (2x2 or 2x4); each wave owns WTM x WTN MFMA
+// tiles of 32x32 (v_mfma_f32_32x32x16_bf16), so the workgroup tile is
+// BM x BN = (32 WTM WGM) x (32 WTN WGN).  K advances 32 bf16 per step.
+//
+// Operands go straight from global memory into LDS (global_load_lds_dwordx4:
+// each wave instruction fills 1 KB = 16 rows of 64 bytes, no registers on the
+// way) through a ring of NSTAGE stages, NSTAGE - 1 steps in flight.  Rows are
+// unpadded; the 16-byte chunk c of row r sits at chunk c ^ ((r >> 2) & 3),
+// which makes the fragment reads (32 consecutive rows, one chunk) free of
+// bank conflicts.  One workgroup barrier per step: after it every wave's
+// loads of the step have landed and every wave has finished the previous
+// step, whose stage is then refilled.
 // grid.x = m_blocks * n_seg.  out_s/out_i: [M_pad][n_seg * TPR][CAND] where
-// TPR = 256 / BM threads share a row in the epilogue.
-template <int WTM, int WTN, int BK> struct CorrShape {
-    static constexpr int BM = 64 * WTM, BN = 64 * WTN;
-    static constexpr int LD = BK + 8;                         // LDS row, bf16
-    static constexpr int TPR = kThreads / BM;                  // epilogue threads per row
-    static constexpr int CH_A = BM * BK / 8 / kThreads;        // 16-byte chunks per thread
-    static constexpr int CH_B = BN * BK / 8 / kThreads;
-    static constexpr int CPR = BK / 8;                         // chunks per row
-    static constexpr size_t lds(bool dbuf)
+// TPR = THREADS / BM threads share a row in the epilogue.
+constexpr int kBK = 32;        // bf16 per K step
+constexpr int kStages = 4;     // LDS ring depth
+
+template <int WGM, int WGN, int WTM, int WTN> struct CorrShape {
+    static constexpr int THREADS = 64 * WGM * WGN, WAVES = WGM * WGN;
+    static constexpr int BM = 32 * WTM * WGM, BN = 32 * WTN * WGN;
+    static constexpr int ROWB = kBK * 2;                       // bytes per LDS row
+    static constexpr int A_BYTES = BM * ROWB, STAGE = (BM + BN) * ROWB;
+    static constexpr int A_BLK = BM / 16, B_BLK = BN / 16;     // 1-KB blocks per stage
+    static constexpr int BLK_PER_WAVE = (A_BLK + B_BLK) / WAVES;
+    static constexpr int TPR = THREADS / BM;                   // epilogue threads per row
+    static_assert((A_BLK + B_BLK) % WAVES == 0, "stage blocks must split evenly over the waves");
+    static constexpr size_t lds()
     {
-        const size_t ab = (size_t)(dbuf ? 2 : 1) * (BM + BN) * LD * sizeof(uint16_t);
+        const size_t ab = (size_t)kStages * STAGE;
         const size_t c = (size_t)BM * 65 * sizeof(float);
         return ab > c ? ab : c;
     }
 };
 
-template <int WTM, int WTN, int BK, int CAND, bool DBUF>
-__global__ __launch_bounds__(kThreads) void k_corr_topk(const uint16_t *__restrict__ A, const uint16_t *__restrict__ B,
+typedef __attribute__((address_space(3))) void lds_void;
+
+// s_waitcnt vmcnt(N): this wave's vector-memory operations (here the LDS
+// fills) beyond the newest N have completed.
+template <int N> __device__ __forceinline__ void wait_vmcnt()
+{
+    static_assert(N >= 0 && N < 64, "vmcnt range");
+    asm volatile("s_waitcnt vmcnt(%0)" ::"n"(N) : "memory");
+}
+
+// Workgroup barrier without a memory fence (a fence would wait for every
+// outstanding LDS fill); ordering of the fills is by wait_vmcnt.
+__device__ __forceinline__ void barrier_only()
+{
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+}
+
+// One K step of MFMAs from a stage.  Per slice of 16 along K a wave needs WTM
+// A and WTN B fragments (8 bf16 per lane: row lane % 32, chunk
+// 2 * slice + lane / 32); the second slice's fragments are read while the
+// first slice's MFMAs run.
+template <int WTM, int WTN>
+__device__ __forceinline__ void mfma_frags(const bf16x8 (&fa)[WTM], const bf16x8 (&fb)[WTN], f32x16 (&acc)[WTM][WTN])
+{
+#pragma unroll
+    for (int a = 0; a < WTM; ++a)
+#pragma unroll
+        for (int c = 0; c < WTN; ++c)
+            acc[a][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[a], fb[c], acc[a][c], 0, 0, 0);
+}
+
+template <int WTM, int WTN>
+__device__ __forceinline__ void read_frags(const unsigned char *a_rows, const unsigned char *b_rows, int off,
+                                           bf16x8 (&fa)[WTM], bf16x8 (&fb)[WTN])
+{
+#pragma unroll
+    for (int a = 0; a < WTM; ++a) fa[a] = *reinterpret_cast<const bf16x8 *>(a_rows + a * 32 * 64 + off);
+#pragma unroll
+    for (int c = 0; c < WTN; ++c) fb[c] = *reinterpret_cast<const bf16x8 *>(b_rows + c * 32 * 64 + off);
+}
+
+// Fill stage `stage` with K step `step`: this wave's NB blocks (block
+// wave + j * WAVES; A blocks first, then B), 16 rows each.
+template <class S>
+__device__ __forceinline__ void fill_stage(unsigned char *smem, const uint16_t *__restrict__ A,
+                                           const uint16_t *__restrict__ B, int64_t m0, int64_t n0, int64_t Kp, int wave,
+                                           int64_t lane_off, int step, int stage)
+{
+    unsigned char *st = smem + (size_t)stage * S::STAGE;
+#pragma unroll
+    for (int j = 0; j < S::BLK_PER_WAVE; ++j) {
+        const int blk = wave + j * S::WAVES;
+        const uint16_t *base = blk < S::A_BLK ? A + (m0 + 16 * (int64_t)blk) * Kp
+                                              : B + (n0 + 16 * (int64_t)(blk - S::A_BLK)) * Kp;
+        __builtin_amdgcn_global_load_lds(base + lane_off + (int64_t)step * kBK, (lds_void *)(st + blk * 1024), 16, 0, 0);
+    }
+}
+
+template <int WGM, int WGN, int WTM, int WTN, int CAND>
+__global__ __launch_bounds__(64 * WGM * WGN) void k_corr_topk(const uint16_t *__restrict__ A, const uint16_t *__restrict__ B,
                                                         const float *__restrict__ norm2, int64_t Kp, int m_blocks,
                                                         int n_tiles, int tiles_per_seg, int n_seg,
                                                         float *__restrict__ out_s, int32_t *__restrict__ out_i)
 {
-    using S = CorrShape<WTM, WTN, BK>;
-    constexpr int BM = S::BM, BN = S::BN, LD = S::LD, TPR = S::TPR;
-    constexpr int NBUF = DBUF ? 2 : 1;
-    static_assert(TPR >= 1 && S::CH_A >= 1 && S::CH_B >= 1, "tile too small for 256 threads");
+    using S = CorrShape<WGM, WGN, WTM, WTN>;
+    constexpr int BM = S::BM, BN = S::BN, TPR = S::TPR, NB = S::BLK_PER_WAVE;
+    static_assert(TPR >= 1 && S::THREADS % BM == 0, "tile too small for the workgroup");
+    static_assert((BN / WGN) % 64 == 0, "each wave must own whole 64-column epilogue passes");
     extern __shared__ __align__(16) unsigned char smem[];
-    uint16_t *As = reinterpret_cast<uint16_t *>(smem);                 // [NBUF][BM][LD]
-    uint16_t *Bs = As + NBUF * BM * LD;                                // [NBUF][BN][LD]
-    float *Cs = reinterpret_cast<float *>(smem);                       // [BM][65], aliases As/Bs
+    float *Cs = reinterpret_cast<float *>(smem);                       // [BM][65], aliases the stages
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
-    const int wave = tid >> 6;
-    const int wm = wave & 1, wn = wave >> 1;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int wm = wave % WGM, wn = wave / WGM;
     // XCD-aware ordering: workgroup ids are dealt round-robin to the 8 XCDs;
     // map them so that each XCD walks a contiguous range of (m_block, seg)
     // (segment-major), i.e. its resident workgroups share library segments.
@@ -192,13 +261,23 @@ __global__ __launch_bounds__(kThreads) void k_corr_topk(const uint16_t *__restri
     const int t0 = seg * tiles_per_seg;
     const int t1 = min(t0 + tiles_per_seg, n_tiles);
 
+    // fill side: wave-block j of a stage is block wave + j * WAVES (A blocks
+    // first, then B); lane i loads row 16 * blk + i / 4, logical chunk
+    // (i % 4) ^ ((i / 16) % 4), and lands at byte 16 i of the block
+    const int64_t lane_off = (int64_t)(lane >> 2) * Kp + 8 * ((lane & 3) ^ ((lane >> 4) & 3));
+    // read side: fragment row (lane % 32) of every 32-row group, chunk
+    // 2 * slice + lane / 32 stored at chunk ^ ((lane >> 2) & 3)
+    const int r_x = (lane >> 2) & 3;
+    const int r_off0 = (lane & 31) * 64 + 16 * ((lane >> 5) ^ r_x);
+    const int r_off1 = (lane & 31) * 64 + 16 * ((2 + (lane >> 5)) ^ r_x);
+
     // epilogue ownership: thread -> (row, part of each 64-column pass)
     const int e_row = tid % BM;
     const int e_part = tid / BM;
     TopList<CAND> top;
     top.init();
 
-    const int KT = (int)(Kp / BK);
+    const int KT = (int)(Kp / kBK);
     for (int nt = t0; nt < t1; ++nt) {
         const int64_t n0 = (int64_t)nt * BN;
         f32x16 acc[WTM][WTN];
@@ -209,93 +288,35 @@ __global__ __launch_bounds__(kThreads) void k_corr_topk(const uint16_t *__restri
 #pragma unroll
                 for (int r = 0; r < 16; ++r) acc[a][c][r] = 0.0f;
 
-        // global -> register staging in named registers (no private arrays)
-        uint4 ra0, ra1, ra2, ra3, ra4, ra5, ra6, ra7, rb0, rb1, rb2, rb3, rb4, rb5, rb6, rb7;
-        static_assert(S::CH_A <= 8 && S::CH_B <= 8, "staging holds at most 8 chunks per operand");
-#define AR_GLOAD(kt_)                                                                               \
-    do {                                                                                            \
-        const int64_t k0_ = (int64_t)(kt_) * BK;                                                    \
-        if constexpr (0 < S::CH_A) ra0 = *reinterpret_cast<const uint4 *>(A + (size_t)(m0 + (tid + 0 * kThreads) / S::CPR) * Kp + k0_ + ((tid + 0 * kThreads) % S::CPR) * 8); \
-        if constexpr (1 < S::CH_A) ra1 = *reinterpret_cast<const uint4 *>(A + (size_t)(m0 + (tid + 1 * kThreads) / S::CPR) * Kp + k0_ + ((tid + 1 * kThreads) % S::CPR) * 8); \
-        if constexpr (2 < S::CH_A) ra2 = *reinterpret_cast<const uint4 *>(A + (size_t)(m0 + (tid + 2 * kThreads) / S::CPR) * Kp + k0_ + ((tid + 2 * kThreads) % S::CPR) * 8); \
-        if constexpr (3 < S::CH_A) ra3 = *reinterpret_cast<const uint4 *>(A + (size_t)(m0 + (tid + 3 * kThreads) / S::CPR) * Kp + k0_ + ((tid + 3 * kThreads) % S::CPR) * 8); \
-        if constexpr (4 < S::CH_A) ra4 = *reinterpret_cast<const uint4 *>(A + (size_t)(m0 + (tid + 4 * kThreads) / S::CPR) * Kp + k0_ + ((tid + 4 * kThreads) % S::CPR) * 8); \
-        if constexpr (5 < S::CH_A) ra5 = *reinterpret_cast<const uint4 *>(A + (size_t)(m0 + (tid + 5 * kThreads) / S::CPR) * Kp + k0_ + ((tid + 5 * kThreads) % S::CPR) * 8); \
-        if constexpr (6 < S::CH_A) ra6 = *reinterpret_cast<const uint4 *>(A + (size_t)(m0 + (tid + 6 * kThreads) / S::CPR) * Kp + k0_ + ((tid + 6 * kThreads) % S::CPR) * 8); \
-        if constexpr (7 < S::CH_A) ra7 = *reinterpret_cast<const uint4 *>(A + (size_t)(m0 + (tid + 7 * kThreads) / S::CPR) * Kp + k0_ + ((tid + 7 * kThreads) % S::CPR) * 8); \
-        if constexpr (0 < S::CH_B) rb0 = *reinterpret_cast<const uint4 *>(B + (size_t)(n0 + (tid + 0 * kThreads) / S::CPR) * Kp + k0_ + ((tid + 0 * kThreads) % S::CPR) * 8); \
-        if constexpr (1 < S::CH_B) rb1 = *reinterpret_cast<const uint4 *>(B + (size_t)(n0 + (tid + 1 * kThreads) / S::CPR) * Kp + k0_ + ((tid + 1 * kThreads) % S::CPR) * 8); \
-        if constexpr (2 < S::CH_B) rb2 = *reinterpret_cast<const uint4 *>(B + (size_t)(n0 + (tid + 2 * kThreads) / S::CPR) * Kp + k0_ + ((tid + 2 * kThreads) % S::CPR) * 8); \
-        if constexpr (3 < S::CH_B) rb3 = *reinterpret_cast<const uint4 *>(B + (size_t)(n0 + (tid + 3 * kThreads) / S::CPR) * Kp + k0_ + ((tid + 3 * kThreads) % S::CPR) * 8); \
-        if constexpr (4 < S::CH_B) rb4 = *reinterpret_cast<const uint4 *>(B + (size_t)(n0 + (tid + 4 * kThreads) / S::CPR) * Kp + k0_ + ((tid + 4 * kThreads) % S::CPR) * 8); \
-        if constexpr (5 < S::CH_B) rb5 = *reinterpret_cast<const uint4 *>(B + (size_t)(n0 + (tid + 5 * kThreads) / S::CPR) * Kp + k0_ + ((tid + 5 * kThreads) % S::CPR) * 8); \
-        if constexpr (6 < S::CH_B) rb6 = *reinterpret_cast<const uint4 *>(B + (size_t)(n0 + (tid + 6 * kThreads) / S::CPR) * Kp + k0_ + ((tid + 6 * kThreads) % S::CPR) * 8); \
-        if constexpr (7 < S::CH_B) rb7 = *reinterpret_cast<const uint4 *>(B + (size_t)(n0 + (tid + 7 * kThreads) / S::CPR) * Kp + k0_ + ((tid + 7 * kThreads) % S::CPR) * 8); \
-    } while (0)
-#define AR_SSTORE(buf_)                                                                             \
-    do {                                                                                            \
-        if constexpr (0 < S::CH_A) *reinterpret_cast<uint4 *>(As + (size_t)(buf_) * BM * LD + ((tid + 0 * kThreads) / S::CPR) * LD + ((tid + 0 * kThreads) % S::CPR) * 8) = ra0; \
-        if constexpr (1 < S::CH_A) *reinterpret_cast<uint4 *>(As + (size_t)(buf_) * BM * LD + ((tid + 1 * kThreads) / S::CPR) * LD + ((tid + 1 * kThreads) % S::CPR) * 8) = ra1; \
-        if constexpr (2 < S::CH_A) *reinterpret_cast<uint4 *>(As + (size_t)(buf_) * BM * LD + ((tid + 2 * kThreads) / S::CPR) * LD + ((tid + 2 * kThreads) % S::CPR) * 8) = ra2; \
-        if constexpr (3 < S::CH_A) *reinterpret_cast<uint4 *>(As + (size_t)(buf_) * BM * LD + ((tid + 3 * kThreads) / S::CPR) * LD + ((tid + 3 * kThreads) % S::CPR) * 8) = ra3; \
-        if constexpr (4 < S::CH_A) *reinterpret_cast<uint4 *>(As + (size_t)(buf_) * BM * LD + ((tid + 4 * kThreads) / S::CPR) * LD + ((tid + 4 * kThreads) % S::CPR) * 8) = ra4; \
-        if constexpr (5 < S::CH_A) *reinterpret_cast<uint4 *>(As + (size_t)(buf_) * BM * LD + ((tid + 5 * kThreads) / S::CPR) * LD + ((tid + 5 * kThreads) % S::CPR) * 8) = ra5; \
-        if constexpr (6 < S::CH_A) *reinterpret_cast<uint4 *>(As + (size_t)(buf_) * BM * LD + ((tid + 6 * kThreads) / S::CPR) * LD + ((tid + 6 * kThreads) % S::CPR) * 8) = ra6; \
-        if constexpr (7 < S::CH_A) *reinterpret_cast<uint4 *>(As + (size_t)(buf_) * BM * LD + ((tid + 7 * kThreads) / S::CPR) * LD + ((tid + 7 * kThreads) % S::CPR) * 8) = ra7; \
-        if constexpr (0 < S::CH_B) *reinterpret_cast<uint4 *>(Bs + (size_t)(buf_) * BN * LD + ((tid + 0 * kThreads) / S::CPR) * LD + ((tid + 0 * kThreads) % S::CPR) * 8) = rb0; \
-        if constexpr (1 < S::CH_B) *reinterpret_cast<uint4 *>(Bs + (size_t)(buf_) * BN * LD + ((tid + 1 * kThreads) / S::CPR) * LD + ((tid + 1 * kThreads) % S::CPR) * 8) = rb1; \
-        if constexpr (2 < S::CH_B) *reinterpret_cast<uint4 *>(Bs + (size_t)(buf_) * BN * LD + ((tid + 2 * kThreads) / S::CPR) * LD + ((tid + 2 * kThreads) % S::CPR) * 8) = rb2; \
-        if constexpr (3 < S::CH_B) *reinterpret_cast<uint4 *>(Bs + (size_t)(buf_) * BN * LD + ((tid + 3 * kThreads) / S::CPR) * LD + ((tid + 3 * kThreads) % S::CPR) * 8) = rb3; \
-        if constexpr (4 < S::CH_B) *reinterpret_cast<uint4 *>(Bs + (size_t)(buf_) * BN * LD + ((tid + 4 * kThreads) / S::CPR) * LD + ((tid + 4 * kThreads) % S::CPR) * 8) = rb4; \
-        if constexpr (5 < S::CH_B) *reinterpret_cast<uint4 *>(Bs + (size_t)(buf_) * BN * LD + ((tid + 5 * kThreads) / S::CPR) * LD + ((tid + 5 * kThreads) % S::CPR) * 8) = rb5; \
-        if constexpr (6 < S::CH_B) *reinterpret_cast<uint4 *>(Bs + (size_t)(buf_) * BN * LD + ((tid + 6 * kThreads) / S::CPR) * LD + ((tid + 6 * kThreads) % S::CPR) * 8) = rb6; \
-        if constexpr (7 < S::CH_B) *reinterpret_cast<uint4 *>(Bs + (size_t)(buf_) * BN * LD + ((tid + 7 * kThreads) / S::CPR) * LD + ((tid + 7 * kThreads) % S::CPR) * 8) = rb7; \
-    } while (0)
-        AR_GLOAD(0);
-        __syncthreads();   // the previous tile's epilogue read Cs, which aliases As/Bs
-        AR_SSTORE(0);
-        __syncthreads();
+        __syncthreads();   // the previous tile's epilogue read Cs, which aliases the stages
+#pragma unroll
+        for (int p = 0; p < kStages - 1; ++p)
+            if (p < KT) fill_stage<S>(smem, A, B, m0, n0, Kp, wave, lane_off, p, p);
         for (int kt = 0; kt < KT; ++kt) {
-            const int cur = DBUF ? (kt & 1) : 0;
-            if (kt + 1 < KT) AR_GLOAD(kt + 1);
-            const uint16_t *a_s = As + (size_t)cur * BM * LD;
-            const uint16_t *b_s = Bs + (size_t)cur * BN * LD;
-#pragma unroll
-            for (int kk = 0; kk < BK; kk += 16) {
-                bf16x8 fa[WTM], fb[WTN];
-#pragma unroll
-                for (int a = 0; a < WTM; ++a) {
-                    const int row = wm * (BM / 2) + a * 32 + (lane & 31);
-                    fa[a] = *reinterpret_cast<const bf16x8 *>(a_s + row * LD + kk + (lane >> 5) * 8);
-                }
-#pragma unroll
-                for (int c = 0; c < WTN; ++c) {
-                    const int col = wn * (BN / 2) + c * 32 + (lane & 31);
-                    fb[c] = *reinterpret_cast<const bf16x8 *>(b_s + col * LD + kk + (lane >> 5) * 8);
-                }
-#pragma unroll
-                for (int a = 0; a < WTM; ++a)
-#pragma unroll
-                    for (int c = 0; c < WTN; ++c)
-                        acc[a][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[a], fb[c], acc[a][c], 0, 0, 0);
-            }
-            if (DBUF) {
-                if (kt + 1 < KT) AR_SSTORE(cur ^ 1);
-                __syncthreads();
-            } else if (kt + 1 < KT) {
-                __syncthreads();
-                AR_SSTORE(0);
-                __syncthreads();
-            }
+            // this wave's fills of step kt have landed once at most the fills
+            // of the later steps in flight remain outstanding
+            const int later = min(kStages - 2, KT - 1 - kt);
+            if (later == kStages - 2) wait_vmcnt<(kStages - 2) * NB>();
+            else if (later == 1) wait_vmcnt<NB>();
+            else wait_vmcnt<0>();
+            barrier_only();
+            if (kt + kStages - 1 < KT)
+                fill_stage<S>(smem, A, B, m0, n0, Kp, wave, lane_off, kt + kStages - 1, (kt + kStages - 1) % kStages);
+            const unsigned char *st = smem + (size_t)(kt % kStages) * S::STAGE;
+            const unsigned char *a_rows = st + (wm * (BM / WGM)) * 64;
+            const unsigned char *b_rows = st + S::A_BYTES + (wn * (BN / WGN)) * 64;
+            bf16x8 fa0[WTM], fb0[WTN], fa1[WTM], fb1[WTN];
+            read_frags<WTM, WTN>(a_rows, b_rows, r_off0, fa0, fb0);
+            read_frags<WTM, WTN>(a_rows, b_rows, r_off1, fa1, fb1);
+            mfma_frags<WTM, WTN>(fa0, fb0, acc);
+            mfma_frags<WTM, WTN>(fa1, fb1, acc);
         }
-#undef AR_GLOAD
-#undef AR_SSTORE
         __syncthreads();
         // epilogue in 64-column passes: the waves owning the columns write their
         // scores |L|^2 - 2<S,L> to LDS, then every thread scans its share of a row
 #pragma unroll
         for (int h = 0; h < BN / 64; ++h) {
-            constexpr int WCOLS = BN / 2;                 // columns per wave
+            constexpr int WCOLS = BN / WGN;               // columns per wave
             const int wave_of_pass = (h * 64) / WCOLS;    // compile-time after unrolling
             if (wn == wave_of_pass) {
                 const int c0 = (h * 64 - wave_of_pass * WCOLS) / 32;   // first 32-wide tile of the pass
@@ -308,7 +329,7 @@ __global__ __launch_bounds__(kThreads) void k_corr_topk(const uint16_t *__restri
                             const float nrm = norm2[n0 + h * 64 + col];
 #pragma unroll
                             for (int r = 0; r < 16; ++r) {
-                                const int row = wm * (BM / 2) + a * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+                                const int row = wm * (BM / WGM) + a * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
                                 Cs[row * 65 + col] = fmaf(-2.0f, acc[a][c][r], nrm);
                             }
                         }
@@ -449,61 +470,59 @@ __global__ void k_copy_cand(const int32_t *__restrict__ cand, int64_t n_rows, in
     if (i < n_rows * CAND) out[i] = cand[i];
 }
 
-// Correlation tile configurations (per-wave 32x32 tiles WTM x WTN, K step).
+// Correlation tile configurations: WAVES 4 (2x2 wave grid) or 8 (2x4), per-wave
+// 32x32 tiles WTM x WTN, K step BK.
 struct CorrCfg {
-    int wtm, wtn, bk;
-    int bm() const { return 64 * wtm; }
-    int bn() const { return 64 * wtn; }
+    int waves, wtm, wtn, bk;
+    int wgn() const { return waves == 8 ? 4 : 2; }
+    int bm() const { return 32 * wtm * 2; }
+    int bn() const { return 32 * wtn * wgn(); }
+    int threads() const { return 64 * waves; }
 };
 
-template <int WTM, int WTN, int BK, int CAND>
+template <int WGM, int WGN, int WTM, int WTN, int CAND>
 ar_status launch_corr_t(ar_context *ctx, const uint16_t *A, const ar_library *lib, int m_blocks, int n_tiles,
                         int tiles_per_seg, int n_seg, float *out_s, int32_t *out_i, hipStream_t s)
 {
-    using S = CorrShape<WTM, WTN, BK>;
+    using S = CorrShape<WGM, WGN, WTM, WTN>;
     const unsigned blocks = (unsigned)(m_blocks * n_seg);
-    const size_t big = S::lds(true);
-    static int dbuf_ok = -1;   // per instantiation: can a workgroup get `big` bytes of LDS?
-    if (dbuf_ok < 0) {
-        dbuf_ok = 0;
-        if ((size_t)ctx->lds_per_block >= big &&
-            hipFuncSetAttribute((const void *)k_corr_topk<WTM, WTN, BK, CAND, true>,
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)big) == hipSuccess)
-            dbuf_ok = 1;
-        (void)hipGetLastError();
+    const size_t lds = S::lds();
+    AR_CHECK((size_t)ctx->lds_per_block >= lds, "correlation tile needs %zu bytes of LDS per workgroup", lds);
+    static bool attr_set = false;   // per instantiation
+    if (!attr_set && lds > 65536) {
+        AR_HIP(hipFuncSetAttribute((const void *)k_corr_topk<WGM, WGN, WTM, WTN, CAND>,
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+        attr_set = true;
     }
-    if (dbuf_ok == 1) {
-        k_corr_topk<WTM, WTN, BK, CAND, true><<<blocks, kThreads, big, s>>>(
-            A, lib->bf16.as<uint16_t>(), lib->norm2.as<float>(), lib->Kp, m_blocks, n_tiles, tiles_per_seg, n_seg,
-            out_s, out_i);
-    } else {
-        const size_t small = S::lds(false);
-        if (small > 65536)
-            (void)hipFuncSetAttribute((const void *)k_corr_topk<WTM, WTN, BK, CAND, false>,
-                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)small);
-        k_corr_topk<WTM, WTN, BK, CAND, false><<<blocks, kThreads, small, s>>>(
-            A, lib->bf16.as<uint16_t>(), lib->norm2.as<float>(), lib->Kp, m_blocks, n_tiles, tiles_per_seg, n_seg,
-            out_s, out_i);
-    }
+    k_corr_topk<WGM, WGN, WTM, WTN, CAND><<<blocks, S::THREADS, lds, s>>>(
+        A, lib->bf16.as<uint16_t>(), lib->norm2.as<float>(), lib->Kp, m_blocks, n_tiles, tiles_per_seg, n_seg, out_s,
+        out_i);
     AR_HIP(hipGetLastError());
     return AR_OK;
+}
+
+// (waves, wtm, wtn): 2x2 or 2x4 wave grids, K step 32
+#define AR_CORR_TILES(X) X(4, 2, 2) X(4, 2, 4) X(4, 4, 2) X(8, 2, 2) X(8, 4, 2)
+
+bool corr_tile_supported(int waves, int wtm, int wtn, int bk)
+{
+#define AR_CORR_IS(w_, m_, n_) if (waves == w_ && wtm == m_ && wtn == n_ && bk == kBK) return true;
+    AR_CORR_TILES(AR_CORR_IS)
+#undef AR_CORR_IS
+    return false;
 }
 
 template <int CAND>
 ar_status launch_corr(ar_context *ctx, const CorrCfg &c, const uint16_t *A, const ar_library *lib, int m_blocks,
                       int n_tiles, int tiles_per_seg, int n_seg, float *out_s, int32_t *out_i, hipStream_t s)
 {
-#define AR_CORR_CASE(wm_, wn_, bk_)                                                                   \
-    if (c.wtm == wm_ && c.wtn == wn_ && c.bk == bk_)                                                 \
-        return launch_corr_t<wm_, wn_, bk_, CAND>(ctx, A, lib, m_blocks, n_tiles, tiles_per_seg, n_seg, out_s, \
-                                                  out_i, s);
-    AR_CORR_CASE(2, 2, 64)
-    AR_CORR_CASE(2, 4, 32)
-    AR_CORR_CASE(4, 2, 32)
-    AR_CORR_CASE(4, 4, 32)
-    AR_CORR_CASE(2, 4, 64)
+#define AR_CORR_CASE(w_, m_, n_)                                                                   \
+    if (c.waves == w_ && c.wtm == m_ && c.wtn == n_)                                               \
+        return launch_corr_t<2, (w_) / 2, m_, n_, CAND>(ctx, A, lib, m_blocks, n_tiles, tiles_per_seg, n_seg, out_s, \
+                                                        out_i, s);
+    AR_CORR_TILES(AR_CORR_CASE)
 #undef AR_CORR_CASE
-    return fail(AR_EINVAL, "unsupported correlation tile %dx%dx%d", c.wtm, c.wtn, c.bk);
+    return fail(AR_EINVAL, "unsupported correlation tile %d waves %dx%dx%d", c.waves, c.wtm, c.wtn, c.bk);
 }
 
 int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
@@ -591,16 +610,16 @@ ar_status index_orientations_ex(ar_context *ctx, const float *images, int64_t n_
     AR_CHECK(lib->ctx == ctx, "library belongs to another context");
     AR_HIP(hipSetDevice(ctx->device));
     hipStream_t s = (hipStream_t)stream;
-    const idx::CorrCfg cfg{ctx->corr_wtm, ctx->corr_wtn, ctx->corr_bk};
+    const idx::CorrCfg cfg{ctx->corr_waves, ctx->corr_wtm, ctx->corr_wtn, ctx->corr_bk};
     const int64_t m_pad = idx::round_up(n_roi, idx::kPadM);
     const int m_blocks = (int)(m_pad / cfg.bm());
     const int n_tiles = (int)(lib->n_pad / cfg.bn());
     // segments: enough workgroups to fill the chip several times over
-    const int target = 8 * ctx->cu_count;
+    const int target = (cfg.waves == 8 ? 4 : 8) * ctx->cu_count;
     int n_seg = std::max(1, std::min(n_tiles, (target + m_blocks - 1) / m_blocks));
     const int tiles_per_seg = (n_tiles + n_seg - 1) / n_seg;
     n_seg = (n_tiles + tiles_per_seg - 1) / tiles_per_seg;
-    const int n_lists = n_seg * (idx::kThreads / cfg.bm());
+    const int n_lists = n_seg * (cfg.threads() / cfg.bm());
 
     AR_TRY(ctx->i_bf16.reserve(sizeof(uint16_t) * (size_t)m_pad * lib->Kp));
     AR_TRY(ctx->i_inv.reserve(sizeof(float) * (size_t)n_roi * lib->n_win));
@@ -644,13 +663,12 @@ ar_status index_orientations_ex(ar_context *ctx, const float *images, int64_t n_
     return AR_OK;
 }
 
-ar_status ar_index_set_tile(ar_context *ctx, int32_t wtm, int32_t wtn, int32_t bk)
+ar_status ar_index_set_tile(ar_context *ctx, int32_t waves, int32_t wtm, int32_t wtn, int32_t bk)
 {
     AR_CHECK(ctx != nullptr, "context is NULL");
-    const bool ok = (wtm == 2 && wtn == 2 && bk == 64) || (wtm == 2 && wtn == 4 && bk == 32) ||
-                    (wtm == 4 && wtn == 2 && bk == 32) || (wtm == 4 && wtn == 4 && bk == 32) ||
-                    (wtm == 2 && wtn == 4 && bk == 64);
-    AR_CHECK(ok, "unsupported correlation tile %dx%dx%d", wtm, wtn, bk);
+    AR_CHECK(idx::corr_tile_supported(waves, wtm, wtn, bk), "unsupported correlation tile %d waves %dx%dx%d", waves,
+             wtm, wtn, bk);
+    ctx->corr_waves = waves;
     ctx->corr_wtm = wtm;
     ctx->corr_wtn = wtn;
     ctx->corr_bk = bk;

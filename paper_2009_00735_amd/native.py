@@ -43,7 +43,7 @@ _SIGS = {
     "ar_library_create": ([vp, vp, i64, i32, i32, vp, P(vp)], ctypes.c_int),
     "ar_library_destroy": ([vp], ctypes.c_int),
     "index_orientations": ([vp, vp, i64, vp, i32, vp, vp, vp], ctypes.c_int),
-    "ar_index_set_tile": ([vp, i32, i32, i32], ctypes.c_int),
+    "ar_index_set_tile": ([vp, i32, i32, i32, i32], ctypes.c_int),
     "index_orientations_ex": ([vp, vp, i64, vp, i32, i32, vp, vp, vp, vp], ctypes.c_int),
     "ar_disorientation_cubic": ([vp, vp, i64, vp, vp], ctypes.c_int),
     "ar_rotate_reference": ([vp, vp, i32, i32, vp, i32, vp, vp, i64, vp, vp], ctypes.c_int),
@@ -289,8 +289,9 @@ class Library:
             pass
 
 
-def ar_index_set_tile(ctx: Context, wtm: int, wtn: int, bk: int) -> None:
-    _call("ar_index_set_tile", ctx.handle, wtm, wtn, bk)
+def ar_index_set_tile(ctx: Context, waves: int, wtm: int, wtn: int, bk: int) -> None:
+    """Correlation tile of this context's index calls (see include/araullo.h)."""
+    _call("ar_index_set_tile", ctx.handle, waves, wtm, wtn, bk)
 
 
 def index_orientations(ctx: Context, images: torch.Tensor, library: Library, k: int = 16):

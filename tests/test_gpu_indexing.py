@@ -180,19 +180,19 @@ def test_index_invalid_arguments(nat, ctx):
         nat.index_orientations_ex(ctx, dev(S), lib, 4, 20)
 
 
-@pytest.mark.parametrize("tile", [(2, 2, 64), (2, 4, 32), (4, 2, 32), (4, 4, 32), (2, 4, 64)])
+@pytest.mark.parametrize("tile", [(4, 2, 2, 32), (4, 2, 4, 32), (4, 4, 2, 32), (8, 2, 2, 32), (8, 4, 2, 32)])
 def test_every_correlation_tile_gives_identical_results(nat, ctx, tile):
     """Each score accumulates K in the same order whatever the workgroup
     tile, so candidates, indices and FP32 scores are bit-identical."""
     S, L, truth = synth.planted_images(333, 1500, 4, 300, seed=21)
     lib = nat.Library(ctx, dev(L))
-    nat.ar_index_set_tile(ctx, 2, 2, 64)
+    nat.ar_index_set_tile(ctx, 4, 2, 2, 32)
     try:
         ref = nat.index_orientations_ex(ctx, dev(S), lib, 16, 16)
         nat.ar_index_set_tile(ctx, *tile)
         got = nat.index_orientations_ex(ctx, dev(S), lib, 16, 16)
     finally:
-        nat.ar_index_set_tile(ctx, 2, 4, 64)
+        nat.ar_index_set_tile(ctx, 8, 4, 2, 32)
     for a, b in zip(ref, got):
         assert torch.equal(a, b)
     assert np.array_equal(got[0][:, 0].cpu().numpy(), truth)
