@@ -70,6 +70,9 @@ def parse():
     ap.add_argument("--cpu-sample-rois", type=int, default=16)
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain device copy of 1 GiB (scale factor for HBM counters)")
+    ap.add_argument("--compare", action="store_true",
+                    help="instead of the step: plain vs batched signatures (configs 2 and 3) and BF16-MFMA vs "
+                         "plain FP32 indexing on the same GPU; prints one JSON line")
     return ap.parse_args()
 
 
@@ -105,6 +108,9 @@ def main():
         b.copy_(a)
         torch.cuda.synchronize()
         print(json.dumps({"copy_probe_bytes_read": 4 * n, "copy_probe_bytes_written": 4 * n}))
+        return
+    if args.compare:
+        compare(nat, synth, torch, dev)
         return
 
     # ------------------------------------------------------------ setup (untimed)
@@ -316,6 +322,78 @@ def main():
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(s, windows.numpy(), L, lib_q, ref, T, args, n_lib)
     print(json.dumps(rec), flush=True)
+
+
+def compare(nat, synth, torch, dev):
+    """The batched and BF16 forms against the plain method on the same GPU.
+    Signatures: the plain per-launch kernel (one workgroup per ROI and
+    256-direction tile) against the autotuned persistent plan replayed as a
+    graph, on config 2 (even ROIs) and config 3 (uneven, surface-clipped);
+    the images must be bit-identical.  Indexing: the BF16 MFMA correlation
+    with fused top-16 and FP32 rescore against a plain FP32 evaluation of the
+    same dense score (library GEMM in FP32 through torch, then top-16) on the
+    config-2 images and 20000-reference library; reported: times and top-1
+    agreement."""
+    def best_ms(fn, reps=3):
+        fn()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        return min(ts)
+
+    ctx = nat.Context(0)
+    rec = {"compare": "plain vs batched signatures; BF16 MFMA + FP32 rescore vs plain FP32 indexing"}
+    for name, s in (("cfg2", synth.config2()), ("cfg3", synth.config3())):
+        w = nat.windows_for(s.radius, s.nbins, s.spacings)
+        pos = torch.from_numpy(s.positions).to(dev)
+        cen = torch.from_numpy(s.centres).to(dev)
+        dirs = torch.from_numpy(s.directions).to(dev)
+        off, rel = nat.ar_roi_gather(ctx, pos, cen, s.radius)
+        plain = nat.araullo_signatures_csr(ctx, rel, off, s.radius, dirs, s.nbins, w)
+        t_plain = best_ms(lambda: nat.araullo_signatures_csr(ctx, rel, off, s.radius, dirs, s.nbins, w, out=plain))
+        plan = nat.SignaturePlan(ctx, len(s.centres), rel.shape[0], len(s.directions), s.nbins, len(w))
+        out = plan.tune(rel, off, s.radius, dirs, w)
+        t_plan = best_ms(lambda: plan.run(rel, off, s.radius, dirs, w, out=out, use_graph=True))
+        units = len(s.centres) * len(s.directions)
+        counts = torch.diff(off).cpu().numpy()
+        rec[f"signatures_{name}"] = {
+            "rois": len(s.centres), "atoms_min": int(counts.min()), "atoms_max": int(counts.max()),
+            "plain_ms": t_plain, "batched_ms": t_plan, "speedup": t_plain / t_plan,
+            "batched_roi_dir_per_s": units / (t_plan / 1e3), "identical": bool(torch.equal(out, plain)),
+            "plan": dict(zip(["dirs_per_item", "atoms_per_stage", "blocks_per_cu", "min_waves"], plan.config()))}
+        if name == "cfg2":
+            images = out.clone()
+            rpos, roffs = synth.reference_rois(0, 16, R=s.radius, cfg=4)
+            ref = nat.araullo_signatures(ctx, torch.from_numpy(rpos).to(dev), torch.from_numpy(roffs).to(dev),
+                                         s.radius, dirs, s.nbins, w, counts=False).mean(0, keepdim=True)
+            lib_q = torch.from_numpy(synth.library_orientations(20000, 2)).to(dev)
+            L = nat.ar_rotate_reference(ctx, ref.contiguous(), dirs, lib_q,
+                                        torch.zeros(20000, dtype=torch.int32, device=dev))
+        del plain, out, plan
+    lib = nat.Library(ctx, L)
+    t_bf16 = best_ms(lambda: nat.index_orientations(ctx, images, lib, 16))
+    idx_bf16, _ = nat.index_orientations(ctx, images, lib, 16)
+
+    def plain_fp32():
+        Sh = (images / images.amax(dim=2, keepdim=True).clamp_min(1e-30)).reshape(len(images), -1)
+        Lh = (L / L.amax(dim=2, keepdim=True).clamp_min(1e-30)).reshape(len(L), -1)
+        d = (Lh * Lh).sum(1)[None, :] - 2.0 * (Sh @ Lh.T)
+        return torch.topk(d, 16, dim=1, largest=False).indices
+    t_fp32 = best_ms(plain_fp32)
+    idx_fp32 = plain_fp32()
+    agree = float((idx_fp32[:, 0] == idx_bf16[:, 0].long()).float().mean())
+    rec["indexing_cfg2"] = {
+        "rois": int(images.shape[0]), "references": int(L.shape[0]), "k": 16,
+        "bf16_mfma_rescored_ms": t_bf16, "plain_fp32_ms": t_fp32, "speedup": t_fp32 / t_bf16,
+        "top1_agreement": agree,
+        "plain_fp32": "normalise, FP32 GEMM S L^T (torch / hipBLASLt), |L|^2 - 2 S.L, torch.topk"}
+    print(json.dumps(rec))
 
 
 def cpu_baseline(s, windows, L, lib_q, ref, T, args, n_lib):

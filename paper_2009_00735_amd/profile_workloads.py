@@ -1,0 +1,69 @@
+"""Single-stage workloads for profiling one kernel family under rocprofv3.
+
+    python -m paper_2009_00735_amd.profile_workloads indexing [--reps 5]
+    python -m paper_2009_00735_amd.profile_workloads signatures [--reps 5]
+
+`indexing`: the config-2 indexing shape (2000 ROI images x 20000 references,
+4 x 10242 nodes) on seeded random non-negative images generated on the
+device; calls `index_orientations(k = 16)` `reps` times.
+
+`signatures`: config 2 (2000 ROIs of about 1000 atoms, 10242 directions,
+1024 bins): one ROI query, then the autotuned persistent signature plan
+replayed `reps` times.
+
+Every call goes through the C ABI (`native`); nothing here computes any part
+of the method.  Prints one line per repetition with the wall time.
+"""
+from __future__ import annotations
+
+import argparse
+import time
+
+import torch
+
+from . import native as nat
+from . import synth
+
+
+def _timed(label: str, fn, reps: int) -> None:
+    for i in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fn()
+        torch.cuda.synchronize()
+        print(f"{label} rep {i}: {(time.perf_counter() - t0) * 1e3:.2f} ms", flush=True)
+
+
+def indexing(reps: int) -> None:
+    ctx = nat.Context(0)
+    gen = torch.Generator(device="cuda").manual_seed(5)
+    L = torch.rand((20000, 4, 10242), device="cuda", generator=gen) ** 2
+    S = torch.rand((2000, 4, 10242), device="cuda", generator=gen) ** 2
+    lib = nat.Library(ctx, L)
+    _timed("index_orientations", lambda: nat.index_orientations(ctx, S, lib, 16), reps)
+
+
+def signatures(reps: int) -> None:
+    ctx = nat.Context(0)
+    s = synth.config2()
+    w = nat.windows_for(s.radius, s.nbins, s.spacings)
+    pos = torch.from_numpy(s.positions).cuda()
+    cen = torch.from_numpy(s.centres).cuda()
+    dirs = torch.from_numpy(s.directions).cuda()
+    off, rel = nat.ar_roi_gather(ctx, pos, cen, s.radius)
+    plan = nat.SignaturePlan(ctx, len(s.centres), rel.shape[0], len(s.directions), s.nbins, len(w))
+    out = plan.tune(rel, off, s.radius, dirs, w)
+    print("plan", plan.config(), flush=True)
+    _timed("signature plan", lambda: plan.run(rel, off, s.radius, dirs, w, out=out, use_graph=True), reps)
+
+
+def main() -> None:
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("workload", choices=["indexing", "signatures"])
+    ap.add_argument("--reps", type=int, default=5)
+    a = ap.parse_args()
+    {"indexing": indexing, "signatures": signatures}[a.workload](a.reps)
+
+
+if __name__ == "__main__":
+    main()
