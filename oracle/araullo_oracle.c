@@ -51,6 +51,18 @@
  *      |k| = f_w along rotated mesh directions; A = |F| / N_w and
  *      J(q) = sum (A - T)^2.  This refinement score is not in the paper; it is
  *      built on Eq. (2) (Sec. 2.2, FSP paragraph).
+ *  R12 sparse form of Eq. S1 (supplement, "Indexing algorithm"; cost O_idx
+ *      in the complexity paragraph): per phase, the reference image is
+ *      normalised per window (R7) and its n_hat entries (window w, node v)
+ *      with the largest normalised value are kept, in decreasing order (the
+ *      value is the FP64 quotient x / max of the FP32 inputs; equal values
+ *      keep the lower flat index w * n_dir + v first).  For orientation q the
+ *      look-up node of entry i is the mesh node closest to R(q) n_{v_i}
+ *      (largest dot product in FP64, ties to the lower index) and
+ *      Delta(r, q) = sum_i (S^_r[w_i][p(q, i)] - Ref^[w_i][v_i])^2.  The
+ *      window of the strong entry is carried along (the paper has one window
+ *      per signature).  R(q) rather than R(q)^T: a reference feature at node
+ *      u appears at R(q) n_u in the image rotated as in R10.
  */
 #include <math.h>
 #include <stdint.h>
@@ -487,4 +499,134 @@ double orc_sf_refine(const float *rel, int64_t n_w, double *q, const float *dirs
         }
     }
     return J;
+}
+
+/* ---------------------------------------------------------------------- */
+/* Sparse look-up-table indexing (reading R12), FP64                        */
+/* ---------------------------------------------------------------------- */
+typedef struct {
+    double v;
+    int32_t i;
+} orc_ranked;
+
+/* decreasing value, then increasing flat index */
+static int orc_ranked_cmp(const void *a, const void *b)
+{
+    const orc_ranked *x = (const orc_ranked *)a, *y = (const orc_ranked *)b;
+    if (x->v > y->v) return -1;
+    if (x->v < y->v) return 1;
+    return (x->i > y->i) - (x->i < y->i);
+}
+
+/* Per phase: the n_hat strongest entries of the window-normalised reference.
+ * strong_idx[c][i] = w * n_dir + v, strong_val[c][i] = x / max (FP64). */
+void orc_sparse_strong(const float *ref, int32_t n_phase, int32_t n_win, int32_t n_dir, int32_t n_hat,
+                       int32_t *strong_idx, double *strong_val)
+{
+    const int64_t K = (int64_t)n_win * n_dir;
+    orc_ranked *e = (orc_ranked *)malloc(sizeof(orc_ranked) * (size_t)K);
+    for (int32_t c = 0; c < n_phase; ++c) {
+        for (int32_t w = 0; w < n_win; ++w) {
+            const float *src = ref + ((size_t)c * n_win + w) * n_dir;
+            double m = 0.0;
+            for (int32_t v = 0; v < n_dir; ++v) if ((double)src[v] > m) m = (double)src[v];
+            for (int32_t v = 0; v < n_dir; ++v) {
+                e[(size_t)w * n_dir + v].v = m > 0.0 ? (double)src[v] / m : 0.0;
+                e[(size_t)w * n_dir + v].i = w * n_dir + v;
+            }
+        }
+        qsort(e, (size_t)K, sizeof(orc_ranked), orc_ranked_cmp);
+        for (int32_t i = 0; i < n_hat; ++i) {
+            strong_idx[(size_t)c * n_hat + i] = e[i].i;
+            strong_val[(size_t)c * n_hat + i] = e[i].v;
+        }
+    }
+    free(e);
+}
+
+/* lut[l][i] = index u of the node with the largest n_u . (R(q_l) n_v),
+ * v = node of strong entry i of phase[l]; FP64, ties to the lower index. */
+void orc_sparse_lut(const double *quats, const int32_t *phase, int64_t n_lib, const int32_t *strong_idx,
+                    int32_t n_hat, const float *dirs, int32_t n_dir, int32_t *lut, int32_t n_threads)
+{
+#ifdef _OPENMP
+    if (n_threads < 1) n_threads = 1;
+#pragma omp parallel for schedule(dynamic, 1) num_threads(n_threads)
+#endif
+    for (int64_t l = 0; l < n_lib; ++l) {
+        double M[9];
+        orc_qmatrix(quats + 4 * l, M);
+        for (int32_t i = 0; i < n_hat; ++i) {
+            const int32_t v = strong_idx[(size_t)phase[l] * n_hat + i] % n_dir;
+            double x = dirs[3 * v], y = dirs[3 * v + 1], z = dirs[3 * v + 2];
+            /* R n */
+            double rx = M[0] * x + M[1] * y + M[2] * z;
+            double ry = M[3] * x + M[4] * y + M[5] * z;
+            double rz = M[6] * x + M[7] * y + M[8] * z;
+            double best = -INFINITY;
+            int32_t arg = 0;
+            for (int32_t u = 0; u < n_dir; ++u) {
+                double d = rx * dirs[3 * u] + ry * dirs[3 * u + 1] + rz * dirs[3 * u + 2];
+                if (d > best) { best = d; arg = u; }
+            }
+            lut[(size_t)l * n_hat + i] = arg;
+        }
+    }
+}
+
+/* Eq. S1 (sparse) for one (ROI, library entry) pair. */
+static double orc_sparse_delta(const double *s, int32_t n_dir, const int32_t *strong_idx, const double *strong_val,
+                               const int32_t *lut_row, int32_t n_hat)
+{
+    double delta = 0.0;
+    for (int32_t i = 0; i < n_hat; ++i) {
+        const int32_t w = strong_idx[i] / n_dir;
+        double e = s[(size_t)w * n_dir + lut_row[i]] - strong_val[i];
+        delta += e * e;
+    }
+    return delta;
+}
+
+/* For every normalised ROI image Sh[r][n_win][n_dir]: the k library entries
+ * with the smallest sparse Delta, ascending by (Delta, library index). */
+void orc_sparse_index_topk(const double *Sh, int64_t n_roi, int32_t n_win, int32_t n_dir, const int32_t *strong_idx,
+                           const double *strong_val, const int32_t *phase, const int32_t *lut, int64_t n_lib,
+                           int32_t n_hat, int32_t k, int32_t *top_idx, double *top_score, int32_t n_threads)
+{
+#ifdef _OPENMP
+    if (n_threads < 1) n_threads = 1;
+#pragma omp parallel for schedule(dynamic, 1) num_threads(n_threads)
+#endif
+    for (int64_t r = 0; r < n_roi; ++r) {
+        const double *s = Sh + (size_t)r * n_win * n_dir;
+        int32_t *bi = top_idx + (size_t)r * k;
+        double *bs = top_score + (size_t)r * k;
+        int32_t filled = 0;
+        for (int64_t l = 0; l < n_lib; ++l) {
+            const size_t c = (size_t)phase[l];
+            double delta = orc_sparse_delta(s, n_dir, strong_idx + c * n_hat, strong_val + c * n_hat,
+                                            lut + (size_t)l * n_hat, n_hat);
+            int32_t pos = filled;
+            while (pos > 0 && bs[pos - 1] > delta) --pos;
+            if (pos >= k) continue;
+            int32_t last = filled < k ? filled : k - 1;
+            for (int32_t m = last; m > pos; --m) { bs[m] = bs[m - 1]; bi[m] = bi[m - 1]; }
+            bs[pos] = delta; bi[pos] = (int32_t)l;
+            if (filled < k) ++filled;
+        }
+        for (int32_t m = filled; m < k; ++m) { bs[m] = INFINITY; bi[m] = -1; }
+    }
+}
+
+/* Sparse Delta for explicit (roi, library) pairs; lut rows of the listed
+ * library entries are passed in lut_rows[p][n_hat]. */
+void orc_sparse_pairs(const double *Sh, int32_t n_win, int32_t n_dir, const int32_t *strong_idx,
+                      const double *strong_val, const int32_t *pair_phase, const int32_t *lut_rows, int32_t n_hat,
+                      const int64_t *roi, int64_t n_pairs, double *out)
+{
+    for (int64_t p = 0; p < n_pairs; ++p) {
+        const size_t c = (size_t)pair_phase[p];
+        out[p] = orc_sparse_delta(Sh + (size_t)roi[p] * n_win * n_dir, n_dir, strong_idx + c * n_hat,
+                                  strong_val + c * n_hat, lut_rows + (size_t)p * n_hat, n_hat);
+    }
 }

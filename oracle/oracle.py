@@ -64,6 +64,11 @@ def lib():
         L.orc_disorientation_cubic.argtypes = [F64P, F64P, c_i64, F64P]
         L.orc_cubic_group_out.argtypes = [F64P]
         L.orc_rotated_nodes.argtypes = [F64P, c_i64, F32P, c_i32, I32P, c_i32]
+        L.orc_sparse_strong.argtypes = [F32P, c_i32, c_i32, c_i32, c_i32, I32P, F64P]
+        L.orc_sparse_lut.argtypes = [F64P, I32P, c_i64, I32P, c_i32, F32P, c_i32, I32P, c_i32]
+        L.orc_sparse_index_topk.argtypes = [F64P, c_i64, c_i32, c_i32, I32P, F64P, I32P, I32P, c_i64, c_i32,
+                                            c_i32, I32P, F64P, c_i32]
+        L.orc_sparse_pairs.argtypes = [F64P, c_i32, c_i32, I32P, F64P, I32P, I32P, c_i32, I64P, c_i64, F64P]
         L.orc_sf_amplitudes.argtypes = [F32P, c_i64, F64P, F32P, c_i32, F64P, c_i32, F64P]
         L.orc_sf_score.argtypes = [F32P, c_i64, F64P, F32P, c_i32, F64P, c_i32, F64P]
         L.orc_sf_score.restype = c_f64
@@ -214,6 +219,56 @@ def library_images(reference, phase_of, quats, directions, threads: Optional[int
     out = np.empty((len(lut), ref.shape[1], ref.shape[2]), ref.dtype)
     for l in range(len(lut)):
         out[l] = ref[ph[l]][:, lut[l]]
+    return out
+
+
+# ---------------------------------------------------------------- sparse indexing (reading R12)
+def sparse_strong(reference, n_hat: int) -> Tuple[np.ndarray, np.ndarray]:
+    """Per phase of reference [n_phase][n_win][n_dir]: the n_hat strongest
+    window-normalised entries as flat indices w*n_dir+v (decreasing value,
+    ties to the lower index) and their FP64 normalised values."""
+    x = _f32(reference)
+    n_phase, n_win, n_dir = x.shape
+    assert 1 <= n_hat <= n_win * n_dir
+    idx = np.zeros((n_phase, n_hat), np.int32)
+    val = np.zeros((n_phase, n_hat), np.float64)
+    lib().orc_sparse_strong(x, n_phase, n_win, n_dir, n_hat, idx, val)
+    return idx, val
+
+
+def sparse_lut(quats, phase, strong_idx, directions, threads: Optional[int] = None) -> np.ndarray:
+    """lut[l][i]: mesh node closest to R(q_l) n_v, v = node of strong entry i
+    of phase[l]."""
+    q = _f64(quats).reshape(-1, 4)
+    ph = _i32(phase)
+    si = _i32(strong_idx)
+    d = _f32(directions)
+    out = np.zeros((len(q), si.shape[1]), np.int32)
+    lib().orc_sparse_lut(q, ph, len(q), si, si.shape[1], d, len(d), out, threads or default_threads())
+    return out
+
+
+def sparse_index_topk(S_hat, strong_idx, strong_val, phase, lut, k: int,
+                      threads: Optional[int] = None) -> Tuple[np.ndarray, np.ndarray]:
+    S = _f64(S_hat)
+    n_roi, n_win, n_dir = S.shape
+    si, sv, ph, lt = _i32(strong_idx), _f64(strong_val), _i32(phase), _i32(lut)
+    idx = np.zeros((n_roi, k), np.int32)
+    sc = np.zeros((n_roi, k), np.float64)
+    lib().orc_sparse_index_topk(S, n_roi, n_win, n_dir, si, sv, ph, lt, len(lt), si.shape[1], k, idx, sc,
+                                threads or default_threads())
+    return idx, sc
+
+
+def sparse_pairs(S_hat, strong_idx, strong_val, pair_phase, lut_rows, roi) -> np.ndarray:
+    """Sparse Delta of (roi[p], entry with look-up row lut_rows[p] and phase
+    pair_phase[p])."""
+    S = _f64(S_hat)
+    n_roi, n_win, n_dir = S.shape
+    si, sv = _i32(strong_idx), _f64(strong_val)
+    r = np.ascontiguousarray(roi, np.int64)
+    out = np.zeros(len(r), np.float64)
+    lib().orc_sparse_pairs(S, n_win, n_dir, si, sv, _i32(pair_phase), _i32(lut_rows), si.shape[1], r, len(r), out)
     return out
 
 
