@@ -43,6 +43,7 @@ typedef enum {
 typedef struct ar_context ar_context;
 typedef struct ar_library ar_library;
 typedef struct ar_plan ar_plan;
+typedef struct ar_sparse_lut ar_sparse_lut;
 
 /* Message of the last failed call on this thread ("" if none). */
 const char *ar_last_error(void);
@@ -202,11 +203,11 @@ ar_status ar_library_destroy(ar_library *lib);
  * over all nodes of all windows),
  *   Delta(r,l) = sum_{w,v} (S_r[w][v]/max_v S_r[w] - L_l[w][v]/max_v L_l[w])^2.
  * Candidates come from a BF16-input / FP32-accumulate MFMA correlation
- * (score = |L_l|^2 - 2 <S_r, L_l>) keeping the best `cand` (>= k, <= 64)
- * per ROI, which are then rescored in FP32 from the FP32 images; the output
- * is sorted ascending by (FP32 Delta, library index).
+ * (score = |L_l|^2 - 2 <S_r, L_l>) keeping the best `cand` (16 for
+ * k <= 16, else 32) per ROI, which are then rescored in FP32 from the FP32
+ * images; the output is sorted ascending by (FP32 Delta, library index).
  *   images    device float [n_roi][n_win][n_dir] (raw signatures)
- *   k         1 .. 64 outputs per ROI
+ *   k         1 .. 32 outputs per ROI
  *   top_idx   device int32 [n_roi][k], out
  *   top_score device float [n_roi][k], out: FP32 Delta
  * Does not synchronise.
@@ -215,8 +216,8 @@ ar_status index_orientations(ar_context *ctx, const float *images, int64_t n_roi
                              const ar_library *lib, int32_t k, int32_t *top_idx, float *top_score,
                              void *stream);
 
-/* As index_orientations with an explicit candidate count `cand`
- * (k <= cand <= 64; index_orientations uses cand = max(k, 16)), optionally
+/* As index_orientations with an explicit candidate count `cand` (16 or 32,
+ * k <= cand; index_orientations uses 16 for k <= 16, else 32), optionally
  * returning the BF16-stage candidates before rescoring.
  *   cand_idx  device int32 [n_roi][cand] or NULL, out */
 ar_status index_orientations_ex(ar_context *ctx, const float *images, int64_t n_roi,
@@ -230,6 +231,54 @@ ar_status index_orientations_ex(ar_context *ctx, const float *images, int64_t n_
  * (8,2,2,32) (8,4,2,32); default (8,4,2,32), a 256 x 256 tile.  Results do not depend on the
  * tile: every score accumulates K in the same order. */
 ar_status ar_index_set_tile(ar_context *ctx, int32_t waves, int32_t wtm, int32_t wtn, int32_t bk);
+
+/*
+ * Sparse indexing (supplement, "Indexing algorithm", Eq. S1 over the n_hat
+ * strongest reference entries, look-up costs O_lu and O_idx of the
+ * complexity paragraph).  The look-up table, per phase c:
+ *   - the reference image of c is normalised per window, key = x / max in
+ *     FP64 (an all-zero window gives 0); its n_hat entries (w, v) with the
+ *     largest key, equal keys by the lower flat index w * n_dir + v, form the
+ *     strong list (decreasing key), with values R_i = (float)key;
+ *   - for every orientation g of phase c and strong entry i the node
+ *     p(g, i) = argmax_u n_u . (R(q_g) n_{v_i}) (FP32 ranking, re-ranked in
+ *     FP64 within 1e-5 of the best, ties to the lower index).
+ *   reference   device float [n_phase][n_win][n_dir], finite, read during the call only
+ *   directions  device float [n_dir][3] unit mesh normals, n_dir <= 65535
+ *   quats       device double [n_lib][4] (w, x, y, z); the entries of phase c
+ *               are the consecutive rows after those of phases 0 .. c-1
+ *   phase_count host int64 [n_phase]: entries per phase (sum = n_lib >= 1)
+ *   n_hat       1 .. min(n_win * n_dir, 65535)
+ * The table owns copies of everything it needs (2 * n_lib * n_hat bytes of
+ * node ids in each of two layouts); destroy frees them.
+ */
+ar_status ar_sparse_lut_create(ar_context *ctx, const float *reference, int32_t n_phase, int32_t n_win,
+                               const float *directions, int32_t n_dir, const double *quats,
+                               const int64_t *phase_count, int32_t n_hat, void *stream,
+                               ar_sparse_lut **out);
+ar_status ar_sparse_lut_destroy(ar_sparse_lut *lut);
+/* Copy out the strong lists and the table (any pointer may be NULL):
+ *   strong_idx device int32 [n_phase][n_hat]: w * n_dir + v, decreasing key
+ *   strong_val device float [n_phase][n_hat]: R_i
+ *   nodes      device int32 [n_lib][n_hat]: p(g, i) */
+ar_status ar_sparse_lut_export(const ar_sparse_lut *lut, int32_t *strong_idx, float *strong_val,
+                               int32_t *nodes, void *stream);
+
+/*
+ * The k library entries with the smallest sparse Eq. S1
+ *   Delta(r, g) = sum_i (S_r[w_i][p(g, i)] / max_v S_r[w_i] - R_i)^2
+ * (w_i the window of strong entry i of g's phase).  A screen in FP16 image
+ * values with FP32 accumulation keeps 16 (k <= 16) or 32 candidates per
+ * ROI, which are rescored in FP32 from the FP32 image; the output is sorted
+ * ascending by (FP32 Delta, library index).
+ *   images    device float [n_roi][n_win][n_dir] (raw signatures), n_roi >= 1
+ *   k         1 .. 32
+ *   top_idx   device int32 [n_roi][k], out;  top_score device float [n_roi][k], out
+ * Does not synchronise.
+ */
+ar_status index_orientations_sparse(ar_context *ctx, const float *images, int64_t n_roi,
+                                    const ar_sparse_lut *lut, int32_t k, int32_t *top_idx,
+                                    float *top_score, void *stream);
 
 /*
  * Disorientation angle in degrees under cubic symmetry (supplement,

@@ -81,6 +81,8 @@ struct ar_context {
     int corr_waves = 8, corr_wtm = 4, corr_wtn = 2, corr_bk = 32;
     // indexing workspace
     ar::DeviceBuffer i_bf16, i_inv, i_cand_idx, i_cand_score, i_merge_idx;
+    // sparse indexing workspace
+    ar::DeviceBuffer sp_half, sp_inv, sp_cand_s, sp_cand_i, sp_merge;
     // refinement workspace
     ar::DeviceBuffer r_partials, r_state, r_dirs;
     // twiddle tables exp(-2 pi i j / nbins), j < nbins, per nbins

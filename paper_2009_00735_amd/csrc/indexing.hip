@@ -26,6 +26,7 @@
 #include <algorithm>
 
 #include "ar_internal.h"
+#include "topk_device.h"
 
 namespace ar {
 namespace idx {
@@ -102,36 +103,6 @@ __global__ __launch_bounds__(256) void k_row_norm2(const uint16_t *__restrict__ 
     }
     if (threadIdx.x == 0) norm2[row] = row < n_valid ? red[0] : INFINITY;
 }
-
-// ------------------------------------------------------------ top-CAND list
-// Sorted ascending by (score, index); insertion keeps the CAND smallest.
-template <int CAND>
-struct TopList {
-    float s[CAND];
-    int i[CAND];
-    __device__ __forceinline__ void init()
-    {
-#pragma unroll
-        for (int j = 0; j < CAND; ++j) {
-            s[j] = INFINITY;
-            i[j] = 0x7fffffff;
-        }
-    }
-    __device__ __forceinline__ void insert(float cs, int ci)
-    {
-        if (!(cs < s[CAND - 1] || (cs == s[CAND - 1] && ci < i[CAND - 1]))) return;
-#pragma unroll
-        for (int j = 0; j < CAND; ++j) {
-            const bool lt = cs < s[j] || (cs == s[j] && ci < i[j]);
-            const float ts = lt ? s[j] : cs;
-            const int ti = lt ? i[j] : ci;
-            s[j] = lt ? cs : s[j];
-            i[j] = lt ? ci : i[j];
-            cs = ts;
-            ci = ti;
-        }
-    }
-};
 
 // ------------------------------------------------------------ correlation
 // Workgroup: WGM x WGN waves (2x2 or 2x4); each wave owns WTM x WTN MFMA
@@ -370,31 +341,9 @@ __global__ __launch_bounds__(256) void k_merge(const float *__restrict__ in_s, c
     TopList<CAND> t;
     t.init();
     for (int e = lane; e < n; e += 64) t.insert(s[e], ix[e]);
-    // CAND rounds of a wave-wide argmin over the lanes' list heads
-    int head = 0;
-    for (int j = 0; j < CAND; ++j) {
-        float hs = INFINITY;
-        int hi = 0x7fffffff;
-#pragma unroll
-        for (int q = 0; q < CAND; ++q)
-            if (q == head) {
-                hs = t.s[q];
-                hi = t.i[q];
-            }
-        float bs = hs;
-        int bi = hi;
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) {
-            const float os = __shfl_xor(bs, off);
-            const int oi = __shfl_xor(bi, off);
-            if (os < bs || (os == bs && oi < bi)) {
-                bs = os;
-                bi = oi;
-            }
-        }
-        if (hs == bs && hi == bi && head < CAND) ++head;
+    wave_select<CAND>(t, [&](int j, float, int bi) {
         if (lane == 0) cand_idx[(size_t)row * CAND + j] = bi;
-    }
+    });
 }
 
 // ------------------------------------------------------------ FP32 rescore

@@ -4,6 +4,7 @@
 #include <math.h>
 
 #include "ar_internal.h"
+#include "mesh_device.h"
 
 namespace ar {
 namespace {
@@ -55,9 +56,9 @@ __global__ __launch_bounds__(256) void k_disorientation(const double *__restrict
     deg[i] = 2.0 * acos(c) * (180.0 / 3.14159265358979323846);
 }
 
-// One thread per (entry, node): rotate n_v by R(q)^T, find the closest node
-// (largest dot product) in FP32 over all nodes, then re-rank every node within
-// 1e-5 of that maximum in FP64 (ties to the lower index).
+// One thread per (entry, node): rotate n_v by R(q)^T and take the reference
+// value at the closest node (nearest_node: FP32 scan, FP64 re-rank, ties to
+// the lower index).
 __global__ __launch_bounds__(256) void k_rotate_reference(const float *__restrict__ ref, int n_win,
                                                           const float *__restrict__ dirs, int n_dir,
                                                           const double *__restrict__ quats,
@@ -68,39 +69,14 @@ __global__ __launch_bounds__(256) void k_rotate_reference(const float *__restric
     const int64_t l = gid / n_dir;
     const int v = (int)(gid - l * n_dir);
     const bool valid = l < n_lib;
-    double M[9] = {0};
-    if (valid) {
-        double w = quats[4 * l], x = quats[4 * l + 1], y = quats[4 * l + 2], z = quats[4 * l + 3];
-        const double nq = sqrt(w * w + x * x + y * y + z * z);
-        w /= nq; x /= nq; y /= nq; z /= nq;
-        M[0] = 1 - 2 * (y * y + z * z); M[1] = 2 * (x * y - w * z);     M[2] = 2 * (x * z + w * y);
-        M[3] = 2 * (x * y + w * z);     M[4] = 1 - 2 * (x * x + z * z); M[5] = 2 * (y * z - w * x);
-        M[6] = 2 * (x * z - w * y);     M[7] = 2 * (y * z + w * x);     M[8] = 1 - 2 * (x * x + y * y);
-    }
+    double M[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1};
+    if (valid) quat_matrix64(quats + 4 * l, M);
     const double nx = valid ? dirs[3 * v] : 0.0, ny = valid ? dirs[3 * v + 1] : 0.0, nz = valid ? dirs[3 * v + 2] : 0.0;
     const double rx = M[0] * nx + M[3] * ny + M[6] * nz;
     const double ry = M[1] * nx + M[4] * ny + M[7] * nz;
     const double rz = M[2] * nx + M[5] * ny + M[8] * nz;
-    const float fx = (float)rx, fy = (float)ry, fz = (float)rz;
-    float best = -INFINITY;
-    for (int u = 0; u < n_dir; ++u) {
-        const float d = fmaf(fz, dirs[3 * u + 2], fmaf(fy, dirs[3 * u + 1], fx * dirs[3 * u]));
-        best = fmaxf(best, d);
-    }
+    const int arg = nearest_node(rx, ry, rz, dirs, n_dir);
     if (!valid) return;
-    double bd = -INFINITY;
-    int arg = 0;
-    const float thr = best - 1e-5f;
-    for (int u = 0; u < n_dir; ++u) {
-        const float d = fmaf(fz, dirs[3 * u + 2], fmaf(fy, dirs[3 * u + 1], fx * dirs[3 * u]));
-        if (d >= thr) {
-            const double dd = rx * (double)dirs[3 * u] + ry * (double)dirs[3 * u + 1] + rz * (double)dirs[3 * u + 2];
-            if (dd > bd) {
-                bd = dd;
-                arg = u;
-            }
-        }
-    }
     const int p = phase[l];
     for (int w = 0; w < n_win; ++w)
         out[((size_t)l * n_win + w) * n_dir + v] = ref[((size_t)p * n_win + w) * n_dir + arg];

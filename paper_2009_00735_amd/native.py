@@ -44,6 +44,10 @@ _SIGS = {
     "ar_library_destroy": ([vp], ctypes.c_int),
     "index_orientations": ([vp, vp, i64, vp, i32, vp, vp, vp], ctypes.c_int),
     "ar_index_set_tile": ([vp, i32, i32, i32, i32], ctypes.c_int),
+    "ar_sparse_lut_create": ([vp, vp, i32, i32, vp, i32, vp, P(i64), i32, vp, P(vp)], ctypes.c_int),
+    "ar_sparse_lut_destroy": ([vp], ctypes.c_int),
+    "ar_sparse_lut_export": ([vp, vp, vp, vp, vp], ctypes.c_int),
+    "index_orientations_sparse": ([vp, vp, i64, vp, i32, vp, vp, vp], ctypes.c_int),
     "index_orientations_ex": ([vp, vp, i64, vp, i32, i32, vp, vp, vp, vp], ctypes.c_int),
     "ar_disorientation_cubic": ([vp, vp, i64, vp, vp], ctypes.c_int),
     "ar_rotate_reference": ([vp, vp, i32, i32, vp, i32, vp, vp, i64, vp, vp], ctypes.c_int),
@@ -315,6 +319,63 @@ def index_orientations_ex(ctx: Context, images: torch.Tensor, library: Library, 
     _call("index_orientations_ex", ctx.handle, _dev(images, torch.float32, d, "images"), n_roi, library.handle, k,
           cand, idx.data_ptr(), sc.data_ptr(), ci.data_ptr(), _stream(d))
     return idx, sc, ci
+
+
+class SparseLUT:
+    """ar_sparse_lut: the n_hat strongest entries of each phase's reference
+    and the rotated-node look-up table for every library orientation (the
+    orientations of phase c are the phase_count[c] rows after those of the
+    phases before it)."""
+
+    def __init__(self, ctx: Context, reference: torch.Tensor, directions: torch.Tensor, quats: torch.Tensor,
+                 phase_count: Sequence[int], n_hat: int):
+        self.ctx = ctx
+        d = ctx.device
+        n_phase, n_win, n_dir = reference.shape
+        if len(phase_count) != n_phase:
+            raise ValueError("phase_count needs one entry per phase")
+        counts = (i64 * n_phase)(*[int(c) for c in phase_count])
+        self.n_phase, self.n_win, self.n_dir, self.n_hat = n_phase, n_win, n_dir, n_hat
+        self.n_lib = int(sum(int(c) for c in phase_count))
+        if quats.shape != (self.n_lib, 4):
+            raise ValueError(f"quats must be [{self.n_lib}][4]")
+        h = vp()
+        _call("ar_sparse_lut_create", ctx.handle, _dev(reference, torch.float32, d, "reference"), n_phase, n_win,
+              _dev(directions, torch.float32, d, "directions"), n_dir, _dev(quats, torch.float64, d, "quats"), counts,
+              n_hat, _stream(d), ctypes.byref(h))
+        self.handle = h
+
+    def export(self):
+        """-> (strong_idx int32 [n_phase][n_hat], strong_val float32 [n_phase][n_hat],
+        nodes int32 [n_lib][n_hat])."""
+        d = self.ctx.device
+        si = torch.empty((self.n_phase, self.n_hat), dtype=torch.int32, device=d)
+        sv = torch.empty((self.n_phase, self.n_hat), dtype=torch.float32, device=d)
+        nodes = torch.empty((self.n_lib, self.n_hat), dtype=torch.int32, device=d)
+        _call("ar_sparse_lut_export", self.handle, si.data_ptr(), sv.data_ptr(), nodes.data_ptr(), _stream(d))
+        return si, sv, nodes
+
+    def close(self):
+        if getattr(self, "handle", None) and self.handle.value:
+            _L.ar_sparse_lut_destroy(self.handle)
+            self.handle = vp()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def index_orientations_sparse(ctx: Context, images: torch.Tensor, lut: SparseLUT, k: int = 16):
+    """-> (top_idx int32 [n_roi][k], top_score float32 [n_roi][k]): sparse Eq. S1."""
+    d = ctx.device
+    n_roi = images.shape[0]
+    idx = torch.empty((n_roi, k), dtype=torch.int32, device=d)
+    sc = torch.empty((n_roi, k), dtype=torch.float32, device=d)
+    _call("index_orientations_sparse", ctx.handle, _dev(images, torch.float32, d, "images"), n_roi, lut.handle, k,
+          idx.data_ptr(), sc.data_ptr(), _stream(d))
+    return idx, sc
 
 
 def ar_disorientation_cubic(qa: torch.Tensor, qb: torch.Tensor) -> torch.Tensor:

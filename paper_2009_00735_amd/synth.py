@@ -27,6 +27,7 @@ streams 0 orientation, 1 lattice offset, 2 deletion, 3 noise, 4 ROI placement,
 from __future__ import annotations
 
 import dataclasses
+import itertools
 import math
 from typing import Dict, List, Optional, Tuple
 
@@ -473,3 +474,57 @@ def planted_images(n_roi: int, n_lib: int, n_win: int, n_dir: int, seed: int, no
     jitter = 1.0 + noise * gen.standard_normal((n_roi, n_win, n_dir), dtype=np.float32)
     S = np.abs(L[truth] * gain * jitter).astype(np.float32)
     return S, L, truth
+
+
+# --------------------------------------------------------------------------
+# signature-like spherical images (indexing inputs without running the
+# signature path): peaks at the crystal directions of each window's
+# lattice-plane family, the shape real window-maximum images have
+# --------------------------------------------------------------------------
+def _family(hkl) -> np.ndarray:
+    """One unit vector per antipodal pair of the cubic family {hkl}."""
+    out = []
+    vals = set()
+    h = [abs(x) for x in hkl]
+    for perm in itertools.permutations(h):
+        for sg in itertools.product((-1, 1), repeat=3):
+            v = tuple(a * b for a, b in zip(perm, sg))
+            if v == (0, 0, 0):
+                continue
+            neg = tuple(-a for a in v)
+            if neg not in vals:
+                vals.add(v)
+    for v in sorted(vals):
+        out.append(np.array(v, np.float64) / np.linalg.norm(v))
+    return np.array(out)
+
+
+# plane-normal families behind the four windows: fcc {111} {200} {220} {311},
+# bcc {110} {200} {211} {220}
+BUMP_FAMILIES = {0: [(1, 1, 1), (1, 0, 0), (1, 1, 0), (3, 1, 1)], 1: [(1, 1, 0), (1, 0, 0), (2, 1, 1), (1, 1, 0)]}
+
+
+def bump_images(directions: np.ndarray, quats: np.ndarray, phase: np.ndarray, n_win: int, width: float = 0.02,
+                background: float = 0.1, gain: Optional[np.ndarray] = None, noise: float = 0.0,
+                seed: int = 0) -> np.ndarray:
+    """Images [n][n_win][n_dir] float32: window w of image i is
+    background + sum_a exp((|u . a| - 1) / width) over the directions a of
+    family w of phase[i], u = R(q_i)^T n_v (the crystal rotated by q_i seen at
+    node v), times gain[i][w] and (1 + noise * N(0,1)) clipped at 0."""
+    d = np.asarray(directions, np.float64)
+    q = np.asarray(quats, np.float64).reshape(-1, 4)
+    ph = np.asarray(phase).reshape(-1)
+    gen = np.random.Generator(np.random.PCG64(np.random.SeedSequence([SEED_ROOT, 778, seed])))
+    fams = {c: [_family(BUMP_FAMILIES[c][w % 4]) for w in range(n_win)] for c in BUMP_FAMILIES}
+    out = np.empty((len(q), n_win, len(d)), np.float32)
+    for i in range(len(q)):
+        u = d @ quat_matrix(q[i])                 # rows R^T n_v
+        for w in range(n_win):
+            a = fams[int(ph[i])][w]
+            x = background + np.exp((np.abs(u @ a.T) - 1.0) / width).sum(axis=1)
+            if gain is not None:
+                x *= gain[i][w]
+            if noise > 0:
+                x *= np.maximum(0.0, 1.0 + noise * gen.standard_normal(len(d)))
+            out[i, w] = x
+    return out
