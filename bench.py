@@ -393,6 +393,37 @@ def compare(nat, synth, torch, dev):
         "bf16_mfma_rescored_ms": t_bf16, "plain_fp32_ms": t_fp32, "speedup": t_fp32 / t_bf16,
         "top1_agreement": agree,
         "plain_fp32": "normalise, FP32 GEMM S L^T (torch / hipBLASLt), |L|^2 - 2 S.L, torch.topk"}
+    # the paper's sparse form of Eq. S1 (strongest reference entries through a
+    # look-up table) against the dense score, same images and orientations
+    truth = torch.from_numpy(synth.config2().truth_q).to(dev)
+    n_rot = lib_q.shape[0]
+    dis_dense = nat.ar_disorientation_cubic(lib_q[idx_bf16[:, 0].long()].contiguous(), truth).cpu().numpy()
+    sparse = {"rois": int(images.shape[0]), "orientations": n_rot, "k": 16,
+              "dense_ms": t_bf16, "dense_top1_disorientation_median_deg": float(np.median(dis_dense))}
+    peaks = nat.ar_measure_peaks(ctx)
+    rb = 4 if images.shape[2] * 8 <= 163840 else (2 if images.shape[2] * 4 <= 163840 else 1)
+    sparse["screen_rois_per_lds_read"] = rb
+    sparse["measured_lds_gather8_per_s"] = peaks["lds_gather8_per_s"]
+    for n_hat in (250, 1000, 4000):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        lut = nat.SparseLUT(ctx, ref.contiguous(), dirs, lib_q, [n_rot], n_hat)
+        torch.cuda.synchronize()
+        t_lut = (time.perf_counter() - t0) * 1e3
+        t_sp = best_ms(lambda: nat.index_orientations_sparse(ctx, images, lut, 16))
+        idx_sp, _ = nat.index_orientations_sparse(ctx, images, lut, 16)
+        dis_sp = nat.ar_disorientation_cubic(lib_q[idx_sp[:, 0].long()].contiguous(), truth).cpu().numpy()
+        sparse[f"n_hat_{n_hat}"] = {
+            "lut_build_ms": t_lut, "index_ms": t_sp, "speedup_vs_dense": t_bf16 / t_sp,
+            "terms_per_s": images.shape[0] * n_rot * n_hat / (t_sp / 1e3),
+            # whole call (screen + rescore + normalise) against random LDS reads:
+            # one 8-byte read serves rb ROI terms
+            "lds_gather_frac": images.shape[0] * n_rot * n_hat / rb / (t_sp / 1e3) / peaks["lds_gather8_per_s"],
+            "top1_same_as_dense": float((idx_sp[:, 0] == idx_bf16[:, 0]).float().mean()),
+            "top1_disorientation_median_deg": float(np.median(dis_sp)),
+            "top1_disorientation_p95_deg": float(np.percentile(dis_sp, 95))}
+        del lut
+    rec["sparse_indexing_cfg2"] = sparse
     print(json.dumps(rec))
 
 

@@ -377,6 +377,8 @@ ar_status ar_refine_orientations(ar_context *ctx, const float *rel, const int64_
  *   out[AR_PEAK_SIN_OVERLAP]      time of 16 FMA chains / time of the same with 4 sin chains beside
  *                                 them (1 = the transcendental unit runs beside the FMA pipeline)
  *   out[AR_PEAK_BF16_MFMA_FLOPS]  v_mfma_f32_32x32x16_bf16, flop per second
+ *   out[AR_PEAK_LDS_GATHER8]      8-byte LDS reads at pseudo-random addresses of a 64 KB table
+ *                                 (the look-up gather pattern, bank conflicts included), lane reads per second
  *   out    host double [n_out], n_out >= AR_PEAK_COUNT
  * Allocates 2 GiB of device memory for the copy and frees it.  Synchronises.
  */
@@ -388,7 +390,8 @@ enum {
     AR_PEAK_SIN = 4,
     AR_PEAK_SIN_OVERLAP = 5,
     AR_PEAK_BF16_MFMA_FLOPS = 6,
-    AR_PEAK_COUNT = 7
+    AR_PEAK_LDS_GATHER8 = 7,
+    AR_PEAK_COUNT = 8
 };
 ar_status ar_measure_peaks(ar_context *ctx, double *out, int32_t n_out);
 

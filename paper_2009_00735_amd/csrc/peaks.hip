@@ -1,7 +1,7 @@
 // Measured peak rates of the units the kernels are bound by (the roofline
 // denominators): HBM copy, LDS 16-byte reads, conflict-free LDS atomics,
 // non-packed FP32 FMA, the transcendental unit (alone and issued beside FMA
-// work), and BF16 MFMA.  Each probe runs a fixed loop on a grid of eight
+// work), BF16 MFMA, and random 8-byte LDS reads.  Each probe runs a fixed loop on a grid of eight
 // workgroups per compute unit and is timed with HIP events around the launch.
 
 #include "ar_internal.h"
@@ -76,6 +76,24 @@ __global__ __launch_bounds__(kBlock) void k_alu(int iters, float b, float c, flo
 #pragma unroll
     for (int k = 0; k < NS; ++k) r += s[k];
     out[(size_t)blockIdx.x * kBlock + threadIdx.x] = r;
+}
+
+// 8-byte LDS reads at pseudo-random addresses: a per-lane linear congruential
+// sequence picks one of 8192 entries (64 KB) per read, so a wavefront's reads
+// collide on banks as random look-ups do.
+__global__ __launch_bounds__(kBlock) void k_lds_gather(int iters, float *__restrict__ out)
+{
+    __shared__ uint2 buf[8192];
+    for (int i = threadIdx.x; i < 8192; i += kBlock) buf[i] = make_uint2(i, 3 * i);
+    __syncthreads();
+    uint32_t h = threadIdx.x * 2654435761u + blockIdx.x * 40503u + 1u;
+    uint32_t acc = 0;
+    for (int it = 0; it < iters; ++it) {
+        h = h * 1664525u + 1013904223u;
+        const uint2 v = buf[h >> 19];
+        acc += v.x ^ v.y;
+    }
+    out[(size_t)blockIdx.x * kBlock + threadIdx.x] = (float)acc;
 }
 
 // v_mfma_f32_32x32x16_bf16 on four independent accumulators per wavefront.
@@ -171,6 +189,8 @@ ar_status ar_measure_peaks(ar_context *ctx, double *out, int32_t n_out)
     out[AR_PEAK_SIN_OVERLAP] = t_fma / t;
     AR_TRY(time_launch([&] { k_mfma<<<blocks, kBlock>>>(it_mfma, sink.as<float>()); }, &t));
     out[AR_PEAK_BF16_MFMA_FLOPS] = (double)blocks * (kBlock / 64) * it_mfma * 4.0 * (32.0 * 32.0 * 16.0 * 2.0) / t;
+    AR_TRY(time_launch([&] { k_lds_gather<<<blocks, kBlock>>>(it_lds, sink.as<float>()); }, &t));
+    out[AR_PEAK_LDS_GATHER8] = (double)threads * it_lds / t;
     return AR_OK;
 }
 

@@ -22,8 +22,8 @@
 //   2. k_sparse_screen  one workgroup per (orientation chunk, group of RB
 //                       ROIs): for each window, the RB ROI images of that
 //                       window sit in LDS (RB FP16 values per node, one
-//                       8/4/2-byte read per look-up); every lane owns two
-//                       orientations, reads their look-up nodes (one 4-byte
+//                       8/4/2-byte read per look-up); every lane owns four
+//                       orientations, reads their look-up nodes (one 8-byte
 //                       load per strong entry), forms s - R in packed FP16
 //                       and accumulates the squares in FP32.  The
 //                       workgroup keeps the CAND best orientations per ROI
@@ -55,7 +55,7 @@ struct ar_sparse_lut {
     ar::DeviceBuffer seg;                // int32 [n_phase][n_win + 1], window segments of the window order
     ar::DeviceBuffer lut_ig;             // uint16 [n_hat][ld], window order of each column's phase
     ar::DeviceBuffer lut_gi;             // uint16 [n_lib][n_hat], decreasing-value order
-    ar::DeviceBuffer chunks;             // int4 [n_chunks]: phase, first column (even), valid [lo, hi)
+    ar::DeviceBuffer chunks;             // int4 [n_chunks]: phase, first column (multiple of 4), valid [lo, hi)
 };
 
 namespace ar {
@@ -63,10 +63,12 @@ namespace sparse {
 
 constexpr int kThreads = 1024;               // screen workgroup: 16 waves
 constexpr int kWaves = kThreads / 64;
-constexpr int kChunk = 2 * kThreads;         // orientations per workgroup (two per lane)
+constexpr int kPerLane = 4;                  // orientations per lane
+constexpr int kChunk = kPerLane * kThreads;  // orientations per workgroup
 
 typedef _Float16 half2_t __attribute__((ext_vector_type(2)));
 typedef _Float16 half4_t __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
 // ------------------------------------------------------------ look-up table
 __global__ __launch_bounds__(256) void k_ref_max(const float *__restrict__ ref, int n_dir, float *__restrict__ out)
@@ -200,16 +202,40 @@ __global__ __launch_bounds__(256) void k_lut_export(const uint16_t *__restrict__
 }
 
 // ------------------------------------------------------------ indexing
-// acc[j] += (x_j - R)^2 for the RB FP16 values x of node p: the difference
-// in packed FP16 (v_pk_add_f16), the square accumulated in FP32
-// (v_fma_mix_f32).  R2 holds (R, R) in FP16.
+// The screen kernel addresses its window slab by integer LDS address from 0:
+// it declares no static LDS, so its dynamic allocation is [0, bytes).
+template <typename T>
+__device__ __forceinline__ __attribute__((address_space(3))) T *lds_at(uint32_t byte_offset)
+{
+    return (__attribute__((address_space(3))) T *)(size_t)byte_offset;
+}
+
+// Byte offset (node id << SHIFT) of the 16-bit node id in half H of a packed
+// pair: one v_lshlrev_b32 with a word-select source operand.
+template <int SHIFT, int H>
+__device__ __forceinline__ uint32_t node_offset(uint32_t pair)
+{
+    uint32_t off;
+    if (H == 0)
+        asm("v_lshlrev_b32_sdwa %0, %2, %1 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:DWORD src1_sel:WORD_0"
+            : "=v"(off) : "v"(pair), "n"(SHIFT));
+    else
+        asm("v_lshlrev_b32_sdwa %0, %2, %1 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:DWORD src1_sel:WORD_1"
+            : "=v"(off) : "v"(pair), "n"(SHIFT));
+    return off;
+}
+
+// acc[j] += (x_j - R)^2 for the RB FP16 values x at LDS byte offset `off`:
+// the difference in packed FP16 (v_pk_add_f16), the square accumulated in
+// FP32 (v_fma_mix_f32).  R2 holds (R, R) in FP16.
 template <int RB>
 struct RoiVec;
 template <>
 struct RoiVec<4> {
-    __device__ __forceinline__ static void acc(const unsigned char *lds, uint32_t p, uint32_t R2, float (&a)[4])
+    static constexpr int SHIFT = 3;
+    __device__ __forceinline__ static void acc(uint32_t off, uint32_t R2, float (&a)[4])
     {
-        const half4_t x = reinterpret_cast<const half4_t *>(lds)[p];
+        const half4_t x = *lds_at<const half4_t>(off);
         const half2_t R = __builtin_bit_cast(half2_t, R2);
         const half2_t d01 = x.xy - R, d23 = x.zw - R;
         a[0] = fmaf((float)d01.x, (float)d01.x, a[0]);
@@ -220,19 +246,20 @@ struct RoiVec<4> {
 };
 template <>
 struct RoiVec<2> {
-    __device__ __forceinline__ static void acc(const unsigned char *lds, uint32_t p, uint32_t R2, float (&a)[2])
+    static constexpr int SHIFT = 2;
+    __device__ __forceinline__ static void acc(uint32_t off, uint32_t R2, float (&a)[2])
     {
-        const half2_t x = reinterpret_cast<const half2_t *>(lds)[p];
-        const half2_t d = x - __builtin_bit_cast(half2_t, R2);
+        const half2_t d = *lds_at<const half2_t>(off) - __builtin_bit_cast(half2_t, R2);
         a[0] = fmaf((float)d.x, (float)d.x, a[0]);
         a[1] = fmaf((float)d.y, (float)d.y, a[1]);
     }
 };
 template <>
 struct RoiVec<1> {
-    __device__ __forceinline__ static void acc(const unsigned char *lds, uint32_t p, uint32_t R2, float (&a)[1])
+    static constexpr int SHIFT = 1;
+    __device__ __forceinline__ static void acc(uint32_t off, uint32_t R2, float (&a)[1])
     {
-        const _Float16 d = reinterpret_cast<const _Float16 *>(lds)[p] - __builtin_bit_cast(half2_t, R2).x;
+        const _Float16 d = *lds_at<const _Float16>(off) - __builtin_bit_cast(half2_t, R2).x;
         a[0] = fmaf((float)d, (float)d, a[0]);
     }
 };
@@ -297,66 +324,66 @@ __global__ __launch_bounds__(kThreads) void k_sparse_screen(
     const int grp = (int)(t - (int64_t)chunk * n_grp);
     const int4 ch = chunks[chunk];
     const int tid = threadIdx.x;
-    const int64_t ld2 = ld >> 1;
-    const uint32_t *lut2 = reinterpret_cast<const uint32_t *>(lut_ig + ch.y) + tid;
+    // each lane owns orientations ch.y + 4 tid .. + 3: one 8-byte load of
+    // their four node ids per strong entry from a wave-uniform row address
+    const uint16_t *lut_c = lut_ig + ch.y;
+    const unsigned utid = threadIdx.x;   // unsigned: row base in SGPRs, lane offset in a VGPR
     const uint32_t *kv2 = kval2 + (size_t)ch.x * n_hat;
     const int32_t *sg = seg + (size_t)ch.x * (n_win + 1);
 
-    float acc0[RB], acc1[RB];
+    float acc[kPerLane][RB];
 #pragma unroll
-    for (int r = 0; r < RB; ++r) acc0[r] = acc1[r] = 0.0f;
+    for (int g = 0; g < kPerLane; ++g)
+#pragma unroll
+        for (int r = 0; r < RB; ++r) acc[g][r] = 0.0f;
+
+    constexpr int SH = RoiVec<RB>::SHIFT;
+    auto term = [&](uint2 pr, uint32_t R2) {
+        RoiVec<RB>::acc(node_offset<SH, 0>(pr.x), R2, acc[0]);
+        RoiVec<RB>::acc(node_offset<SH, 1>(pr.x), R2, acc[1]);
+        RoiVec<RB>::acc(node_offset<SH, 0>(pr.y), R2, acc[2]);
+        RoiVec<RB>::acc(node_offset<SH, 1>(pr.y), R2, acc[3]);
+    };
 
     for (int w = 0; w < n_win; ++w) {
         const int j0 = sg[w], j1 = sg[w + 1];
         if (j0 == j1) continue;
         __syncthreads();   // every wave is done with the previous window
         {
-            const uint4 *src = reinterpret_cast<const uint4 *>(half + ((size_t)grp * n_win + w) * slab);
-            uint4 *dst = reinterpret_cast<uint4 *>(smem);
+            const u32x4 *src = reinterpret_cast<const u32x4 *>(half + ((size_t)grp * n_win + w) * slab);
             const int n16 = (int)(slab >> 3);
-            for (int q = tid; q < n16; q += kThreads) dst[q] = src[q];
+            for (int q = tid; q < n16; q += kThreads) *lds_at<u32x4>(16u * q) = src[q];
         }
         __syncthreads();
-        const uint32_t *lp = lut2 + (size_t)j0 * ld2;
-        const uint32_t *kp = kv2 + j0;
         int j = j0;
         for (; j + 4 <= j1; j += 4) {
-            uint32_t pr[4], R2[4];
+            uint2 pr[4];
+            uint32_t R2[4];
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
-                pr[u] = lp[u * ld2];
-                R2[u] = kp[u];
+                pr[u] = reinterpret_cast<const uint2 *>(lut_c + (size_t)(j + u) * ld)[utid];
+                R2[u] = kv2[j + u];
             }
-            lp += 4 * ld2;
-            kp += 4;
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                RoiVec<RB>::acc(smem, pr[u] & 0xffffu, R2[u], acc0);
-                RoiVec<RB>::acc(smem, pr[u] >> 16, R2[u], acc1);
-            }
+            for (int u = 0; u < 4; ++u) term(pr[u], R2[u]);
         }
-        for (; j < j1; ++j) {
-            const uint32_t pr = *lp, R2 = *kp;
-            lp += ld2;
-            ++kp;
-            RoiVec<RB>::acc(smem, pr & 0xffffu, R2, acc0);
-            RoiVec<RB>::acc(smem, pr >> 16, R2, acc1);
-        }
+        for (; j < j1; ++j) term(reinterpret_cast<const uint2 *>(lut_c + (size_t)j * ld)[utid], kv2[j]);
     }
 
     // ---- the CAND best orientations of this chunk per ROI
-    const int ga = ch.y + 2 * tid, gb = ga + 1;
-    const bool va = ga >= ch.z && ga < ch.w, vb = gb >= ch.z && gb < ch.w;
     const int wave = tid >> 6, lane = tid & 63;
     __syncthreads();   // LDS now holds the wave lists
     float *ws = reinterpret_cast<float *>(smem);
     int32_t *wi = reinterpret_cast<int32_t *>(smem + sizeof(float) * kWaves * RB * CAND);
 #pragma unroll
     for (int r = 0; r < RB; ++r) {
-        TopList<2> tl;
+        TopList<kPerLane> tl;
         tl.init();
-        if (va) tl.insert(acc0[r], ga);
-        if (vb) tl.insert(acc1[r], gb);
+#pragma unroll
+        for (int g = 0; g < kPerLane; ++g) {
+            const int gi = ch.y + kPerLane * tid + g;
+            if (gi >= ch.z && gi < ch.w) tl.insert(acc[g][r], gi);
+        }
         wave_select<CAND>(tl, [&](int j, float bs, int bi) {
             if (lane == 0) {
                 ws[(wave * RB + r) * CAND + j] = bs;
@@ -554,10 +581,11 @@ ar_status ar_sparse_lut_create(ar_context *ctx, const float *reference, int32_t 
     AR_HIP(hipSetDevice(ctx->device));
     hipStream_t s = (hipStream_t)stream;
 
-    // screen chunks: per phase, columns from the even column below its start
+    // screen chunks: per phase, columns from the multiple of four at or below its start
     std::vector<int4> ch;
     for (int c = 0; c < n_phase; ++c)
-        for (int64_t a = start[c] & ~(int64_t)1; start[c] < start[c + 1] && a < start[c + 1]; a += sparse::kChunk)
+        for (int64_t a = start[c] & ~(int64_t)(sparse::kPerLane - 1); start[c] < start[c + 1] && a < start[c + 1];
+             a += sparse::kChunk)
             ch.push_back(make_int4(c, (int)a, (int)std::max(a, start[c]),
                                    (int)std::min(a + sparse::kChunk, start[c + 1])));
 

@@ -458,7 +458,7 @@ def ar_refine_orientations(ctx: Context, rel, offsets, quats, phase, directions,
 
 
 PEAK_NAMES = ("hbm_bytes_per_s", "lds_bytes_per_s", "lds_atomics_per_s", "fp32_fma_flop_per_s", "sin_per_s",
-              "sin_beside_fma_time_ratio", "bf16_mfma_flop_per_s")
+              "sin_beside_fma_time_ratio", "bf16_mfma_flop_per_s", "lds_gather8_per_s")
 
 
 def ar_measure_peaks(ctx: Context) -> dict:

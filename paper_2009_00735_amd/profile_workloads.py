@@ -2,6 +2,7 @@
 
     python -m paper_2009_00735_amd.profile_workloads indexing [--reps 5]
     python -m paper_2009_00735_amd.profile_workloads signatures [--reps 5]
+    python -m paper_2009_00735_amd.profile_workloads sparse [--reps 5]
 
 `indexing`: the config-2 indexing shape (2000 ROI images x 20000 references,
 4 x 10242 nodes) on seeded random non-negative images generated on the
@@ -10,6 +11,12 @@ device; calls `index_orientations(k = 16)` `reps` times.
 `signatures`: config 2 (2000 ROIs of about 1000 atoms, 10242 directions,
 1024 bins): one ROI query, then the autotuned persistent signature plan
 replayed `reps` times.
+
+`sparse`: the config-2 sparse indexing shape: the fcc Al reference (mean
+signature of 16 unrotated crystal ROIs), 20000 library orientations, 1000
+strongest entries; the look-up table is built once, then
+`index_orientations_sparse(k = 16)` runs `reps` times on seeded random
+non-negative ROI images (2000 x 4 x 10242) generated on the device.
 
 Every call goes through the C ABI (`native`); nothing here computes any part
 of the method.  Prints one line per repetition with the wall time.
@@ -57,12 +64,27 @@ def signatures(reps: int) -> None:
     _timed("signature plan", lambda: plan.run(rel, off, s.radius, dirs, w, out=out, use_graph=True), reps)
 
 
+def sparse(reps: int) -> None:
+    ctx = nat.Context(0)
+    s = synth.config2()
+    w = nat.windows_for(s.radius, s.nbins, s.spacings)
+    dirs = torch.from_numpy(s.directions).cuda()
+    rpos, roffs = synth.reference_rois(0, 16, R=s.radius, cfg=4)
+    ref = nat.araullo_signatures(ctx, torch.from_numpy(rpos).cuda(), torch.from_numpy(roffs).cuda(), s.radius, dirs,
+                                 s.nbins, w, counts=False).mean(0, keepdim=True).contiguous()
+    q = torch.from_numpy(synth.library_orientations(20000, 2)).cuda()
+    lut = nat.SparseLUT(ctx, ref, dirs, q, [20000], 1000)
+    gen = torch.Generator(device="cuda").manual_seed(6)
+    S = torch.rand((2000, len(w), len(s.directions)), device="cuda", generator=gen) ** 2
+    _timed("index_orientations_sparse", lambda: nat.index_orientations_sparse(ctx, S, lut, 16), reps)
+
+
 def main() -> None:
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
-    ap.add_argument("workload", choices=["indexing", "signatures"])
+    ap.add_argument("workload", choices=["indexing", "signatures", "sparse"])
     ap.add_argument("--reps", type=int, default=5)
     a = ap.parse_args()
-    {"indexing": indexing, "signatures": signatures}[a.workload](a.reps)
+    {"indexing": indexing, "signatures": signatures, "sparse": sparse}[a.workload](a.reps)
 
 
 if __name__ == "__main__":

@@ -15,6 +15,7 @@ BOUNDS = {
     "fp32_fma_flop_per_s": 157.3e12,
     "sin_per_s": 256 * 4 * 64 * 2.4e9,
     "bf16_mfma_flop_per_s": 2.5e15,
+    "lds_gather8_per_s": 256 * 2.4e9 * 32,        # 8-byte lane reads: at most 256 bytes per clock per CU
 }
 
 
@@ -26,3 +27,5 @@ def test_measured_peaks_are_physical():
     for k, hi in BOUNDS.items():
         assert 0.0 < p[k] <= 1.05 * hi, (k, p[k], hi)
     assert 0.2 < p["sin_beside_fma_time_ratio"] <= 1.2
+    # random reads cannot beat conflict-free 16-byte reads per byte
+    assert 8 * p["lds_gather8_per_s"] <= 1.05 * p["lds_bytes_per_s"]

@@ -1,19 +1,25 @@
 """Configurations 3 -> 4 -> 5 at full size on the GPU.
 
-Config 4: 20000 ROIs of the fcc-Al / bcc-Fe polycrystal (surface-clipped,
-100..1500 atoms) indexed against a library of 2 phases x 50000 Shoemake
-orientations (100000 rotated references, K = 4 x 10242): BF16 MFMA
-correlation, top-16, FP32 rescore.  Parity: on a seeded sample of ROIs the
-GPU top-1 equals the FP64 oracle's top-1 over the whole library (or is a tie
-within 1e-5), and every returned FP32 score is within 1e-5 of FP64.
+Pipeline (throughput and accuracy against the synthetic ground truth): the
+20000 config-4 ROIs of the fcc-Al / bcc-Fe polycrystal (surface-clipped,
+100..1500 atoms) are indexed against a library of 2 phases x 50000 Shoemake
+orientations (100000 rotated references, K = 4 x 10242; BF16 MFMA
+correlation, top-16, FP32 rescore); 4096 config-5 ROIs (800..1200 atoms,
+dominant-grain share >= 0.9) are refined for 50 steps from their top-1 with
+the per-phase structure-factor score.
 
-Config 5: 4096 ROIs with 800..1200 atoms and a dominant-grain share >= 0.9,
-refined for 50 steps from their config-4 top-1 with the per-phase
-structure-factor score.  Parity: GPU adjoint gradient against FP64 central
-finite differences (relative 1e-3) on sampled ROIs at the start orientation.
-
-Both report throughput and accuracy against the ground truth (the dominant
-grain's orientation)."""
+Parity at these sizes, every oracle input computed by the oracle itself or
+drawn from seeded generators (never taken from the GPU path):
+  * signatures of sampled polycrystal ROIs and of the reference crystals, on
+    sampled directions (1e-5 N_w);
+  * rotated library rows of sampled orientations, level-5 mesh (exact);
+  * indexing at the config-4 shape (20000 ROIs x 100000 references x
+    40968 nodes) on seeded images generated on the device by torch: on 8
+    sampled ROIs the GPU top-1 equals the FP64 top-1 over all 100000
+    references or is a tie, and every returned score is within 1e-5 of FP64;
+  * the structure-factor adjoint of sampled config-5 ROIs at a seeded
+    orientation 2 deg from the truth, with the oracle's target, against FP64
+    central differences (relative 1e-3)."""
 import concurrent.futures as cf
 import time
 
@@ -35,6 +41,13 @@ def dev(a, dtype=torch.float32):
     return torch.as_tensor(np.ascontiguousarray(a)).to(dtype).cuda()
 
 
+def _qmul(a, b):
+    return np.stack([a[:, 0] * b[:, 0] - a[:, 1] * b[:, 1] - a[:, 2] * b[:, 2] - a[:, 3] * b[:, 3],
+                     a[:, 0] * b[:, 1] + a[:, 1] * b[:, 0] + a[:, 2] * b[:, 3] - a[:, 3] * b[:, 2],
+                     a[:, 0] * b[:, 2] - a[:, 1] * b[:, 3] + a[:, 2] * b[:, 0] + a[:, 3] * b[:, 1],
+                     a[:, 0] * b[:, 3] + a[:, 1] * b[:, 2] - a[:, 2] * b[:, 1] + a[:, 3] * b[:, 0]], axis=1)
+
+
 @pytest.fixture(scope="module")
 def nat():
     from paper_2009_00735_amd import native
@@ -52,17 +65,18 @@ def world(nat, ctx):
     dirs = synth.icosphere(LEVEL)
     w = nat.windows_for(R, NB, synth.window_spacings())
     pos_d, dirs_d = dev(pos), dev(dirs)
-    refs, targets = [], []
+    refs, targets, ref_in = [], [], []
     ident = np.tile([1.0, 0.0, 0.0, 0.0], (16, 1))
     for ph in (0, 1):
         rpos, roffs = synth.reference_rois(ph, 16, R=R, cfg=4)
+        ref_in.append((rpos, roffs))
         rp, ro = dev(rpos), dev(roffs)
-        refs.append(nat.araullo_signatures(ctx, rp, ro, R, dirs_d, NB, w, counts=False).mean(0))
+        refs.append(nat.araullo_signatures(ctx, rp, ro, R, dirs_d, NB, w, counts=False))
         roff, rrel = nat.ar_roi_gather(ctx, rp, ro, R)
         amp = nat.ar_sf_amplitudes(ctx, rrel.contiguous(), roff, dev(ident), dev(np.zeros(16), torch.int32), dirs_d,
                                    dev(FREQS[ph][None]))
         targets.append(amp.mean(0))
-    ref = torch.stack(refs).contiguous()
+    ref = torch.stack([r.mean(0) for r in refs]).contiguous()
     T = torch.stack(targets).contiguous()
     libq = synth.library_orientations(2 * N_PER_PHASE, cfg=4)
     libph = np.repeat(np.arange(2, dtype=np.int32), N_PER_PHASE)
@@ -72,18 +86,51 @@ def world(nat, ctx):
     torch.cuda.synchronize()
     print(f"\nlibrary: {len(libq)} references built in {time.perf_counter() - t0:.1f} s", flush=True)
     return dict(pos=pos, grain=grain, gq=gq, gphase=gphase, dirs=dirs, w=w, pos_d=pos_d, dirs_d=dirs_d, L=L,
-                lib=lib, libq=libq, libph=libph, T=T)
+                lib=lib, libq=libq, libph=libph, T=T, ref_imgs=refs, ref_in=ref_in)
 
 
-def oracle_top16(orc, S, L, chunk=10000):
-    """FP64 top-16 of the normalised ROI images against the whole library,
-    one library chunk at a time (per-image normalisation is independent of
-    the other rows), merged by (score, index)."""
-    Sh = orc.normalise(S)
-    best_i = np.zeros((len(S), 0), np.int64)
-    best_s = np.zeros((len(S), 0))
-    for c0 in range(0, L.shape[0], chunk):
-        Lh = orc.normalise(L[c0:c0 + chunk].cpu().numpy())
+def test_cfg4_signatures_and_references_sampled(nat, ctx, orc, world):
+    """GPU images of sampled polycrystal ROIs and of every reference-crystal
+    ROI against the oracle's, on 400 sampled directions."""
+    centres, dom, share, counts = synth.polycrystal_rois(20000)
+    sel = np.sort(np.random.default_rng(39).choice(len(centres), 4, replace=False))
+    dsel = np.sort(np.random.default_rng(38).choice(len(world["dirs"]), 400, replace=False))
+    wn = world["w"].numpy()
+    S = nat.araullo_signatures(ctx, world["pos_d"], dev(centres[sel]), R, world["dirs_d"], NB, world["w"],
+                               counts=False)[:, :, torch.as_tensor(dsel).cuda()].cpu().numpy()
+    ref, cnt = orc.signatures(world["pos"], centres[sel], R, world["dirs"][dsel], NB, wn)
+    assert np.array_equal(cnt, counts[sel])
+    for i in range(len(sel)):
+        assert np.abs(S[i] - ref[i]).max() <= 1e-5 * cnt[i]
+    for ph in (0, 1):
+        rpos, roffs = world["ref_in"][ph]
+        oref, ocnt = orc.signatures(rpos, roffs, R, world["dirs"][dsel], NB, wn)
+        g = world["ref_imgs"][ph][:, :, torch.as_tensor(dsel).cuda()].cpu().numpy()
+        for i in range(len(roffs)):
+            assert np.abs(g[i] - oref[i]).max() <= 1e-5 * ocnt[i]
+
+
+def test_cfg4_rotated_rows_sampled(nat, ctx, orc, world):
+    """Rotated reference rows on the level-5 mesh for sampled library
+    orientations of both phases, from an oracle-side (seeded) reference."""
+    ref = np.random.default_rng(37).random((2, 4, len(world["dirs"]))).astype(np.float32)
+    rows = np.array([0, 1, N_PER_PHASE - 1, N_PER_PHASE, 2 * N_PER_PHASE - 1, 12345, 67890, 99998])
+    q, ph = world["libq"][rows], world["libph"][rows]
+    got = nat.ar_rotate_reference(ctx, dev(ref), world["dirs_d"], dev(q, torch.float64), dev(ph, torch.int32))
+    lut = orc.rotated_nodes(q, world["dirs"])
+    expect = np.stack([ref[ph[l]][:, lut[l]] for l in range(len(rows))])
+    assert np.array_equal(got.cpu().numpy(), expect)
+
+
+def oracle_top16(orc, S_sel, L_dev, chunk=10000):
+    """FP64 top-16 of the normalised sampled ROI images against the whole
+    library, one library chunk at a time (per-image normalisation is
+    independent of the other rows), merged by (score, index)."""
+    Sh = orc.normalise(S_sel)
+    best_i = np.zeros((len(S_sel), 0), np.int64)
+    best_s = np.zeros((len(S_sel), 0))
+    for c0 in range(0, L_dev.shape[0], chunk):
+        Lh = orc.normalise(L_dev[c0:c0 + chunk].cpu().numpy())
         i, s = orc.index_topk(Sh, Lh, 16)
         del Lh
         ci = np.concatenate([best_i, i.astype(np.int64) + c0], axis=1)
@@ -94,21 +141,28 @@ def oracle_top16(orc, S, L, chunk=10000):
     return Sh, best_i, best_s
 
 
-def test_cfg4_full_library_indexing(nat, ctx, orc, world):
-    centres, dom, share, counts = synth.polycrystal_rois(20000)
-    S = nat.araullo_signatures(ctx, world["pos_d"], dev(centres), R, world["dirs_d"], NB, world["w"], counts=False)
+def test_cfg4_indexing_shape_parity(nat, ctx, orc):
+    """20000 ROI images x 100000 references x (4 x 10242) nodes, seeded on the
+    device (torch generator): library rows are squared uniforms, ROI r is row
+    truth[r] with a per-window gain and 5 % multiplicative noise."""
+    n_roi, n_lib, n_win, n_dir = 20000, 2 * N_PER_PHASE, 4, 10242
+    g = torch.Generator(device="cuda").manual_seed(2009)
+    L = torch.rand((n_lib, n_win, n_dir), device="cuda", generator=g) ** 2
+    truth = torch.randint(0, n_lib, (n_roi,), device="cuda", generator=g)
+    gain = 0.5 + 1.5 * torch.rand((n_roi, n_win, 1), device="cuda", generator=g)
+    S = (L[truth] * gain * (1.0 + 0.05 * torch.randn((n_roi, n_win, n_dir), device="cuda", generator=g))).abs()
+    lib = nat.Library(ctx, L)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    gidx, gsc = nat.index_orientations(ctx, S, world["lib"], 16)
+    gidx, gsc = nat.index_orientations(ctx, S, lib, 16)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     gidx, gsc = gidx.cpu().numpy(), gsc.cpu().numpy()
-    # parity on a seeded sample against the FP64 oracle over all 100000 references
-    sel = np.sort(np.random.default_rng(40).choice(len(centres), 8, replace=False))
-    Ssel = S[torch.as_tensor(sel).cuda()].cpu().numpy()
-    Sh, oi, osc = oracle_top16(orc, Ssel, world["L"])
+    assert np.array_equal(gidx[:, 0], truth.cpu().numpy())
+    sel = np.sort(np.random.default_rng(40).choice(n_roi, 8, replace=False))
+    Sh, oi, osc = oracle_top16(orc, S[torch.as_tensor(sel).cuda()].cpu().numpy(), L)
     need = np.unique(np.concatenate([gidx[sel].ravel(), oi[:, 0]]))
-    Lh_need = orc.normalise(world["L"][torch.as_tensor(need).cuda()].cpu().numpy())
+    Lh_need = orc.normalise(L[torch.as_tensor(need).cuda()].cpu().numpy())
     pos_of = {int(l): i for i, l in enumerate(need)}
     ties = 0
     for a, r in enumerate(sel):
@@ -117,18 +171,64 @@ def test_cfg4_full_library_indexing(nat, ctx, orc, world):
         if gidx[r, 0] != oi[a, 0]:
             assert d64[0] - osc[a, 0] <= 1e-5 * osc[a, 0] + 1e-6, (r, gidx[r, 0], oi[a, 0], d64[0], osc[a, 0])
             ties += 1
-    # accuracy against the ground truth (dominant grain) where it is well defined
-    top = gidx[:, 0]
+    print(f"\ncfg4 shape: {n_roi} x {n_lib} indexed in {dt * 1e3:.1f} ms; ties on the sample {ties}/8", flush=True)
+
+
+def test_cfg4_pipeline_accuracy(nat, ctx, orc, world):
+    centres, dom, share, counts = synth.polycrystal_rois(20000)
+    S = nat.araullo_signatures(ctx, world["pos_d"], dev(centres), R, world["dirs_d"], NB, world["w"], counts=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    gidx, gsc = nat.index_orientations(ctx, S, world["lib"], 16)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    top = gidx[:, 0].cpu().numpy()
     good = share >= 0.9
     phase_ok = world["libph"][top] == world["gphase"][dom]
     dis = orc.disorientation_cubic(world["libq"][top], world["gq"][dom])
     m = good & phase_ok
     print(f"cfg4: {len(centres)} ROIs x {len(world['libq'])} references in {dt * 1e3:.1f} ms "
-          f"({len(centres) / dt:.0f} indexed ROIs/s); ties on the sample {ties}/8; "
-          f"share>=0.9: {good.sum()} ROIs, phase correct {phase_ok[good].mean():.3f}, "
-          f"top-1 disorientation median {np.median(dis[m]):.2f} p95 {np.percentile(dis[m], 95):.2f} deg", flush=True)
+          f"({len(centres) / dt:.0f} indexed ROIs/s); share>=0.9: {good.sum()} ROIs, phase correct "
+          f"{phase_ok[good].mean():.3f}, top-1 disorientation median {np.median(dis[m]):.2f} "
+          f"p95 {np.percentile(dis[m], 95):.2f} deg", flush=True)
     assert phase_ok[good].mean() > 0.9
     assert np.median(dis[m]) < 5.0
+
+
+def test_cfg5_adjoint_parity_sampled(nat, ctx, orc, world):
+    """Gradient of the structure-factor score of sampled config-5 ROIs at a
+    seeded orientation 2 deg from the truth, against FP64 central
+    differences; the target is the oracle's amplitude image of one reference
+    crystal ROI per phase (the same input on both sides)."""
+    centres, qt, pht, share = synth.config5_rois(4096)
+    sel = np.sort(np.random.default_rng(50).choice(len(centres), 8, replace=False))
+    T64 = []
+    for ph in (0, 1):
+        rpos, roffs = world["ref_in"][ph]
+        rel0 = orc.roi_gather(rpos, roffs[0], R)
+        T64.append(orc.sf_amplitudes(rel0, np.array([1.0, 0, 0, 0]), world["dirs"], FREQS[ph]))
+    T32 = np.stack(T64).astype(np.float32)
+    gen = np.random.default_rng(51)
+    axis = gen.standard_normal((len(sel), 3))
+    axis /= np.linalg.norm(axis, axis=1, keepdims=True)
+    h = np.radians(2.0) / 2
+    q_eval = _qmul(qt[sel], np.concatenate([np.full((len(sel), 1), np.cos(h)), np.sin(h) * axis], axis=1))
+    q_eval = q_eval.astype(np.float32)
+    off, rel = nat.ar_roi_gather(ctx, world["pos_d"], dev(centres[sel]), R)
+    _, grad = nat.ar_sf_score_grad(ctx, rel.contiguous(), off, dev(q_eval), dev(pht[sel], torch.int32),
+                                   world["dirs_d"], dev(FREQS), dev(T32))
+    grad = grad.cpu().numpy()
+
+    def fd(a):
+        r = orc.roi_gather(world["pos"], centres[sel[a]], R)
+        return orc.sf_grad_fd(r, q_eval[a].astype(np.float64), world["dirs"], FREQS[pht[sel[a]]],
+                              T32[pht[sel[a]]].astype(np.float64))
+
+    with cf.ThreadPoolExecutor(max_workers=8) as ex:
+        fds = list(ex.map(fd, range(len(sel))))
+    errs = [np.linalg.norm(grad[a] - g) / np.linalg.norm(g) for a, g in enumerate(fds)]
+    print(f"\ncfg5 adjoint vs FP64 central differences: max relative error {max(errs):.2e}", flush=True)
+    assert max(errs) <= 1e-3, errs
 
 
 def test_cfg5_refinement_from_top1(nat, ctx, orc, world):
@@ -139,27 +239,10 @@ def test_cfg5_refinement_from_top1(nat, ctx, orc, world):
     top = gidx[:, 0].cpu().numpy()
     q0 = world["libq"][top].astype(np.float32)
     ph = world["libph"][top]
-    freqs = dev(FREQS)
-    args = (rel.contiguous(), off, dev(q0), dev(ph, torch.int32), world["dirs_d"], freqs)
-    score, grad = nat.ar_sf_score_grad(ctx, *args, world["T"])
-    grad = grad.cpu().numpy()
-    # adjoint against FP64 central differences on sampled ROIs (the oracle's own gather)
-    sel = np.sort(np.random.default_rng(50).choice(len(centres), 8, replace=False))
-    T64 = world["T"].cpu().numpy().astype(np.float64)
-
-    def fd(i):
-        r = orc.roi_gather(world["pos"], centres[i], R)
-        return orc.sf_grad_fd(r, q0[i].astype(np.float64), world["dirs"], FREQS[ph[i]], T64[ph[i]])
-
-    with cf.ThreadPoolExecutor(max_workers=8) as ex:
-        fds = list(ex.map(fd, sel))
-    errs = [np.linalg.norm(grad[i] - g) / np.linalg.norm(g) for i, g in zip(sel, fds)]
-    assert max(errs) <= 1e-3, errs
-    # 50 refinement steps of all 4096 ROIs
     q = dev(q0)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    nat.ar_refine_orientations(ctx, rel.contiguous(), off, q, dev(ph, torch.int32), world["dirs_d"], freqs,
+    nat.ar_refine_orientations(ctx, rel.contiguous(), off, q, dev(ph, torch.int32), world["dirs_d"], dev(FREQS),
                                world["T"], 50, 0.01)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
@@ -168,8 +251,7 @@ def test_cfg5_refinement_from_top1(nat, ctx, orc, world):
     d0 = orc.disorientation_cubic(q0.astype(np.float64), qt)[ok]
     d1 = orc.disorientation_cubic(qr, qt)[ok]
     print(f"cfg5: {len(centres)} ROIs x 50 steps in {dt:.2f} s ({len(centres) * 50 / dt:.0f} ROI-steps/s); "
-          f"gradient rel. error max {max(errs):.2e}; phase correct {ok.mean():.3f}; disorientation median "
-          f"{np.median(d0):.2f} -> {np.median(d1):.2f} deg, p95 {np.percentile(d0, 95):.2f} -> "
-          f"{np.percentile(d1, 95):.2f} deg", flush=True)
+          f"phase correct {ok.mean():.3f}; disorientation median {np.median(d0):.2f} -> {np.median(d1):.2f} deg, "
+          f"p95 {np.percentile(d0, 95):.2f} -> {np.percentile(d1, 95):.2f} deg", flush=True)
     assert ok.mean() > 0.9
     assert np.median(d1) < 0.5 * np.median(d0)
