@@ -92,6 +92,20 @@ ar_status ar_roi_gather(ar_context *ctx, const float *positions, int64_t n_atoms
                         void *stream);
 
 /*
+ * ROI query restricted to atom types (Sec. 3.1: the L1_2 Al3Sc case needs
+ * one amplitude spectrum per sub-lattice; supplement, Al-Li-Mg specimens:
+ * references for the aluminium and the lithium sub-lattices of Al3Li).  As
+ * ar_roi_gather, and an atom is gathered only if its type t = types[i]
+ * satisfies 0 <= t < 64 and bit t of type_mask is set.
+ *   types      device int32 [n_atoms]
+ * ar_roi_gather equals this call with every type accepted.  Synchronises.
+ */
+ar_status ar_roi_gather_typed(ar_context *ctx, const float *positions, const int32_t *types,
+                              int64_t n_atoms, const float *centres, int64_t n_roi, float radius,
+                              uint64_t type_mask, int64_t *offsets, float *rel, int64_t cap,
+                              int64_t *total, void *stream);
+
+/*
  * Real-space signatures (Sec. 2.2, RSP paragraph and Eq. (1); supplement,
  * "Controlled windowing of the SDMs" and reconstruction parameters).  For
  * every ROI r and direction v: the ROI's atoms are projected on v and binned
@@ -118,6 +132,26 @@ ar_status araullo_signatures(ar_context *ctx, const float *positions, int64_t n_
                              const float *directions, int32_t n_dir, int32_t nbins,
                              const int32_t *windows, int32_t n_win,
                              float *images, int32_t *roi_counts, void *stream);
+
+/*
+ * Sub-lattice signatures (Sec. 3.1, the Al3Sc discussion: one signature per
+ * atom type set; supplement, Al-Li-Mg specimens): for every channel c the
+ * signatures of araullo_signatures computed from the atoms whose type is in
+ * type_masks[c] (as ar_roi_gather_typed), stacked per ROI:
+ *   images[r][c][w][v]     device float [n_roi][n_ch][n_win][n_dir], out
+ *   roi_counts[r][c]       device int32 [n_roi][n_ch] or NULL, out
+ *   types                  device int32 [n_atoms]
+ *   type_masks             host uint64 [n_ch], 1 <= n_ch <= 64
+ * The (channel, window) pairs form the window axis the indexing calls read
+ * (n_ch * n_win windows), so the stacked images index directly against
+ * stacked references.  Channel images are bit-identical to araullo_signatures
+ * on the filtered atoms.  Synchronises.
+ */
+ar_status araullo_signatures_typed(ar_context *ctx, const float *positions, const int32_t *types,
+                                   int64_t n_atoms, const float *centres, int64_t n_roi, float radius,
+                                   const uint64_t *type_masks, int32_t n_ch, const float *directions,
+                                   int32_t n_dir, int32_t nbins, const int32_t *windows, int32_t n_win,
+                                   float *images, int32_t *roi_counts, void *stream);
 
 /*
  * Same Eq. (1) histograms and spectra as araullo_signatures, written out in

@@ -63,6 +63,10 @@
  *      window of the strong entry is carried along (the paper has one window
  *      per signature).  R(q) rather than R(q)^T: a reference feature at node
  *      u appears at R(q) n_u in the image rotated as in R10.
+ *  R13 sub-lattice signatures (Sec. 3.1, the Al3Sc discussion; supplement,
+ *      Al-Li-Mg specimens): the signature of a set of atom types is the
+ *      signature computed from the atoms of those types only (the selection
+ *      itself lives in the NumPy front end, signatures_typed).
  */
 #include <math.h>
 #include <stdint.h>

@@ -149,6 +149,22 @@ def signatures(positions, centres, radius: float, directions, nbins: int, window
     return img, cnt
 
 
+def signatures_typed(positions, types, type_masks, centres, radius: float, directions, nbins: int, windows,
+                     threads: Optional[int] = None) -> Tuple[np.ndarray, np.ndarray]:
+    """Reading R13: channel c of every ROI is the signature of the atoms whose
+    type t has bit t set in type_masks[c] (0 <= t < 64).
+    Returns (images [n_roi][n_ch][n_win][n_dir] float64, counts [n_roi][n_ch])."""
+    t = np.asarray(types, np.int64)
+    p = np.asarray(positions)
+    imgs, cnts = [], []
+    for m in type_masks:
+        ok = (t >= 0) & (t < 64) & (((np.uint64(m) >> t.clip(0, 63).astype(np.uint64)) & np.uint64(1)) == 1)
+        img, cnt = signatures(p[ok], centres, radius, directions, nbins, windows, threads)
+        imgs.append(img)
+        cnts.append(cnt)
+    return np.stack(imgs, axis=1), np.stack(cnts, axis=1)
+
+
 def sdm_debug(rel, radius: float, directions, nbins: int, spectra: bool = True):
     """Histograms [n_dir][nbins] and (if spectra) amplitudes [n_dir][nbins/2+1]."""
     rel = _f32(rel).reshape(-1, 3)

@@ -77,6 +77,8 @@ struct ar_context {
         g_bbox, g_offsets;
     // gathered CSR used by the position-taking signature entry points
     ar::DeviceBuffer s_rel;
+    // one channel's images in the typed-signature entry point
+    ar::DeviceBuffer s_typed;
     // correlation tile: per-wave 32x32 MFMA tiles (wtm x wtn) and K step
     int corr_waves = 8, corr_wtm = 4, corr_wtn = 2, corr_bk = 32;
     // indexing workspace
@@ -105,7 +107,7 @@ struct ar_library {
 
 namespace ar {
 // internal entry points used across translation units
-ar_status gather_csr(ar_context *ctx, const float *positions, int64_t n_atoms, const float *centres,
-                     int64_t n_roi, float radius, int64_t *offsets, float *rel, int64_t cap,
-                     int64_t *total, hipStream_t stream);
+ar_status gather_csr(ar_context *ctx, const float *positions, const int32_t *types, int64_t n_atoms,
+                     const float *centres, int64_t n_roi, float radius, uint64_t type_mask, int64_t *offsets,
+                     float *rel, int64_t cap, int64_t *total, hipStream_t stream);
 }

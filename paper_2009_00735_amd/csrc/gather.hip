@@ -77,21 +77,32 @@ __global__ __launch_bounds__(256) void k_cell_bounds(const uint32_t *__restrict_
     for (int64_t c = prev + 1; c <= cur; ++c) cell_start[c] = (int32_t)i;
 }
 
-__global__ __launch_bounds__(256) void k_sorted_pos(const float *__restrict__ pos, const int32_t *__restrict__ idx,
+// Sorted positions; the 4th component carries the atom type's bits (0 when
+// the call has no types).
+__global__ __launch_bounds__(256) void k_sorted_pos(const float *__restrict__ pos, const int32_t *__restrict__ types,
+                                                    const int32_t *__restrict__ idx,
                                                     const int32_t *__restrict__ cell_start, uint32_t ncells,
                                                     float4 *__restrict__ out)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= cell_start[ncells]) return;
     const int64_t a = idx[i];
-    out[i] = make_float4(pos[3 * a], pos[3 * a + 1], pos[3 * a + 2], 0.f);
+    out[i] = make_float4(pos[3 * a], pos[3 * a + 1], pos[3 * a + 2], __int_as_float(types ? types[a] : 0));
+}
+
+// Atom type t is accepted iff 0 <= t < 64 and bit t of the mask is set.
+__device__ __forceinline__ bool type_accepted(float w, uint64_t mask)
+{
+    const uint32_t t = (uint32_t)__float_as_int(w);
+    return t < 64u && ((mask >> t) & 1ull);
 }
 
 // One wavefront per ROI.  FILL == false: count; FILL == true: write rows.
 template <bool FILL>
 __global__ __launch_bounds__(256) void k_roi_query(const float4 *__restrict__ spos, const int32_t *__restrict__ cell_start,
                                                    Grid g, const float *__restrict__ centres, int64_t n_roi,
-                                                   float radius, float R2, int64_t *__restrict__ counts_or_offsets,
+                                                   float radius, float R2, uint64_t type_mask,
+                                                   int64_t *__restrict__ counts_or_offsets,
                                                    int64_t *__restrict__ offsets0, float4 *__restrict__ rel)
 {
     const int lane = threadIdx.x & 63;
@@ -121,7 +132,7 @@ __global__ __launch_bounds__(256) void k_roi_query(const float4 *__restrict__ sp
                     dx = p.x - cx;
                     dy = p.y - cy;
                     dz = p.z - cz;
-                    in = fmaf(dz, dz, fmaf(dy, dy, dx * dx)) <= R2;
+                    in = fmaf(dz, dz, fmaf(dy, dy, dx * dx)) <= R2 && type_accepted(p.w, type_mask);
                 }
                 const uint64_t m = __ballot(in);
                 if (FILL && in) rel[base + count + __popcll(m & lt_mask)] = make_float4(dx, dy, dz, 0.f);
@@ -133,8 +144,9 @@ __global__ __launch_bounds__(256) void k_roi_query(const float4 *__restrict__ sp
 
 }  // namespace
 
-ar_status gather_csr(ar_context *ctx, const float *positions, int64_t n_atoms, const float *centres, int64_t n_roi,
-                     float radius, int64_t *offsets, float *rel, int64_t cap, int64_t *total, hipStream_t stream)
+ar_status gather_csr(ar_context *ctx, const float *positions, const int32_t *types, int64_t n_atoms,
+                     const float *centres, int64_t n_roi, float radius, uint64_t type_mask, int64_t *offsets, float *rel,
+                     int64_t cap, int64_t *total, hipStream_t stream)
 {
     AR_CHECK(ctx != nullptr, "context is NULL");
     AR_CHECK(n_atoms >= 0 && n_atoms < (int64_t)INT32_MAX, "n_atoms must be in [0, 2^31-1)");
@@ -204,7 +216,7 @@ ar_status gather_csr(ar_context *ctx, const float *positions, int64_t n_atoms, c
                                                                       ctx->g_cell_start.as<int32_t>());
     AR_HIP(hipGetLastError());
     if (n > 0) {
-        k_sorted_pos<<<(unsigned)((n + 255) / 256), 256, 0, stream>>>(positions, ctx->g_vals2.as<int32_t>(),
+        k_sorted_pos<<<(unsigned)((n + 255) / 256), 256, 0, stream>>>(positions, types, ctx->g_vals2.as<int32_t>(),
                                                                      ctx->g_cell_start.as<int32_t>(), ncells,
                                                                      ctx->g_sorted.as<float4>());
         AR_HIP(hipGetLastError());
@@ -213,8 +225,8 @@ ar_status gather_csr(ar_context *ctx, const float *positions, int64_t n_atoms, c
     const unsigned qblocks = (unsigned)((n_roi + 3) / 4);
     AR_TRY(ctx->g_counts.reserve(sizeof(int64_t) * n_roi));
     k_roi_query<false><<<qblocks, 256, 0, stream>>>(ctx->g_sorted.as<float4>(), ctx->g_cell_start.as<int32_t>(), g,
-                                                   centres, n_roi, radius, R2, ctx->g_counts.as<int64_t>(), offsets,
-                                                   nullptr);
+                                                   centres, n_roi, radius, R2, type_mask, ctx->g_counts.as<int64_t>(),
+                                                   offsets, nullptr);
     AR_HIP(hipGetLastError());
     {
         size_t tb = ctx->g_temp.bytes;
@@ -228,7 +240,8 @@ ar_status gather_csr(ar_context *ctx, const float *positions, int64_t n_atoms, c
     if (!rel) return AR_OK;
     AR_CHECK(cap >= tot, "rel capacity %lld is smaller than the %lld gathered rows", (long long)cap, (long long)tot);
     k_roi_query<true><<<qblocks, 256, 0, stream>>>(ctx->g_sorted.as<float4>(), ctx->g_cell_start.as<int32_t>(), g,
-                                                  centres, n_roi, radius, R2, offsets, nullptr, (float4 *)rel);
+                                                  centres, n_roi, radius, R2, type_mask, offsets, nullptr,
+                                                  (float4 *)rel);
     AR_HIP(hipGetLastError());
     return AR_OK;
 }
@@ -239,6 +252,16 @@ extern "C" ar_status ar_roi_gather(ar_context *ctx, const float *positions, int6
                                    int64_t n_roi, float radius, int64_t *offsets, float *rel, int64_t cap,
                                    int64_t *total, void *stream)
 {
-    return ar::gather_csr(ctx, positions, n_atoms, centres, n_roi, radius, offsets, rel, cap, total,
+    return ar::gather_csr(ctx, positions, nullptr, n_atoms, centres, n_roi, radius, ~0ull, offsets, rel, cap, total,
+                          (hipStream_t)stream);
+}
+
+extern "C" ar_status ar_roi_gather_typed(ar_context *ctx, const float *positions, const int32_t *types,
+                                         int64_t n_atoms, const float *centres, int64_t n_roi, float radius,
+                                         uint64_t type_mask, int64_t *offsets, float *rel, int64_t cap,
+                                         int64_t *total, void *stream)
+{
+    AR_CHECK(n_atoms == 0 || types != nullptr, "types is NULL");
+    return ar::gather_csr(ctx, positions, types, n_atoms, centres, n_roi, radius, type_mask, offsets, rel, cap, total,
                           (hipStream_t)stream);
 }

@@ -485,16 +485,16 @@ ar_status araullo_signatures_csr(ar_context *ctx, const float *rel, const int64_
                             1024, 256, (hipStream_t)stream);
 }
 
-static ar_status gather_into_ctx(ar_context *ctx, const float *positions, int64_t n_atoms, const float *centres,
-                                 int64_t n_roi, float radius, ar::DeviceBuffer &offs, ar::DeviceBuffer &rel,
-                                 int64_t *total, hipStream_t stream)
+static ar_status gather_into_ctx(ar_context *ctx, const float *positions, const int32_t *types, int64_t n_atoms,
+                                 const float *centres, int64_t n_roi, float radius, uint64_t type_mask,
+                                 ar::DeviceBuffer &offs, ar::DeviceBuffer &rel, int64_t *total, hipStream_t stream)
 {
     AR_TRY(offs.reserve(sizeof(int64_t) * (n_roi + 1)));
-    AR_TRY(ar::gather_csr(ctx, positions, n_atoms, centres, n_roi, radius, offs.as<int64_t>(), nullptr, 0, total,
-                          stream));
+    AR_TRY(ar::gather_csr(ctx, positions, types, n_atoms, centres, n_roi, radius, type_mask, offs.as<int64_t>(),
+                          nullptr, 0, total, stream));
     AR_TRY(rel.reserve(sizeof(float4) * (*total + 1)));
-    AR_TRY(ar::gather_csr(ctx, positions, n_atoms, centres, n_roi, radius, offs.as<int64_t>(), rel.as<float>(),
-                          *total, total, stream));
+    AR_TRY(ar::gather_csr(ctx, positions, types, n_atoms, centres, n_roi, radius, type_mask, offs.as<int64_t>(),
+                          rel.as<float>(), *total, total, stream));
     return AR_OK;
 }
 
@@ -509,7 +509,8 @@ ar_status araullo_signatures(ar_context *ctx, const float *positions, int64_t n_
     AR_HIP(hipSetDevice(ctx->device));
     hipStream_t s = (hipStream_t)stream;
     int64_t total = 0;
-    AR_TRY(gather_into_ctx(ctx, positions, n_atoms, centres, n_roi, radius, ctx->g_offsets, ctx->s_rel, &total, s));
+    AR_TRY(gather_into_ctx(ctx, positions, nullptr, n_atoms, centres, n_roi, radius, ~0ull, ctx->g_offsets,
+                           ctx->s_rel, &total, s));
     // register chunk sized to the largest ROI (read back once; the gather
     // already synchronised)
     std::vector<int64_t> off(n_roi + 1);
@@ -528,6 +529,50 @@ ar_status araullo_signatures(ar_context *ctx, const float *positions, int64_t n_
                             n_dir, nbins, ws, images, nullptr, nullptr, cap, 256, s);
 }
 
+ar_status araullo_signatures_typed(ar_context *ctx, const float *positions, const int32_t *types, int64_t n_atoms,
+                                   const float *centres, int64_t n_roi, float radius, const uint64_t *type_masks,
+                                   int32_t n_ch, const float *directions, int32_t n_dir, int32_t nbins,
+                                   const int32_t *windows, int32_t n_win, float *images, int32_t *roi_counts,
+                                   void *stream)
+{
+    AR_TRY(ar::check_sig_args(ctx, n_roi, radius, directions, n_dir, nbins));
+    AR_CHECK(images != nullptr, "images is NULL");
+    AR_CHECK(type_masks != nullptr && n_ch >= 1 && n_ch <= 64, "need 1..64 type masks");
+    AR_CHECK(n_atoms == 0 || types != nullptr, "types is NULL");
+    ar::WindowSet ws;
+    AR_TRY(ar::make_windows(windows, n_win, nbins, &ws));
+    AR_HIP(hipSetDevice(ctx->device));
+    hipStream_t s = (hipStream_t)stream;
+    const size_t img_row = (size_t)n_win * n_dir;   // floats per ROI and channel
+    AR_TRY(ctx->s_typed.reserve(sizeof(float) * img_row * n_roi));
+    std::vector<int64_t> off(n_roi + 1);
+    std::vector<int32_t> cnt(roi_counts ? (size_t)n_roi * n_ch : 0);
+    for (int32_t c = 0; c < n_ch; ++c) {
+        int64_t total = 0;
+        AR_TRY(gather_into_ctx(ctx, positions, types, n_atoms, centres, n_roi, radius, type_masks[c], ctx->g_offsets,
+                               ctx->s_rel, &total, s));
+        AR_HIP(hipMemcpyAsync(off.data(), ctx->g_offsets.ptr, sizeof(int64_t) * (n_roi + 1), hipMemcpyDeviceToHost,
+                              s));
+        AR_HIP(hipStreamSynchronize(s));
+        int64_t big = 0;
+        for (int64_t r = 0; r < n_roi; ++r) big = std::max(big, off[r + 1] - off[r]);
+        if (roi_counts)
+            for (int64_t r = 0; r < n_roi; ++r) cnt[(size_t)r * n_ch + c] = (int32_t)(off[r + 1] - off[r]);
+        AR_TRY(ar::launch_plain(ctx, ctx->s_rel.as<float>(), ctx->g_offsets.as<int64_t>(), n_roi, radius, directions,
+                                n_dir, nbins, ws, ctx->s_typed.as<float>(), nullptr, nullptr, ar::sig::stage_for(big),
+                                256, s));
+        // channel c of every ROI: rows of img_row floats at a pitch of n_ch rows
+        AR_HIP(hipMemcpy2DAsync(images + (size_t)c * img_row, sizeof(float) * img_row * n_ch, ctx->s_typed.ptr,
+                                sizeof(float) * img_row, sizeof(float) * img_row, (size_t)n_roi,
+                                hipMemcpyDeviceToDevice, s));
+    }
+    if (roi_counts) {
+        AR_HIP(hipMemcpyAsync(roi_counts, cnt.data(), sizeof(int32_t) * cnt.size(), hipMemcpyHostToDevice, s));
+        AR_HIP(hipStreamSynchronize(s));
+    }
+    return AR_OK;
+}
+
 ar_status araullo_sdm(ar_context *ctx, const float *positions, int64_t n_atoms, const float *centres, int64_t n_roi,
                       float radius, const float *directions, int32_t n_dir, int32_t nbins, int32_t *hist, float *amp,
                       void *stream)
@@ -537,7 +582,8 @@ ar_status araullo_sdm(ar_context *ctx, const float *positions, int64_t n_atoms, 
     AR_HIP(hipSetDevice(ctx->device));
     hipStream_t s = (hipStream_t)stream;
     int64_t total = 0;
-    AR_TRY(gather_into_ctx(ctx, positions, n_atoms, centres, n_roi, radius, ctx->g_offsets, ctx->s_rel, &total, s));
+    AR_TRY(gather_into_ctx(ctx, positions, nullptr, n_atoms, centres, n_roi, radius, ~0ull, ctx->g_offsets,
+                           ctx->s_rel, &total, s));
     ar::WindowSet ws;
     memset(&ws, 0, sizeof(ws));
     return ar::launch_plain(ctx, ctx->s_rel.as<float>(), ctx->g_offsets.as<int64_t>(), n_roi, radius, directions,

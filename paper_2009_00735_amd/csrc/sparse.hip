@@ -327,7 +327,7 @@ __global__ __launch_bounds__(kThreads) void k_sparse_screen(
     // each lane owns orientations ch.y + 4 tid .. + 3: one 8-byte load of
     // their four node ids per strong entry from a wave-uniform row address
     const uint16_t *lut_c = lut_ig + ch.y;
-    const unsigned utid = threadIdx.x;   // unsigned: row base in SGPRs, lane offset in a VGPR
+    const unsigned utid = threadIdx.x;
     const uint32_t *kv2 = kval2 + (size_t)ch.x * n_hat;
     const int32_t *sg = seg + (size_t)ch.x * (n_win + 1);
 

@@ -32,6 +32,9 @@ _SIGS = {
     "ar_window_bins": ([f64, i32, f64, f64, P(i32), P(i32)], ctypes.c_int),
     "ar_roi_gather": ([vp, vp, i64, vp, i64, f32, vp, vp, i64, P(i64), vp], ctypes.c_int),
     "araullo_signatures": ([vp, vp, i64, vp, i64, f32, vp, i32, i32, vp, i32, vp, vp, vp], ctypes.c_int),
+    "ar_roi_gather_typed": ([vp, vp, vp, i64, vp, i64, f32, ctypes.c_uint64, vp, vp, i64, P(i64), vp], ctypes.c_int),
+    "araullo_signatures_typed": ([vp, vp, vp, i64, vp, i64, f32, vp, i32, vp, i32, i32, vp, i32, vp, vp, vp],
+                                 ctypes.c_int),
     "araullo_sdm": ([vp, vp, i64, vp, i64, f32, vp, i32, i32, vp, vp, vp], ctypes.c_int),
     "araullo_signatures_csr": ([vp, vp, vp, i64, f32, vp, i32, i32, vp, i32, vp, vp], ctypes.c_int),
     "ar_signature_plan_create": ([vp, i64, i64, i32, i32, i32, P(vp)], ctypes.c_int),
@@ -139,30 +142,40 @@ def _host_windows(windows) -> torch.Tensor:
 
 
 def ar_roi_gather(ctx: Context, positions: torch.Tensor, centres: torch.Tensor, radius: float,
-                  out: Optional[Tuple[torch.Tensor, torch.Tensor]] = None):
+                  out: Optional[Tuple[torch.Tensor, torch.Tensor]] = None, types: Optional[torch.Tensor] = None,
+                  type_mask: int = (1 << 64) - 1):
     """-> (offsets int64 [n_roi+1], rel float32 [total][4]) on the GPU.
 
     With out=(offsets, rel_buffer) the rows are written into the given
-    buffers (rel_buffer must hold the total; the result is a view of it)."""
+    buffers (rel_buffer must hold the total; the result is a view of it).
+    With types (int32 [n_atoms]) only atoms whose type bit is set in
+    type_mask are gathered (ar_roi_gather_typed)."""
     d = ctx.device
     n_roi = centres.shape[0]
     total = i64()
     pp = _dev(positions, torch.float32, d, "positions") if positions.numel() else None
     cp = _dev(centres, torch.float32, d, "centres")
     s = _stream(d)
+    if types is None:
+        def gather(offp, relp, cap):
+            _call("ar_roi_gather", ctx.handle, pp, positions.shape[0], cp, n_roi, radius, offp, relp, cap,
+                  ctypes.byref(total), s)
+    else:
+        tp = _dev(types, torch.int32, d, "types") if types.numel() else None
+
+        def gather(offp, relp, cap):
+            _call("ar_roi_gather_typed", ctx.handle, pp, tp, positions.shape[0], cp, n_roi, radius, type_mask, offp,
+                  relp, cap, ctypes.byref(total), s)
     if out is not None:
         offsets, rel = out
         _dev(offsets, torch.int64, d, "offsets")
         _dev(rel, torch.float32, d, "rel")
-        _call("ar_roi_gather", ctx.handle, pp, positions.shape[0], cp, n_roi, radius, offsets.data_ptr(),
-              rel.data_ptr(), rel.shape[0], ctypes.byref(total), s)
+        gather(offsets.data_ptr(), rel.data_ptr(), rel.shape[0])
         return offsets, rel[:total.value]
     offsets = torch.empty(n_roi + 1, dtype=torch.int64, device=d)
-    _call("ar_roi_gather", ctx.handle, pp, positions.shape[0], cp, n_roi, radius, offsets.data_ptr(), None, 0,
-          ctypes.byref(total), s)
+    gather(offsets.data_ptr(), None, 0)
     rel = torch.empty((max(total.value, 1), 4), dtype=torch.float32, device=d)
-    _call("ar_roi_gather", ctx.handle, pp, positions.shape[0], cp, n_roi, radius, offsets.data_ptr(),
-          rel.data_ptr(), rel.shape[0], ctypes.byref(total), s)
+    gather(offsets.data_ptr(), rel.data_ptr(), rel.shape[0])
     return offsets, rel[:total.value]
 
 
@@ -176,6 +189,26 @@ def araullo_signatures(ctx: Context, positions: torch.Tensor, centres: torch.Ten
     cnt = torch.empty(n_roi, dtype=torch.int32, device=d) if counts else None
     _call("araullo_signatures", ctx.handle, _dev(positions, torch.float32, d, "positions") if positions.numel() else None,
           positions.shape[0], _dev(centres, torch.float32, d, "centres"), n_roi, radius,
+          _dev(directions, torch.float32, d, "directions"), n_dir, nbins, w.data_ptr(), n_win, images.data_ptr(),
+          cnt.data_ptr() if counts else None, _stream(d))
+    return (images, cnt) if counts else images
+
+
+def araullo_signatures_typed(ctx: Context, positions: torch.Tensor, types: torch.Tensor, centres: torch.Tensor,
+                             radius: float, directions: torch.Tensor, nbins: int, windows, type_masks: Sequence[int],
+                             counts: bool = True):
+    """-> images float32 [n_roi][n_ch][n_win][n_dir] (and int32 counts [n_roi][n_ch]):
+    one signature channel per atom-type mask."""
+    d = ctx.device
+    w = _host_windows(windows)
+    n_roi, n_dir, n_win, n_ch = centres.shape[0], directions.shape[0], w.shape[0], len(type_masks)
+    masks = (ctypes.c_uint64 * n_ch)(*[int(m) for m in type_masks])
+    images = torch.empty((n_roi, n_ch, n_win, n_dir), dtype=torch.float32, device=d)
+    cnt = torch.empty((n_roi, n_ch), dtype=torch.int32, device=d) if counts else None
+    _call("araullo_signatures_typed", ctx.handle,
+          _dev(positions, torch.float32, d, "positions") if positions.numel() else None,
+          _dev(types, torch.int32, d, "types") if types.numel() else None, positions.shape[0],
+          _dev(centres, torch.float32, d, "centres"), n_roi, radius, masks, n_ch,
           _dev(directions, torch.float32, d, "directions"), n_dir, nbins, w.data_ptr(), n_win, images.data_ptr(),
           cnt.data_ptr() if counts else None, _stream(d))
     return (images, cnt) if counts else images

@@ -46,10 +46,18 @@ STREAM_REFERENCE = 8
 A_AL = 0.405   # nm, fcc aluminium
 A_FE = 0.287   # nm, bcc iron
 
+A_AL3SC = 0.4105   # nm, L1_2 Al3Sc
+A_AL3LI = 0.4010   # nm, L1_2 Al3Li (delta')
+
 BASIS = {
     "fcc": np.array([[0.0, 0.0, 0.0], [0.0, 0.5, 0.5], [0.5, 0.0, 0.5], [0.5, 0.5, 0.0]]),
     "bcc": np.array([[0.0, 0.0, 0.0], [0.5, 0.5, 0.5]]),
+    "L12": np.array([[0.0, 0.0, 0.0], [0.0, 0.5, 0.5], [0.5, 0.0, 0.5], [0.5, 0.5, 0.0]]),
 }
+# atom type per basis site: L1_2 (Cu3Au type) puts the minority species (Sc,
+# Li: type 1) on the cube corner and aluminium (type 0) on the face centres
+BASIS_TYPES = {"fcc": np.array([0, 0, 0, 0]), "bcc": np.array([0, 0]), "L12": np.array([1, 0, 0, 0])}
+TYPE_AL, TYPE_MINOR = 0, 1
 
 # Lattice-plane spacings (nm) that centre the four peak windows: fcc Al
 # {111}, {200}, {220}, {311}.
@@ -179,6 +187,37 @@ def lattice_in_ball(kind: str, a: float, q: np.ndarray, offset_frac: np.ndarray,
     lab = pts @ Rm.T
     keep = np.einsum("ij,ij->i", lab, lab) <= radius * radius
     return lab[keep] + np.asarray(centre, dtype=np.float64)
+
+
+def typed_lattice_in_ball(kind: str, a: float, q: np.ndarray, offset_frac: np.ndarray,
+                          centre: np.ndarray, radius: float) -> Tuple[np.ndarray, np.ndarray]:
+    """lattice_in_ball with the atom type of every site (BASIS_TYPES)."""
+    Rm = quat_matrix(q)
+    n = int(math.ceil(radius / a)) + 2
+    r = np.arange(-n, n + 1, dtype=np.float64)
+    ijk = np.stack(np.meshgrid(r, r, r, indexing="ij"), axis=-1).reshape(-1, 1, 3)
+    pts = ((ijk + BASIS[kind][None] + np.asarray(offset_frac)[None, None]) * a).reshape(-1, 3)
+    types = np.tile(BASIS_TYPES[kind], len(ijk)).astype(np.int32)
+    lab = pts @ Rm.T
+    keep = np.einsum("ij,ij->i", lab, lab) <= radius * radius
+    return lab[keep] + np.asarray(centre, dtype=np.float64), types[keep]
+
+
+def l12_specimen(n_roi: int = 64, eta: float = 0.5, sigma: float = 0.03, R: float = 1.0, seed: int = 0,
+                 a: float = A_AL3SC):
+    """A rotated L1_2 crystal (types 0 = Al, 1 = Sc/Li) in a ball of radius
+    3R + 1 nm with kept fraction eta and Gaussian displacements sigma; n_roi
+    ROI centres uniform in the ball of radius 3R.  Returns (positions float32,
+    types int32, centres float32, q)."""
+    gen = np.random.Generator(np.random.PCG64(np.random.SeedSequence([SEED_ROOT, 12, seed])))
+    q = shoemake(1, gen)[0]
+    pos, types = typed_lattice_in_ball("L12", a, q, gen.random(3), np.zeros(3), 3 * R + 1.0)
+    keep = delete_exact(len(pos), eta, gen)
+    pos, types = pos[keep], types[keep]
+    pos = pos + gen.normal(0.0, sigma, pos.shape)
+    c = gen.normal(size=(n_roi, 3))
+    c *= (3 * R * gen.random(n_roi) ** (1 / 3) / np.linalg.norm(c, axis=1))[:, None]
+    return pos.astype(np.float32), types, c.astype(np.float32), q
 
 
 def lattice_in_box(kind: str, a: float, q: np.ndarray, offset_frac: np.ndarray,
