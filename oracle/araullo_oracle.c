@@ -67,6 +67,12 @@
  *      Al-Li-Mg specimens): the signature of a set of atom types is the
  *      signature computed from the atoms of those types only (the selection
  *      itself lives in the NumPy front end, signatures_typed).
+ *  R14 reciprocal-space signatures on a cubic grid (Sec. 2.2, FSP paragraph,
+ *      Eq. (2); supplement, reciprocal-space costs): amp(k) = |sum_w
+ *      exp(-2 pi i k . d_w)| at the L^3 points k = (a - L/2, b - L/2,
+ *      c - L/2) * dk, dk = 2 k_max / L, a, b, c in [0, L) (k in cycles per
+ *      length unit, the origin on the grid).  The paper's k in [-2 pi, 2 pi]^3
+ *      is read as 2 pi k with |k| <= 1 per Angstrom, i.e. k_max = 10 per nm.
  */
 #include <math.h>
 #include <stdint.h>
@@ -633,4 +639,37 @@ void orc_sparse_pairs(const double *Sh, int32_t n_win, int32_t n_dir, const int3
         out[p] = orc_sparse_delta(Sh + (size_t)roi[p] * n_win * n_dir, n_dir, strong_idx + c * n_hat,
                                   strong_val + c * n_hat, lut_rows + (size_t)p * n_hat, n_hat);
     }
+}
+
+/* ---------------------------------------------------------------------- */
+/* Reciprocal-space signatures on a cubic grid (reading R14), FP64          */
+/* ---------------------------------------------------------------------- */
+/* amp at explicit k vectors (cycles per length unit): |sum_w exp(-2 pi i k.d_w)| */
+void orc_fsp_at(const float *rel, int64_t n_w, const double *k, int64_t n_k, double *amp)
+{
+    for (int64_t q = 0; q < n_k; ++q) {
+        double re = 0.0, im = 0.0;
+        for (int64_t w = 0; w < n_w; ++w) {
+            double t = k[3 * q] * rel[3 * w] + k[3 * q + 1] * rel[3 * w + 1] + k[3 * q + 2] * rel[3 * w + 2];
+            re += cos(2.0 * ORC_PI * t);
+            im -= sin(2.0 * ORC_PI * t);
+        }
+        amp[q] = sqrt(re * re + im * im);
+    }
+}
+
+/* amp[a][b][c] on the L^3 grid of reading R14 */
+void orc_fsp_grid(const float *rel, int64_t n_w, int32_t L, double k_max, double *amp, int32_t n_threads)
+{
+    const double dk = 2.0 * k_max / (double)L;
+#ifdef _OPENMP
+    if (n_threads < 1) n_threads = 1;
+#pragma omp parallel for schedule(dynamic, 1) num_threads(n_threads)
+#endif
+    for (int32_t a = 0; a < L; ++a)
+        for (int32_t b = 0; b < L; ++b)
+            for (int32_t c = 0; c < L; ++c) {
+                double k[3] = {(a - L / 2) * dk, (b - L / 2) * dk, (c - L / 2) * dk};
+                orc_fsp_at(rel, n_w, k, 1, amp + ((size_t)a * L + b) * L + c);
+            }
 }

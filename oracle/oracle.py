@@ -69,6 +69,8 @@ def lib():
         L.orc_sparse_index_topk.argtypes = [F64P, c_i64, c_i32, c_i32, I32P, F64P, I32P, I32P, c_i64, c_i32,
                                             c_i32, I32P, F64P, c_i32]
         L.orc_sparse_pairs.argtypes = [F64P, c_i32, c_i32, I32P, F64P, I32P, I32P, c_i32, I64P, c_i64, F64P]
+        L.orc_fsp_at.argtypes = [F32P, c_i64, F64P, c_i64, F64P]
+        L.orc_fsp_grid.argtypes = [F32P, c_i64, c_i32, c_f64, F64P, c_i32]
         L.orc_sf_amplitudes.argtypes = [F32P, c_i64, F64P, F32P, c_i32, F64P, c_i32, F64P]
         L.orc_sf_score.argtypes = [F32P, c_i64, F64P, F32P, c_i32, F64P, c_i32, F64P]
         L.orc_sf_score.restype = c_f64
@@ -285,6 +287,29 @@ def sparse_pairs(S_hat, strong_idx, strong_val, pair_phase, lut_rows, roi) -> np
     r = np.ascontiguousarray(roi, np.int64)
     out = np.zeros(len(r), np.float64)
     lib().orc_sparse_pairs(S, n_win, n_dir, si, sv, _i32(pair_phase), _i32(lut_rows), si.shape[1], r, len(r), out)
+    return out
+
+
+# ---------------------------------------------------------------- reciprocal-space grid (reading R14)
+def fsp_grid_k(L: int, k_max: float) -> np.ndarray:
+    """The grid's k values along one axis (cycles per length unit)."""
+    return (np.arange(L) - L // 2) * (2.0 * k_max / L)
+
+
+def fsp_at(rel, k) -> np.ndarray:
+    """|sum_w exp(-2 pi i k . d_w)| at explicit k vectors [n_k][3]."""
+    r = _f32(rel).reshape(-1, 3)
+    kk = _f64(k).reshape(-1, 3)
+    out = np.zeros(len(kk), np.float64)
+    lib().orc_fsp_at(r, len(r), kk, len(kk), out)
+    return out
+
+
+def fsp_grid(rel, L: int, k_max: float, threads: Optional[int] = None) -> np.ndarray:
+    """Amplitudes [L][L][L] on the cubic grid of reading R14."""
+    r = _f32(rel).reshape(-1, 3)
+    out = np.zeros((L, L, L), np.float64)
+    lib().orc_fsp_grid(r, len(r), L, k_max, out, threads or default_threads())
     return out
 
 
