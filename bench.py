@@ -444,6 +444,28 @@ def compare(nat, synth, torch, dev):
         "typed_ms": t_typed, "untyped_ms": t_untyped, "typed_over_untyped": t_typed / t_untyped,
         "roi_dir_channel_per_s": len(cen) * int(dirs.shape[0]) * 3 / (t_typed / 1e3),
         "note": "each channel = one typed ROI query + the plain signature kernel + a pitched copy"}
+    # reciprocal-space signatures on a cubic grid (Eq. (2)): the paper's
+    # benchmark shape, 10^4 ROIs of R = 2 nm in full-density fcc Al, L = 64
+    # (and 2000 of them at L = 128); algorithmic work 8 N_w L^3 flop per ROI
+    # (one complex multiply-add per atom and grid point)
+    del pos_d, types_d, cen_d
+    pos, cen, _ = synth.fsp_specimen(10000, 2.0)
+    off, rel = nat.ar_roi_gather(ctx, torch.from_numpy(pos).to(dev), torch.from_numpy(cen).to(dev), 2.0)
+    rel = rel.contiguous()
+    n_atoms = int(off[-1])
+    fsp = {"rois": len(cen), "mean_atoms": n_atoms / len(cen), "k_max_per_nm": 10.0,
+           "measured_fp32_mfma_flop_per_s": peaks["fp32_mfma_flop_per_s"]}
+    for L, n in ((64, len(cen)), (128, 2000)):
+        o = off[:n + 1]
+        out = torch.empty((n, L, L, L), dtype=torch.float32, device=dev)
+        t = best_ms(lambda: nat.ar_fsp_amplitudes(ctx, rel, o, L, 10.0, out=out))
+        flops = 8.0 * float(o[-1]) * L ** 3
+        fsp[f"L{L}"] = {"rois": n, "ms": t, "tflop_per_s": flops / (t / 1e3) / 1e12,
+                        "frac_of_datasheet_fp32_mfma": flops / (t / 1e3) / 157.3e12,
+                        "frac_of_measured_fp32_mfma": flops / (t / 1e3) / peaks["fp32_mfma_flop_per_s"],
+                        "output_gb": n * L ** 3 * 4 / 1e9}
+        del out
+    rec["fsp_cubic_grid"] = fsp
     print(json.dumps(rec))
 
 

@@ -315,6 +315,24 @@ ar_status index_orientations_sparse(ar_context *ctx, const float *images, int64_
                                     float *top_score, void *stream);
 
 /*
+ * Reciprocal-space signatures on a cubic grid (Sec. 2.2, FSP paragraph,
+ * Eq. (2); supplement, reciprocal-space cost O(N_roi N_w L^3)):
+ *   amp[r][a][b][c] = |sum_w exp(-2 pi i k . d_w)|,
+ *   k = ((a - L/2), (b - L/2), (c - L/2)) * dk,  dk = 2 k_max / L,
+ * over the gathered relative coordinates d_w of ROI r (k in cycles per
+ * length unit of the coordinates; the origin a = b = c = L/2 holds N_w).
+ * Evaluated as one complex GEMM per ROI on FP32 matrix cores.
+ *   rel, offsets  gathered CSR (ar_roi_gather)
+ *   L             multiple of 32 in [32, 512]
+ *   k_max         > 0 (the grid covers [-k_max, k_max - dk] per axis)
+ *   amp           device float [n_roi][L][L][L], out
+ * AR_EINVAL if n_roi * L^3 / 4096 workgroups exceed 2^31 - 1.  Does not
+ * synchronise.
+ */
+ar_status ar_fsp_amplitudes(ar_context *ctx, const float *rel, const int64_t *offsets, int64_t n_roi,
+                            int32_t L, float k_max, float *amp, void *stream);
+
+/*
  * Disorientation angle in degrees under cubic symmetry (supplement,
  * "Creation of test orientations": the misorientation with the smallest
  * rotation angle among the symmetrically equivalent ones), FP64:
@@ -411,6 +429,7 @@ ar_status ar_refine_orientations(ar_context *ctx, const float *rel, const int64_
  *   out[AR_PEAK_SIN_OVERLAP]      time of 16 FMA chains / time of the same with 4 sin chains beside
  *                                 them (1 = the transcendental unit runs beside the FMA pipeline)
  *   out[AR_PEAK_BF16_MFMA_FLOPS]  v_mfma_f32_32x32x16_bf16, flop per second
+ *   out[AR_PEAK_FP32_MFMA_FLOPS]  v_mfma_f32_32x32x2_f32, flop per second
  *   out[AR_PEAK_LDS_GATHER8]      8-byte LDS reads at pseudo-random addresses of a 64 KB table
  *                                 (the look-up gather pattern, bank conflicts included), lane reads per second
  *   out    host double [n_out], n_out >= AR_PEAK_COUNT
@@ -425,7 +444,8 @@ enum {
     AR_PEAK_SIN_OVERLAP = 5,
     AR_PEAK_BF16_MFMA_FLOPS = 6,
     AR_PEAK_LDS_GATHER8 = 7,
-    AR_PEAK_COUNT = 8
+    AR_PEAK_FP32_MFMA_FLOPS = 8,
+    AR_PEAK_COUNT = 9
 };
 ar_status ar_measure_peaks(ar_context *ctx, double *out, int32_t n_out);
 

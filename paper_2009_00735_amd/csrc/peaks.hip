@@ -1,7 +1,7 @@
 // Measured peak rates of the units the kernels are bound by (the roofline
 // denominators): HBM copy, LDS 16-byte reads, conflict-free LDS atomics,
 // non-packed FP32 FMA, the transcendental unit (alone and issued beside FMA
-// work), BF16 MFMA, and random 8-byte LDS reads.  Each probe runs a fixed loop on a grid of eight
+// work), BF16 and FP32 MFMA, and random 8-byte LDS reads.  Each probe runs a fixed loop on a grid of eight
 // workgroups per compute unit and is timed with HIP events around the launch.
 
 #include "ar_internal.h"
@@ -122,6 +122,27 @@ __global__ __launch_bounds__(kBlock) void k_mfma(int iters, float *__restrict__ 
     out[(size_t)blockIdx.x * kBlock + threadIdx.x] = r;
 }
 
+// v_mfma_f32_32x32x2_f32 on four independent accumulators per wavefront.
+__global__ __launch_bounds__(kBlock) void k_mfma_f32(int iters, float *__restrict__ out)
+{
+    const float a = 0.001f * (float)threadIdx.x, b = 0.002f * (float)(threadIdx.x + 1);
+    f32x16 acc[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int i = 0; i < 16; ++i) acc[j][i] = 0.f;
+    for (int it = 0; it < iters; ++it) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, acc[j], 0, 0, 0);
+    }
+    float r = 0.f;
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int i = 0; i < 16; ++i) r += acc[j][i];
+    out[(size_t)blockIdx.x * kBlock + threadIdx.x] = r;
+}
+
 }  // namespace peaks
 }  // namespace ar
 
@@ -189,6 +210,8 @@ ar_status ar_measure_peaks(ar_context *ctx, double *out, int32_t n_out)
     out[AR_PEAK_SIN_OVERLAP] = t_fma / t;
     AR_TRY(time_launch([&] { k_mfma<<<blocks, kBlock>>>(it_mfma, sink.as<float>()); }, &t));
     out[AR_PEAK_BF16_MFMA_FLOPS] = (double)blocks * (kBlock / 64) * it_mfma * 4.0 * (32.0 * 32.0 * 16.0 * 2.0) / t;
+    AR_TRY(time_launch([&] { k_mfma_f32<<<blocks, kBlock>>>(it_mfma / 4, sink.as<float>()); }, &t));
+    out[AR_PEAK_FP32_MFMA_FLOPS] = (double)blocks * (kBlock / 64) * (it_mfma / 4) * 4.0 * (32.0 * 32.0 * 2.0 * 2.0) / t;
     AR_TRY(time_launch([&] { k_lds_gather<<<blocks, kBlock>>>(it_lds, sink.as<float>()); }, &t));
     out[AR_PEAK_LDS_GATHER8] = (double)threads * it_lds / t;
     return AR_OK;

@@ -51,6 +51,7 @@ _SIGS = {
     "ar_sparse_lut_destroy": ([vp], ctypes.c_int),
     "ar_sparse_lut_export": ([vp, vp, vp, vp, vp], ctypes.c_int),
     "index_orientations_sparse": ([vp, vp, i64, vp, i32, vp, vp, vp], ctypes.c_int),
+    "ar_fsp_amplitudes": ([vp, vp, vp, i64, i32, f32, vp, vp], ctypes.c_int),
     "index_orientations_ex": ([vp, vp, i64, vp, i32, i32, vp, vp, vp, vp], ctypes.c_int),
     "ar_disorientation_cubic": ([vp, vp, i64, vp, vp], ctypes.c_int),
     "ar_rotate_reference": ([vp, vp, i32, i32, vp, i32, vp, vp, i64, vp, vp], ctypes.c_int),
@@ -411,6 +412,18 @@ def index_orientations_sparse(ctx: Context, images: torch.Tensor, lut: SparseLUT
     return idx, sc
 
 
+def ar_fsp_amplitudes(ctx: Context, rel: torch.Tensor, offsets: torch.Tensor, L: int, k_max: float,
+                      out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """-> amplitudes float32 [n_roi][L][L][L] of Eq. (2) on the cubic grid."""
+    d = ctx.device
+    n_roi = offsets.shape[0] - 1
+    if out is None:
+        out = torch.empty((n_roi, L, L, L), dtype=torch.float32, device=d)
+    _call("ar_fsp_amplitudes", ctx.handle, _dev(rel, torch.float32, d, "rel"), _dev(offsets, torch.int64, d, "offsets"),
+          n_roi, L, k_max, _dev(out, torch.float32, d, "out"), _stream(d))
+    return out
+
+
 def ar_disorientation_cubic(qa: torch.Tensor, qb: torch.Tensor) -> torch.Tensor:
     d = qa.device
     n = qa.shape[0]
@@ -491,7 +504,7 @@ def ar_refine_orientations(ctx: Context, rel, offsets, quats, phase, directions,
 
 
 PEAK_NAMES = ("hbm_bytes_per_s", "lds_bytes_per_s", "lds_atomics_per_s", "fp32_fma_flop_per_s", "sin_per_s",
-              "sin_beside_fma_time_ratio", "bf16_mfma_flop_per_s", "lds_gather8_per_s")
+              "sin_beside_fma_time_ratio", "bf16_mfma_flop_per_s", "lds_gather8_per_s", "fp32_mfma_flop_per_s")
 
 
 def ar_measure_peaks(ctx: Context) -> dict:

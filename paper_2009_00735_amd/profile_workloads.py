@@ -3,6 +3,7 @@
     python -m paper_2009_00735_amd.profile_workloads indexing [--reps 5]
     python -m paper_2009_00735_amd.profile_workloads signatures [--reps 5]
     python -m paper_2009_00735_amd.profile_workloads sparse [--reps 5]
+    python -m paper_2009_00735_amd.profile_workloads fsp [--reps 5]
 
 `indexing`: the config-2 indexing shape (2000 ROI images x 20000 references,
 4 x 10242 nodes) on seeded random non-negative images generated on the
@@ -17,6 +18,10 @@ signature of 16 unrotated crystal ROIs), 20000 library orientations, 1000
 strongest entries; the look-up table is built once, then
 `index_orientations_sparse(k = 16)` runs `reps` times on seeded random
 non-negative ROI images (2000 x 4 x 10242) generated on the device.
+
+`fsp`: Eq. (2) on the 64^3 grid (k_max = 10/nm) for 10^4 ROIs of R = 2 nm in
+full-density fcc Al (`synth.fsp_specimen`); `ar_fsp_amplitudes` runs `reps`
+times into one output buffer.
 
 Every call goes through the C ABI (`native`); nothing here computes any part
 of the method.  Prints one line per repetition with the wall time.
@@ -79,12 +84,21 @@ def sparse(reps: int) -> None:
     _timed("index_orientations_sparse", lambda: nat.index_orientations_sparse(ctx, S, lut, 16), reps)
 
 
+def fsp(reps: int) -> None:
+    ctx = nat.Context(0)
+    pos, cen, _ = synth.fsp_specimen(10000, 2.0)
+    off, rel = nat.ar_roi_gather(ctx, torch.from_numpy(pos).cuda(), torch.from_numpy(cen).cuda(), 2.0)
+    rel = rel.contiguous()
+    out = torch.empty((len(cen), 64, 64, 64), dtype=torch.float32, device="cuda")
+    _timed("ar_fsp_amplitudes", lambda: nat.ar_fsp_amplitudes(ctx, rel, off, 64, 10.0, out=out), reps)
+
+
 def main() -> None:
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
-    ap.add_argument("workload", choices=["indexing", "signatures", "sparse"])
+    ap.add_argument("workload", choices=["indexing", "signatures", "sparse", "fsp"])
     ap.add_argument("--reps", type=int, default=5)
     a = ap.parse_args()
-    {"indexing": indexing, "signatures": signatures, "sparse": sparse}[a.workload](a.reps)
+    {"indexing": indexing, "signatures": signatures, "sparse": sparse, "fsp": fsp}[a.workload](a.reps)
 
 
 if __name__ == "__main__":

@@ -567,3 +567,22 @@ def bump_images(directions: np.ndarray, quats: np.ndarray, phase: np.ndarray, n_
                 x *= np.maximum(0.0, 1.0 + noise * gen.standard_normal(len(d)))
             out[i, w] = x
     return out
+
+
+# --------------------------------------------------------------------------
+# reciprocal-space benchmark input (supplement, reciprocal-space benchmark:
+# 1e4 ROIs of R = 20 A in synthetic aluminium single crystals)
+# --------------------------------------------------------------------------
+def fsp_specimen(n_roi: int = 10000, R: float = 2.0, box: float = 24.0, eta: float = 1.0, seed: int = 0):
+    """A full-density (eta = 1) fcc Al single crystal in a cube of edge `box`
+    nm, rotated by a seeded orientation, and n_roi ROI centres uniform in the
+    cube shrunk by R (every ROI complete).  Returns (positions float32,
+    centres float32, q)."""
+    gen = np.random.Generator(np.random.PCG64(np.random.SeedSequence([SEED_ROOT, 21, seed])))
+    q = shoemake(1, gen)[0]
+    lo, hi = np.zeros(3), np.full(3, box)
+    pos = lattice_in_box("fcc", A_AL, q, gen.random(3), lo, hi)
+    if eta < 1.0:
+        pos = pos[delete_exact(len(pos), eta, gen)]
+    cen = R + gen.random((n_roi, 3)) * (box - 2 * R)
+    return pos.astype(np.float32), cen.astype(np.float32), q

@@ -16,6 +16,7 @@ BOUNDS = {
     "sin_per_s": 256 * 4 * 64 * 2.4e9,
     "bf16_mfma_flop_per_s": 2.5e15,
     "lds_gather8_per_s": 256 * 2.4e9 * 32,        # 8-byte lane reads: at most 256 bytes per clock per CU
+    "fp32_mfma_flop_per_s": 157.3e12,
 }
 
 
