@@ -71,6 +71,9 @@ def lib():
         L.orc_sparse_pairs.argtypes = [F64P, c_i32, c_i32, I32P, F64P, I32P, I32P, c_i32, I64P, c_i64, F64P]
         L.orc_fsp_at.argtypes = [F32P, c_i64, F64P, c_i64, F64P]
         L.orc_fsp_grid.argtypes = [F32P, c_i64, c_i32, c_f64, F64P, c_i32]
+        L.orc_refine_roi_grid.argtypes = [F32P, F64P, I32P, c_i64, c_i32, c_i32, ctypes.c_uint32, c_f64, c_f64,
+                                          c_i32, I32P, F32P, I32P, c_i64]
+        L.orc_refine_roi_grid.restype = c_i64
         L.orc_sf_amplitudes.argtypes = [F32P, c_i64, F64P, F32P, c_i32, F64P, c_i32, F64P]
         L.orc_sf_score.argtypes = [F32P, c_i64, F64P, F32P, c_i32, F64P, c_i32, F64P]
         L.orc_sf_score.restype = c_f64
@@ -311,6 +314,25 @@ def fsp_grid(rel, L: int, k_max: float, threads: Optional[int] = None) -> np.nda
     out = np.zeros((L, L, L), np.float64)
     lib().orc_fsp_grid(r, len(r), L, k_max, out, threads or default_threads())
     return out
+
+
+# ---------------------------------------------------------------- adaptive ROI grid (reading R15)
+def refine_roi_grid(centres, images, counts, window_mask: int, kappa: float, h: float, split: int = 5):
+    """-> (keep int32 [n_roi], refined centres float32 [n_keep*split^3][3],
+    parent int32 [n_keep*split^3])."""
+    c = _f32(centres).reshape(-1, 3)
+    img = _f64(images)
+    n_roi, n_win, n_dir = img.shape
+    assert n_win <= 32
+    cnt = _i32(counts)
+    keep = np.zeros(n_roi, np.int32)
+    cap = int(n_roi) * split ** 3
+    out = np.zeros((max(cap, 1), 3), np.float32)
+    par = np.zeros(max(cap, 1), np.int32)
+    n_keep = lib().orc_refine_roi_grid(c, img, cnt, n_roi, n_win, n_dir, window_mask, kappa, h, split, keep, out,
+                                       par, cap)
+    n = int(n_keep) * split ** 3
+    return keep, out[:n], par[:n]
 
 
 # ---------------------------------------------------------------- structure factor
