@@ -376,6 +376,7 @@ def compare(nat, synth, torch, dev):
             L = nat.ar_rotate_reference(ctx, ref.contiguous(), dirs, lib_q,
                                         torch.zeros(20000, dtype=torch.int32, device=dev))
         del plain, out, plan
+    log("compare: signatures done")
     lib = nat.Library(ctx, L)
     t_bf16 = best_ms(lambda: nat.index_orientations(ctx, images, lib, 16))
     idx_bf16, _ = nat.index_orientations(ctx, images, lib, 16)
@@ -413,6 +414,7 @@ def compare(nat, synth, torch, dev):
         t_sp = best_ms(lambda: nat.index_orientations_sparse(ctx, images, lut, 16))
         idx_sp, _ = nat.index_orientations_sparse(ctx, images, lut, 16)
         dis_sp = nat.ar_disorientation_cubic(lib_q[idx_sp[:, 0].long()].contiguous(), truth).cpu().numpy()
+        log(f"compare: sparse indexing N^ = {n_hat}")
         sparse[f"n_hat_{n_hat}"] = {
             "lut_build_ms": t_lut, "index_ms": t_sp, "speedup_vs_dense": t_bf16 / t_sp,
             "terms_per_s": images.shape[0] * n_rot * n_hat / (t_sp / 1e3),
@@ -424,6 +426,7 @@ def compare(nat, synth, torch, dev):
             "top1_disorientation_p95_deg": float(np.percentile(dis_sp, 95))}
         del lut
     rec["sparse_indexing_cfg2"] = sparse
+    log("compare: indexing done")
     # sub-lattice signatures: an L1_2 Al3Sc crystal (eta 0.5, sigma 0.03 nm),
     # 2000 ROIs of R = 2 nm, 10242 directions, 1024 bins, the four windows plus
     # the superlattice window at d = a; channels: all atoms, Al, Sc
@@ -444,6 +447,7 @@ def compare(nat, synth, torch, dev):
         "typed_ms": t_typed, "untyped_ms": t_untyped, "typed_over_untyped": t_typed / t_untyped,
         "roi_dir_channel_per_s": len(cen) * int(dirs.shape[0]) * 3 / (t_typed / 1e3),
         "note": "each channel = one typed ROI query + the plain signature kernel + a pitched copy"}
+    log("compare: typed signatures done")
     # reciprocal-space signatures on a cubic grid (Eq. (2)): the paper's
     # benchmark shape, 10^4 ROIs of R = 2 nm in full-density fcc Al, L = 64
     # (and 2000 of them at L = 128); algorithmic work 8 N_w L^3 flop per ROI
@@ -466,6 +470,49 @@ def compare(nat, synth, torch, dev):
                         "output_gb": n * L ** 3 * 4 / 1e9}
         del out
     rec["fsp_cubic_grid"] = fsp
+    log("compare: reciprocal-space grid done")
+    del rel, off
+    # adaptive ROI-grid refinement on config 3: a coarse 2 nm grid over the
+    # specimen's bounding box (ROIs with >= 100 atoms), batched signatures,
+    # kappa = 0.75 on any window, 5^3 split, batched signatures of the refined
+    # ROIs; a naive 5^3 refinement of every coarse ROI is priced at the
+    # measured refined rate
+    log("compare: adaptive grid on config 3")
+    s3 = synth.config3()
+    pos3 = torch.from_numpy(s3.positions).to(dev)
+    dirs3 = torch.from_numpy(s3.directions).to(dev)
+    w3 = nat.windows_for(s3.radius, s3.nbins, s3.spacings)
+    grid = synth.roi_grid(s3.positions.min(0), s3.positions.max(0), 2.0)
+    off_all, _ = nat.ar_roi_gather(ctx, pos3, torch.from_numpy(grid).to(dev), s3.radius)
+    keep = (torch.diff(off_all) >= 100).cpu().numpy()
+    coarse = torch.from_numpy(grid[keep]).to(dev)
+
+    def batch(centres, config=None):
+        off, rel = nat.ar_roi_gather(ctx, pos3, centres, s3.radius)
+        plan = nat.SignaturePlan(ctx, centres.shape[0], rel.shape[0], dirs3.shape[0], s3.nbins, w3.shape[0])
+        if config is None:
+            img = plan.tune(rel, off, s3.radius, dirs3, w3)
+        else:
+            plan.set_config(*config)
+            img = plan.run(rel, off, s3.radius, dirs3, w3, use_graph=False)
+        t = best_ms(lambda: plan.run(rel, off, s3.radius, dirs3, w3, out=img, use_graph=True), reps=2)
+        return off, img, t, plan.config()
+
+    log(f"adaptive grid: {len(coarse)} coarse ROIs")
+    off_c, img_c, t_coarse, cfg_c = batch(coarse)
+    counts_c = torch.diff(off_c).to(torch.int32).contiguous()
+    t_refine = best_ms(lambda: nat.ar_refine_roi_grid(ctx, coarse, img_c, counts_c, 0xF, 0.75, 2.0, 5))
+    refined, parent = nat.ar_refine_roi_grid(ctx, coarse, img_c, counts_c, 0xF, 0.75, 2.0, 5)
+    del img_c
+    log(f"adaptive grid: {refined.shape[0]} refined ROIs")
+    off_r, img_r, t_refined, _ = batch(refined.contiguous(), cfg_c)
+    n_c, n_r = int(coarse.shape[0]), int(refined.shape[0])
+    rec["adaptive_grid_cfg3"] = {
+        "coarse_rois": n_c, "kept": n_r // 125, "refined_rois": n_r, "directions": int(dirs3.shape[0]),
+        "coarse_signatures_ms": t_coarse, "selection_and_split_ms": t_refine, "refined_signatures_ms": t_refined,
+        "total_ms": t_coarse + t_refine + t_refined,
+        "naive_refined_rois": n_c * 125, "naive_estimate_ms": t_refined * n_c * 125 / max(n_r, 1),
+        "refined_roi_dir_per_s": n_r * int(dirs3.shape[0]) / (t_refined / 1e3)}
     print(json.dumps(rec))
 
 

@@ -333,6 +333,30 @@ ar_status ar_fsp_amplitudes(ar_context *ctx, const float *rel, const int64_t *of
                             int32_t L, float k_max, float *amp, void *stream);
 
 /*
+ * Adaptive ROI-grid refinement (Sec. 3.4, aluminium bicrystal: a coarse
+ * cubic ROI grid, then a local octree-like refinement where the signal is
+ * strong; supplement, local grid refinement).  Coarse ROI r has atom count
+ * counts[r] = N_r and images img[r][w][v]; its intensity in window w is
+ * I = max_v img[r][w][v] / N_r (0 if N_r = 0).  ROI r is kept iff for some
+ * window w with bit w of window_mask set, I[r][w] >= kappa * max_r' I[r'][w]
+ * (FP32).  Every kept ROI's grid cell (edge h, centred on the ROI) is split
+ * into split^3 cells whose centres are written, ordered by kept ROI, then x,
+ * y, z sub-cell: c + h (2i + 1 - split) / (2 split) per axis (the offset
+ * evaluated in FP64 and rounded to FP32, the sum in FP32).
+ *   centres      device float [n_roi][3];  images device float [n_roi][n_win][n_dir]
+ *   counts       device int32 [n_roi]
+ *   n_win        1 .. 32;  split 1 .. 16
+ *   out_centres  device float [cap][3], out;  out_parent device int32 [cap] or NULL, out
+ *   n_out        host int64, out: refined ROIs (kept * split^3)
+ * AR_EINVAL if cap < n_out (n_out is still written).  Synchronises.
+ */
+ar_status ar_refine_roi_grid(ar_context *ctx, const float *centres, const float *images,
+                             const int32_t *counts, int64_t n_roi, int32_t n_win, int32_t n_dir,
+                             uint32_t window_mask, float kappa, float h, int32_t split,
+                             float *out_centres, int32_t *out_parent, int64_t cap, int64_t *n_out,
+                             void *stream);
+
+/*
  * Disorientation angle in degrees under cubic symmetry (supplement,
  * "Creation of test orientations": the misorientation with the smallest
  * rotation angle among the symmetrically equivalent ones), FP64:

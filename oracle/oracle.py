@@ -329,8 +329,9 @@ def refine_roi_grid(centres, images, counts, window_mask: int, kappa: float, h: 
     cap = int(n_roi) * split ** 3
     out = np.zeros((max(cap, 1), 3), np.float32)
     par = np.zeros(max(cap, 1), np.int32)
-    n_keep = lib().orc_refine_roi_grid(c, img, cnt, n_roi, n_win, n_dir, window_mask, kappa, h, split, keep, out,
-                                       par, cap)
+    # the cell edge is a single-precision parameter of the method's interface
+    n_keep = lib().orc_refine_roi_grid(c, img, cnt, n_roi, n_win, n_dir, window_mask, kappa, float(np.float32(h)),
+                                       split, keep, out, par, cap)
     n = int(n_keep) * split ** 3
     return keep, out[:n], par[:n]
 

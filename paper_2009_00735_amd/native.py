@@ -52,6 +52,8 @@ _SIGS = {
     "ar_sparse_lut_export": ([vp, vp, vp, vp, vp], ctypes.c_int),
     "index_orientations_sparse": ([vp, vp, i64, vp, i32, vp, vp, vp], ctypes.c_int),
     "ar_fsp_amplitudes": ([vp, vp, vp, i64, i32, f32, vp, vp], ctypes.c_int),
+    "ar_refine_roi_grid": ([vp, vp, vp, vp, i64, i32, i32, ctypes.c_uint32, f32, f32, i32, vp, vp, i64, P(i64), vp],
+                           ctypes.c_int),
     "index_orientations_ex": ([vp, vp, i64, vp, i32, i32, vp, vp, vp, vp], ctypes.c_int),
     "ar_disorientation_cubic": ([vp, vp, i64, vp, vp], ctypes.c_int),
     "ar_rotate_reference": ([vp, vp, i32, i32, vp, i32, vp, vp, i64, vp, vp], ctypes.c_int),
@@ -422,6 +424,22 @@ def ar_fsp_amplitudes(ctx: Context, rel: torch.Tensor, offsets: torch.Tensor, L:
     _call("ar_fsp_amplitudes", ctx.handle, _dev(rel, torch.float32, d, "rel"), _dev(offsets, torch.int64, d, "offsets"),
           n_roi, L, k_max, _dev(out, torch.float32, d, "out"), _stream(d))
     return out
+
+
+def ar_refine_roi_grid(ctx: Context, centres: torch.Tensor, images: torch.Tensor, counts: torch.Tensor,
+                       window_mask: int, kappa: float, h: float, split: int = 5):
+    """-> (refined centres float32 [n][3], parent int32 [n]) of the coarse ROIs
+    that pass the kappa test (see include/araullo.h)."""
+    d = ctx.device
+    n_roi, n_win, n_dir = images.shape
+    cap = n_roi * split ** 3
+    out = torch.empty((max(cap, 1), 3), dtype=torch.float32, device=d)
+    par = torch.empty(max(cap, 1), dtype=torch.int32, device=d)
+    n = i64()
+    _call("ar_refine_roi_grid", ctx.handle, _dev(centres, torch.float32, d, "centres"),
+          _dev(images, torch.float32, d, "images"), _dev(counts, torch.int32, d, "counts"), n_roi, n_win, n_dir,
+          window_mask, kappa, h, split, out.data_ptr(), par.data_ptr(), cap, ctypes.byref(n), _stream(d))
+    return out[:n.value], par[:n.value]
 
 
 def ar_disorientation_cubic(qa: torch.Tensor, qb: torch.Tensor) -> torch.Tensor:

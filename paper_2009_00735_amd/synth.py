@@ -586,3 +586,35 @@ def fsp_specimen(n_roi: int = 10000, R: float = 2.0, box: float = 24.0, eta: flo
         pos = pos[delete_exact(len(pos), eta, gen)]
     cen = R + gen.random((n_roi, 3)) * (box - 2 * R)
     return pos.astype(np.float32), cen.astype(np.float32), q
+
+
+# --------------------------------------------------------------------------
+# coarse ROI grids and a bicrystal (Sec. 3.4: ROIs on a cubic grid over an
+# aluminium bicrystal, then local refinement)
+# --------------------------------------------------------------------------
+def roi_grid(lo, hi, h: float) -> np.ndarray:
+    """ROI centres lo + h (i + 1/2) along each axis inside [lo, hi), float32 [n][3]."""
+    lo = np.asarray(lo, np.float64)
+    hi = np.asarray(hi, np.float64)
+    n = np.floor((hi - lo) / h).astype(int)
+    axes = [lo[a] + h * (np.arange(n[a]) + 0.5) for a in range(3)]
+    g = np.stack(np.meshgrid(*axes, indexing="ij"), axis=-1).reshape(-1, 3)
+    return g.astype(np.float32)
+
+
+def bicrystal(box: float = 12.0, eta: float = 0.5, sigma: tuple = (0.02, 0.08), seed: int = 0):
+    """Two fcc Al grains filling the cube [0, box)^3, split at x = box/2, with
+    seeded orientations; grain 0 is displaced by sigma[0], grain 1 by sigma[1]
+    (a sharp and a blurred grain).  Returns (positions float32, grain int32, q [2][4])."""
+    gen = np.random.Generator(np.random.PCG64(np.random.SeedSequence([SEED_ROOT, 31, seed])))
+    q = shoemake(2, gen)
+    parts, gid = [], []
+    for g in range(2):
+        lo = np.array([g * box / 2, 0.0, 0.0])
+        hi = np.array([(g + 1) * box / 2, box, box])
+        p = lattice_in_box("fcc", A_AL, q[g], gen.random(3), lo, hi)
+        p = p[delete_exact(len(p), eta, gen)]
+        p = p + gen.normal(0.0, sigma[g], p.shape)
+        parts.append(p)
+        gid.append(np.full(len(p), g, np.int32))
+    return np.concatenate(parts).astype(np.float32), np.concatenate(gid), q
