@@ -425,6 +425,27 @@ def compare(nat, synth, torch, dev):
             "top1_disorientation_median_deg": float(np.median(dis_sp)),
             "top1_disorientation_p95_deg": float(np.percentile(dis_sp, 95))}
         del lut
+    # the oracle beside it, on a bounded sample: strongest entries and the
+    # look-up rows of 400 orientations (N^ = 1000), then Eq. S1 for 16 ROIs
+    # against those orientations; rates extrapolate per unit of work
+    from oracle import oracle as orc
+    threads = orc.default_threads()
+    t0 = time.perf_counter()
+    osi, osv = orc.sparse_strong(ref.cpu().numpy(), 1000)
+    sub = np.linspace(0, n_rot - 1, 400).astype(int)
+    qs = lib_q.cpu().numpy()[sub]
+    olut = orc.sparse_lut(qs, np.zeros(len(sub), np.int32), osi, dirs.cpu().numpy(), threads)
+    t_olut = time.perf_counter() - t0
+    Sh16 = orc.normalise(images[:16].cpu().numpy())
+    t0 = time.perf_counter()
+    orc.sparse_index_topk(Sh16, osi, osv, np.zeros(len(sub), np.int32), olut, 16, threads)
+    t_oidx = time.perf_counter() - t0
+    sparse["cpu_oracle"] = {
+        "kind": "oracle", "cores": threads,
+        "sample": "N^ = 1000: strongest entries + look-up rows of 400 of the 20000 orientations; Eq. S1 (FP64) "
+                  "for 16 ROIs against those 400",
+        "lut_rows_per_s": len(sub) / t_olut, "terms_per_s": 16 * len(sub) * 1000 / t_oidx,
+        "full_call_estimate_s": 2000 * n_rot * 1000 / (16 * len(sub) * 1000 / t_oidx)}
     rec["sparse_indexing_cfg2"] = sparse
     log("compare: indexing done")
     # sub-lattice signatures: an L1_2 Al3Sc crystal (eta 0.5, sigma 0.03 nm),
@@ -447,6 +468,12 @@ def compare(nat, synth, torch, dev):
         "typed_ms": t_typed, "untyped_ms": t_untyped, "typed_over_untyped": t_typed / t_untyped,
         "roi_dir_channel_per_s": len(cen) * int(dirs.shape[0]) * 3 / (t_typed / 1e3),
         "note": "each channel = one typed ROI query + the plain signature kernel + a pitched copy"}
+    t0 = time.perf_counter()
+    orc.signatures_typed(pos, types, masks, cen[:2], 2.0, dirs.cpu().numpy(), 1024, w5.numpy(), threads)
+    t_ot = time.perf_counter() - t0
+    rec["typed_signatures_l12"]["cpu_oracle"] = {
+        "kind": "oracle", "cores": threads, "sample": "2 ROIs x 3 channels, all 10242 directions",
+        "roi_dir_channel_per_s": 2 * 3 * int(dirs.shape[0]) / t_ot}
     log("compare: typed signatures done")
     # reciprocal-space signatures on a cubic grid (Eq. (2)): the paper's
     # benchmark shape, 10^4 ROIs of R = 2 nm in full-density fcc Al, L = 64
@@ -469,6 +496,16 @@ def compare(nat, synth, torch, dev):
                         "frac_of_measured_fp32_mfma": flops / (t / 1e3) / peaks["fp32_mfma_flop_per_s"],
                         "output_gb": n * L ** 3 * 4 / 1e9}
         del out
+    x0 = orc.roi_gather(pos, cen[0], 2.0)
+    kk = orc.fsp_grid_k(64, 10.0)
+    idx = np.random.default_rng(0).integers(0, 64, (2048, 3))
+    t0 = time.perf_counter()
+    orc.fsp_at(x0, kk[idx])
+    t_of = time.perf_counter() - t0
+    fsp["cpu_oracle"] = {
+        "kind": "oracle", "cores": 1, "sample": f"1 ROI ({len(x0)} atoms) x 2048 grid points, FP64, one thread",
+        "flop_per_s": 8.0 * len(x0) * 2048 / t_of,
+        "L64_estimate_s": n_atoms * 64 ** 3 / (len(x0) * 2048 / t_of)}
     rec["fsp_cubic_grid"] = fsp
     log("compare: reciprocal-space grid done")
     del rel, off
