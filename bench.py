@@ -477,7 +477,7 @@ def compare(nat, synth, torch, dev):
     log("compare: typed signatures done")
     # reciprocal-space signatures on a cubic grid (Eq. (2)): the paper's
     # benchmark shape, 10^4 ROIs of R = 2 nm in full-density fcc Al, L = 64
-    # (and 2000 of them at L = 128); algorithmic work 8 N_w L^3 flop per ROI
+    # (and fewer of them at L = 128, 256, 512); algorithmic work 8 N_w L^3 flop per ROI
     # (one complex multiply-add per atom and grid point)
     del pos_d, types_d, cen_d
     pos, cen, _ = synth.fsp_specimen(10000, 2.0)
@@ -486,7 +486,7 @@ def compare(nat, synth, torch, dev):
     n_atoms = int(off[-1])
     fsp = {"rois": len(cen), "mean_atoms": n_atoms / len(cen), "k_max_per_nm": 10.0,
            "measured_fp32_mfma_flop_per_s": peaks["fp32_mfma_flop_per_s"]}
-    for L, n in ((64, len(cen)), (128, 2000)):
+    for L, n in ((64, len(cen)), (128, 2000), (256, 200), (512, 24)):
         o = off[:n + 1]
         out = torch.empty((n, L, L, L), dtype=torch.float32, device=dev)
         t = best_ms(lambda: nat.ar_fsp_amplitudes(ctx, rel, o, L, 10.0, out=out))

@@ -9,28 +9,33 @@
 //                       entries (larger key first, equal keys by lower flat
 //                       index w * n_dir + v) by counting; ranks < n_hat are
 //                       the strong entries in decreasing order.
-//   3. k_window_order   the strong entries regrouped by window (stable), the
-//                       order the screen kernel walks them in, with their
-//                       values as FP16 pairs.
-//   4. k_sparse_lut     for every orientation g of phase c and strong entry i:
+//   3. k_window_count   strong entries per window; the host pads every
+//                       window's segment to a multiple of 4 rows.
+//   4. k_window_order   the strong entries regrouped by window (stable) into
+//                       the padded rows the screens walk, with their values as
+//                       FP16 pairs and as 8-bit codes round(255 R) (padding
+//                       rows: value 0, node = the zero node n_dir).
+//   5. k_sparse_lut     for every orientation g of phase c and strong entry i:
 //                       the mesh node closest to R(q_g) n_{v_i}.
-//   5. k_lut_rows       the same table transposed to one row per orientation.
+//   6. k_lut_rows       the same table transposed to one row per orientation.
 //
-// Indexing (index_orientations_sparse):
-//   1. k_sparse_norm    per (ROI, window) 1 / max in FP32; the normalised
-//                       image in FP16, RB ROIs interleaved per node.
-//   2. k_sparse_screen  one workgroup per (orientation chunk, group of RB
-//                       ROIs): for each window, the RB ROI images of that
-//                       window sit in LDS (RB FP16 values per node, one
-//                       8/4/2-byte read per look-up); every lane owns four
-//                       orientations, reads their look-up nodes (one 8-byte
-//                       load per strong entry), forms s - R in packed FP16
-//                       and accumulates the squares in FP32.  The
-//                       workgroup keeps the CAND best orientations per ROI
-//                       (per-wave selection, then a merge in LDS).
-//   3. k_sparse_merge   per ROI, the CAND best over all chunks.
-//   4. k_sparse_rescore exact FP32 Eq. S1 for the CAND candidates from the
-//                       FP32 image; sorted by (Delta, index).
+// Indexing (index_orientations_sparse): a screen keeps CAND candidates per
+// ROI, k_sparse_merge combines the orientation chunks and k_sparse_rescore
+// evaluates exact FP32 Eq. S1 for the candidates from the FP32 image.  Each
+// screen workgroup takes (a chunk of 4096 orientations of one phase, a group
+// of ROIs): for each window the group's ROI images of that window sit in LDS
+// (node-major, plus a zero node), every lane owns four orientations and reads
+// their node ids with one 8-byte load per strong entry.  Two screens:
+//   * k_sparse_screen8 (meshes whose 8-ROI slab fits LDS): 8 ROIs per node as
+//     8-bit codes round(255 s) in one 8-byte LDS read; per lane and
+//     orientation, four entries' reads are byte-transposed (v_perm_b32) so
+//     that v_dot4_u32_u8 accumulates sum s^2 and sum s R exactly in integers;
+//     score = sum s^2 - 2 sum s R + sum R^2 (in 255^2 units).
+//   * k_sparse_screen<RB> (wider meshes, RB = 2 or 1): RB ROIs per node in
+//     FP16; s - R in packed FP16 (v_pk_add_f16), squares accumulated in FP32
+//     (v_fma_mix_f32).
+// Either way the workgroup keeps the CAND best orientations per ROI
+// (per-wave selection, then a merge in LDS).
 #include <math.h>
 
 #include <algorithm>
@@ -46,14 +51,18 @@ struct ar_sparse_lut {
     int32_t n_phase = 0, n_win = 0, n_dir = 0, n_hat = 0;
     int64_t n_lib = 0;
     int64_t ld = 0;                      // row length of lut_ig (orientations + padding)
+    int32_t n_rows = 0;                  // screen rows per phase (window segments padded to multiples of 4)
     int32_t n_chunks = 0;
+    int32_t screen = 0;                  // 8: 8-bit screen with 8 ROIs per read; 2, 1: FP16 screen with RB ROIs
     ar::DeviceBuffer phase_start;        // int64 [n_phase + 1]
     ar::DeviceBuffer strong_idx;         // int32 [n_phase][n_hat], w * n_dir + v, decreasing value
     ar::DeviceBuffer strong_val;         // float [n_phase][n_hat], normalised value
-    ar::DeviceBuffer kpos;               // int32 [n_phase][n_hat], position of entry i in window order
-    ar::DeviceBuffer kval2;              // uint32 [n_phase][n_hat]: (R, R) in FP16, window order
-    ar::DeviceBuffer seg;                // int32 [n_phase][n_win + 1], window segments of the window order
-    ar::DeviceBuffer lut_ig;             // uint16 [n_hat][ld], window order of each column's phase
+    ar::DeviceBuffer kpos;               // int32 [n_phase][n_hat], screen row of entry i
+    ar::DeviceBuffer kval2;              // uint32 [n_phase][n_rows]: (R, R) in FP16 per screen row
+    ar::DeviceBuffer kq8;                // uint8 [n_phase][n_rows]: round(255 R) per screen row
+    ar::DeviceBuffer q2sum;              // uint32 [n_phase]: sum of the squared 8-bit codes
+    ar::DeviceBuffer seg;                // int32 [n_phase][n_win + 1], padded window segments of the screen rows
+    ar::DeviceBuffer lut_ig;             // uint16 [n_rows][ld], screen rows of each column's phase
     ar::DeviceBuffer lut_gi;             // uint16 [n_lib][n_hat], decreasing-value order
     ar::DeviceBuffer chunks;             // int4 [n_chunks]: phase, first column (multiple of 4), valid [lo, hi)
 };
@@ -63,12 +72,14 @@ namespace sparse {
 
 constexpr int kThreads = 1024;               // screen workgroup: 16 waves
 constexpr int kWaves = kThreads / 64;
-constexpr int kPerLane = 4;                  // orientations per lane
-constexpr int kChunk = kPerLane * kThreads;  // orientations per workgroup
+constexpr int kPerLane = 4;                  // orientations per lane (FP16 screens)
+constexpr int kPerLane8 = 2;                 // orientations per lane (8-bit screen)
+constexpr int kChunk = kPerLane * kThreads;  // largest chunk: orientations per workgroup
 
 typedef _Float16 half2_t __attribute__((ext_vector_type(2)));
 typedef _Float16 half4_t __attribute__((ext_vector_type(4)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
 
 // ------------------------------------------------------------ look-up table
 __global__ __launch_bounds__(256) void k_ref_max(const float *__restrict__ ref, int n_dir, float *__restrict__ out)
@@ -119,34 +130,44 @@ __global__ __launch_bounds__(256) void k_strong_rank(const float *__restrict__ r
     }
 }
 
-// grid (ceil(n_hat / 256), n_phase): window order = stable regrouping of the
-// strong entries by window; seg[c][w] = number of strong entries in windows
-// below w.
+// grid (ceil(n_hat / 256), n_phase): strong entries per window (count is zeroed)
+__global__ __launch_bounds__(256) void k_window_count(const int32_t *__restrict__ strong_idx, int n_hat, int n_win,
+                                                      int n_dir, int32_t *__restrict__ count)
+{
+    const int c = blockIdx.y;
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i < n_hat) atomicAdd(&count[(size_t)c * n_win + strong_idx[(size_t)c * n_hat + i] / n_dir], 1);
+}
+
+// grid (ceil(n_hat / 256), n_phase): screen row of strong entry i = the
+// padded start of its window + its rank among the entries of that window;
+// the row's FP16 pair and 8-bit code; q2sum[c] accumulates the squared codes.
 __global__ __launch_bounds__(256) void k_window_order(const int32_t *__restrict__ strong_idx,
                                                       const float *__restrict__ strong_val, int n_hat, int n_win,
-                                                      int n_dir, int32_t *__restrict__ kpos, uint32_t *__restrict__ kval2,
-                                                      int32_t *__restrict__ seg)
+                                                      int n_dir, const int32_t *__restrict__ seg, int n_rows,
+                                                      int32_t *__restrict__ kpos, uint32_t *__restrict__ kval2,
+                                                      uint8_t *__restrict__ kq8, uint32_t *__restrict__ q2sum)
 {
     const int c = blockIdx.y;
     const int32_t *si = strong_idx + (size_t)c * n_hat;
     const int i = blockIdx.x * 256 + threadIdx.x;
-    if (i < n_hat) {
-        const int wi = si[i] / n_dir;
-        int pos = 0;
-        for (int j = 0; j < n_hat; ++j) {
-            const int wj = si[j] / n_dir;
-            pos += (wj < wi || (wj == wi && j < i)) ? 1 : 0;
-        }
-        kpos[(size_t)c * n_hat + i] = pos;
-        const _Float16 h = (_Float16)strong_val[(size_t)c * n_hat + i];
-        kval2[(size_t)c * n_hat + pos] = __builtin_bit_cast(uint32_t, half2_t{h, h});
-    }
-    if (blockIdx.x == 0)
-        for (int w = threadIdx.x; w <= n_win; w += 256) {
-            int cnt = 0;
-            for (int j = 0; j < n_hat; ++j) cnt += (si[j] / n_dir < w) ? 1 : 0;
-            seg[(size_t)c * (n_win + 1) + w] = cnt;
-        }
+    if (i >= n_hat) return;
+    const int wi = si[i] / n_dir;
+    int pos = seg[(size_t)c * (n_win + 1) + wi];
+    for (int j = 0; j < i; ++j) pos += (si[j] / n_dir == wi) ? 1 : 0;
+    kpos[(size_t)c * n_hat + i] = pos;
+    const float v = strong_val[(size_t)c * n_hat + i];
+    const _Float16 h = (_Float16)v;
+    kval2[(size_t)c * n_rows + pos] = __builtin_bit_cast(uint32_t, half2_t{h, h});
+    const uint32_t q = (uint32_t)rintf(255.0f * fminf(fmaxf(v, 0.0f), 1.0f));
+    kq8[(size_t)c * n_rows + pos] = (uint8_t)q;
+    atomicAdd(&q2sum[c], q * q);
+}
+
+__global__ __launch_bounds__(256) void k_fill_u16(uint16_t *__restrict__ p, int64_t n, uint16_t v)
+{
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (t < n) p[t] = v;
 }
 
 __device__ __forceinline__ int phase_of(int64_t g, const int64_t *__restrict__ phase_start, int n_phase)
@@ -231,20 +252,6 @@ __device__ __forceinline__ uint32_t node_offset(uint32_t pair)
 template <int RB>
 struct RoiVec;
 template <>
-struct RoiVec<4> {
-    static constexpr int SHIFT = 3;
-    __device__ __forceinline__ static void acc(uint32_t off, uint32_t R2, float (&a)[4])
-    {
-        const half4_t x = *lds_at<const half4_t>(off);
-        const half2_t R = __builtin_bit_cast(half2_t, R2);
-        const half2_t d01 = x.xy - R, d23 = x.zw - R;
-        a[0] = fmaf((float)d01.x, (float)d01.x, a[0]);
-        a[1] = fmaf((float)d01.y, (float)d01.y, a[1]);
-        a[2] = fmaf((float)d23.x, (float)d23.x, a[2]);
-        a[3] = fmaf((float)d23.y, (float)d23.y, a[3]);
-    }
-};
-template <>
 struct RoiVec<2> {
     static constexpr int SHIFT = 2;
     __device__ __forceinline__ static void acc(uint32_t off, uint32_t R2, float (&a)[2])
@@ -264,18 +271,13 @@ struct RoiVec<1> {
     }
 };
 
-// grid (n_grp, n_win).  inv_s[r][w] = 1 / max (0 for an all-zero window);
-// half[grp][w][slab]: node v of ROI grp * RB + j at half index v * RB + j
-// (ROIs past n_roi and the slab padding are zero).
+// Per (ROI, window) 1 / max in FP32 (0 for an all-zero window) for RB ROIs of
+// a group, block-wide; inv_s[r][w] is written for ROIs below n_roi.
 template <int RB>
-__global__ __launch_bounds__(256) void k_sparse_norm(const float *__restrict__ img, int64_t n_roi, int n_win, int n_dir,
-                                                     int64_t slab, float *__restrict__ inv_s,
-                                                     _Float16 *__restrict__ half)
+__device__ __forceinline__ void group_inverse_max(const float *__restrict__ img, int64_t n_roi, int n_win, int n_dir,
+                                                  int64_t grp, int w, float *red, float *inv,
+                                                  float *__restrict__ inv_s)
 {
-    __shared__ float red[256];
-    __shared__ float inv[RB];
-    const int64_t grp = blockIdx.x;
-    const int w = blockIdx.y;
     for (int j = 0; j < RB; ++j) {
         const int64_t r = grp * RB + j;
         float m = 0.0f;
@@ -296,6 +298,21 @@ __global__ __launch_bounds__(256) void k_sparse_norm(const float *__restrict__ i
         }
         __syncthreads();
     }
+}
+
+// grid (n_grp, n_win).  half[grp][w][slab]: node v of ROI grp * RB + j at half
+// index v * RB + j, FP16 of the normalised value; node n_dir (the zero node),
+// ROIs past n_roi and the slab padding are zero.
+template <int RB>
+__global__ __launch_bounds__(256) void k_sparse_norm(const float *__restrict__ img, int64_t n_roi, int n_win, int n_dir,
+                                                     int64_t slab, float *__restrict__ inv_s,
+                                                     _Float16 *__restrict__ half)
+{
+    __shared__ float red[256];
+    __shared__ float inv[RB];
+    const int64_t grp = blockIdx.x;
+    const int w = blockIdx.y;
+    group_inverse_max<RB>(img, n_roi, n_win, n_dir, grp, w, red, inv, inv_s);
     _Float16 *dst = half + ((size_t)grp * n_win + w) * slab;
     for (int64_t t = threadIdx.x; t < slab; t += 256) {
         const int v = (int)(t / RB), j = (int)(t - (int64_t)v * RB);
@@ -306,83 +323,92 @@ __global__ __launch_bounds__(256) void k_sparse_norm(const float *__restrict__ i
     }
 }
 
-// grid: the (chunk, ROI group) work items padded to a multiple of 8; item t
-// runs on XCD t / (grid / 8), so the 32 compute units of an XCD share the
-// look-up rows of one chunk in their L2.
-// out_s/out_i: [n_grp * RB][n_chunks][CAND]
-template <int RB, int CAND>
-__global__ __launch_bounds__(kThreads) void k_sparse_screen(
-    const _Float16 *__restrict__ half, int n_win, int64_t slab, const uint16_t *__restrict__ lut_ig, int64_t ld,
-    const uint32_t *__restrict__ kval2, const int32_t *__restrict__ seg, int n_hat, const int4 *__restrict__ chunks,
-    int n_chunks, int n_grp, int64_t n_work, float *__restrict__ out_s, int32_t *__restrict__ out_i)
+// grid (n_grp, n_win), 8 ROIs per group.  q8[grp][w][slab bytes]: byte
+// v * 8 + j = round(255 s) of ROI grp * 8 + j at node v, s the normalised value
+// (clamped to [0, 1]); node n_dir, ROIs past n_roi and padding are zero.
+__global__ __launch_bounds__(256) void k_sparse_norm8(const float *__restrict__ img, int64_t n_roi, int n_win,
+                                                      int n_dir, int64_t slab, float *__restrict__ inv_s,
+                                                      uint32_t *__restrict__ q8)
 {
-    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ float red[256];
+    __shared__ float inv[8];
+    const int64_t grp = blockIdx.x;
+    const int w = blockIdx.y;
+    group_inverse_max<8>(img, n_roi, n_win, n_dir, grp, w, red, inv, inv_s);
+    uint32_t *dst = q8 + ((size_t)grp * n_win + w) * (slab >> 2);
+    // one thread per (node, half of the 8 ROIs): a 4-byte word
+    for (int64_t t = threadIdx.x; t < (slab >> 2); t += 256) {
+        const int v = (int)(t >> 1), h = (int)(t & 1);
+        uint32_t word = 0;
+        if (v < n_dir)
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                const int j = 4 * h + b;
+                const int64_t r = grp * 8 + j;
+                if (r < n_roi) {
+                    const float x = img[((size_t)r * n_win + w) * n_dir + v] * inv[j];
+                    word |= (uint32_t)rintf(255.0f * fminf(fmaxf(x, 0.0f), 1.0f)) << (8 * b);
+                }
+            }
+        dst[t] = word;
+    }
+}
+
+// Bytes (r, r+1, r+2, r+3 of dword a_k) regrouped per r: t[r] byte k = byte r
+// of a_k (a 4 x 4 byte transpose, eight v_perm_b32).
+__device__ __forceinline__ void transpose4(uint32_t a0, uint32_t a1, uint32_t a2, uint32_t a3, uint32_t (&t)[4])
+{
+    const uint32_t p0 = __builtin_amdgcn_perm(a1, a0, 0x05010400u);   // a0.0 a1.0 a0.1 a1.1
+    const uint32_t p1 = __builtin_amdgcn_perm(a1, a0, 0x07030602u);   // a0.2 a1.2 a0.3 a1.3
+    const uint32_t p2 = __builtin_amdgcn_perm(a3, a2, 0x05010400u);   // a2.0 a3.0 a2.1 a3.1
+    const uint32_t p3 = __builtin_amdgcn_perm(a3, a2, 0x07030602u);   // a2.2 a3.2 a2.3 a3.3
+    t[0] = __builtin_amdgcn_perm(p2, p0, 0x05040100u);
+    t[1] = __builtin_amdgcn_perm(p2, p0, 0x07060302u);
+    t[2] = __builtin_amdgcn_perm(p3, p1, 0x05040100u);
+    t[3] = __builtin_amdgcn_perm(p3, p1, 0x07060302u);
+}
+
+// The work item of a screen workgroup: the (chunk, ROI group) items are
+// padded to a multiple of 8 workgroups; item t runs on XCD t / (grid / 8), so
+// the 32 compute units of an XCD share the look-up rows of one chunk in L2.
+__device__ __forceinline__ bool screen_item(int64_t n_work, int n_grp, int &chunk, int &grp)
+{
     const int64_t nb8 = gridDim.x >> 3;
     const int64_t t = (int64_t)(blockIdx.x & 7) * nb8 + (blockIdx.x >> 3);
-    if (t >= n_work) return;
-    const int chunk = (int)(t / n_grp);
-    const int grp = (int)(t - (int64_t)chunk * n_grp);
-    const int4 ch = chunks[chunk];
-    const int tid = threadIdx.x;
-    // each lane owns orientations ch.y + 4 tid .. + 3: one 8-byte load of
-    // their four node ids per strong entry from a wave-uniform row address
-    const uint16_t *lut_c = lut_ig + ch.y;
-    const unsigned utid = threadIdx.x;
-    const uint32_t *kv2 = kval2 + (size_t)ch.x * n_hat;
-    const int32_t *sg = seg + (size_t)ch.x * (n_win + 1);
+    if (t >= n_work) return false;
+    chunk = (int)(t / n_grp);
+    grp = (int)(t - (int64_t)chunk * n_grp);
+    return true;
+}
 
-    float acc[kPerLane][RB];
-#pragma unroll
-    for (int g = 0; g < kPerLane; ++g)
-#pragma unroll
-        for (int r = 0; r < RB; ++r) acc[g][r] = 0.0f;
+// Copy `bytes` (a multiple of 16) from global memory to LDS address 0.
+__device__ __forceinline__ void fill_slab(const void *src, int64_t bytes)
+{
+    const u32x4 *s = reinterpret_cast<const u32x4 *>(src);
+    const int n16 = (int)(bytes >> 4);
+    for (int q = threadIdx.x; q < n16; q += kThreads) *lds_at<u32x4>(16u * q) = s[q];
+}
 
-    constexpr int SH = RoiVec<RB>::SHIFT;
-    auto term = [&](uint2 pr, uint32_t R2) {
-        RoiVec<RB>::acc(node_offset<SH, 0>(pr.x), R2, acc[0]);
-        RoiVec<RB>::acc(node_offset<SH, 1>(pr.x), R2, acc[1]);
-        RoiVec<RB>::acc(node_offset<SH, 0>(pr.y), R2, acc[2]);
-        RoiVec<RB>::acc(node_offset<SH, 1>(pr.y), R2, acc[3]);
-    };
-
-    for (int w = 0; w < n_win; ++w) {
-        const int j0 = sg[w], j1 = sg[w + 1];
-        if (j0 == j1) continue;
-        __syncthreads();   // every wave is done with the previous window
-        {
-            const u32x4 *src = reinterpret_cast<const u32x4 *>(half + ((size_t)grp * n_win + w) * slab);
-            const int n16 = (int)(slab >> 3);
-            for (int q = tid; q < n16; q += kThreads) *lds_at<u32x4>(16u * q) = src[q];
-        }
-        __syncthreads();
-        int j = j0;
-        for (; j + 4 <= j1; j += 4) {
-            uint2 pr[4];
-            uint32_t R2[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                pr[u] = reinterpret_cast<const uint2 *>(lut_c + (size_t)(j + u) * ld)[utid];
-                R2[u] = kv2[j + u];
-            }
-#pragma unroll
-            for (int u = 0; u < 4; ++u) term(pr[u], R2[u]);
-        }
-        for (; j < j1; ++j) term(reinterpret_cast<const uint2 *>(lut_c + (size_t)j * ld)[utid], kv2[j]);
-    }
-
-    // ---- the CAND best orientations of this chunk per ROI
-    const int wave = tid >> 6, lane = tid & 63;
-    __syncthreads();   // LDS now holds the wave lists
+// The CAND best orientations of the chunk per ROI: per-wave selection over
+// the lanes' orientations, then one merge wave per ROI over the wave lists in
+// LDS.  out_s/out_i: [n_grp * RB][n_chunks][CAND].
+template <int PL, int RB, int CAND, typename Score>
+__device__ __forceinline__ void screen_topk(const int4 &ch, int chunk, int grp, int n_chunks, Score score,
+                                            float *__restrict__ out_s, int32_t *__restrict__ out_i)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    __syncthreads();   // every wave is done with the slab; LDS now holds the wave lists
     float *ws = reinterpret_cast<float *>(smem);
     int32_t *wi = reinterpret_cast<int32_t *>(smem + sizeof(float) * kWaves * RB * CAND);
 #pragma unroll
     for (int r = 0; r < RB; ++r) {
-        TopList<kPerLane> tl;
+        TopList<PL> tl;
         tl.init();
 #pragma unroll
-        for (int g = 0; g < kPerLane; ++g) {
-            const int gi = ch.y + kPerLane * tid + g;
-            if (gi >= ch.z && gi < ch.w) tl.insert(acc[g][r], gi);
+        for (int g = 0; g < PL; ++g) {
+            const int gi = ch.y + PL * tid + g;
+            if (gi >= ch.z && gi < ch.w) tl.insert(score(g, r), gi);
         }
         wave_select<CAND>(tl, [&](int j, float bs, int bi) {
             if (lane == 0) {
@@ -411,6 +437,150 @@ __global__ __launch_bounds__(kThreads) void k_sparse_screen(
             }
         });
     }
+}
+
+// FP16 screen, RB ROIs per node.  Window segments are multiples of 4 rows.
+template <int RB, int CAND>
+__global__ __launch_bounds__(kThreads) void k_sparse_screen(
+    const _Float16 *__restrict__ half, int n_win, int64_t slab, const uint16_t *__restrict__ lut_ig, int64_t ld,
+    const uint32_t *__restrict__ kval2, const int32_t *__restrict__ seg, int n_rows, const int4 *__restrict__ chunks,
+    int n_chunks, int n_grp, int64_t n_work, float *__restrict__ out_s, int32_t *__restrict__ out_i)
+{
+    int chunk, grp;
+    if (!screen_item(n_work, n_grp, chunk, grp)) return;
+    const int4 ch = chunks[chunk];
+    // each lane owns orientations ch.y + 4 tid .. + 3: one 8-byte load of
+    // their four node ids per screen row
+    const uint16_t *lut_c = lut_ig + ch.y;
+    const unsigned utid = threadIdx.x;
+    const uint32_t *kv2 = kval2 + (size_t)ch.x * n_rows;
+    const int32_t *sg = seg + (size_t)ch.x * (n_win + 1);
+
+    float acc[kPerLane][RB];
+#pragma unroll
+    for (int g = 0; g < kPerLane; ++g)
+#pragma unroll
+        for (int r = 0; r < RB; ++r) acc[g][r] = 0.0f;
+
+    constexpr int SH = RoiVec<RB>::SHIFT;
+    for (int w = 0; w < n_win; ++w) {
+        const int j0 = sg[w], j1 = sg[w + 1];
+        if (j0 == j1) continue;
+        __syncthreads();   // every wave is done with the previous window
+        fill_slab(half + ((size_t)grp * n_win + w) * slab, slab * 2);
+        __syncthreads();
+        for (int j = j0; j < j1; j += 4) {
+            uint2 pr[4];
+            uint32_t R2[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                pr[u] = reinterpret_cast<const uint2 *>(lut_c + (size_t)(j + u) * ld)[utid];
+                R2[u] = kv2[j + u];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                RoiVec<RB>::acc(node_offset<SH, 0>(pr[u].x), R2[u], acc[0]);
+                RoiVec<RB>::acc(node_offset<SH, 1>(pr[u].x), R2[u], acc[1]);
+                RoiVec<RB>::acc(node_offset<SH, 0>(pr[u].y), R2[u], acc[2]);
+                RoiVec<RB>::acc(node_offset<SH, 1>(pr[u].y), R2[u], acc[3]);
+            }
+        }
+    }
+    screen_topk<kPerLane, RB, CAND>(ch, chunk, grp, n_chunks, [&](int g, int r) { return acc[g][r]; }, out_s, out_i);
+}
+
+// 8-bit screen, 8 ROIs per node (one 8-byte read); each lane owns two
+// orientations (a 4-byte load of their node ids per row).  Per lane and
+// orientation, the reads of four rows are byte-transposed so that one
+// v_dot4_u32_u8 adds four rows of s^2 (or s R) for one ROI.  Score in 255^2
+// units: sum s^2 - 2 sum s R + sum R^2 (exact integers, as FP32).
+template <int CAND>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_sparse_screen8(
+    const uint32_t *__restrict__ q8, int n_win, int64_t slab, const uint16_t *__restrict__ lut_ig, int64_t ld,
+    const uint32_t *__restrict__ kq4, const uint32_t *__restrict__ q2sum, const int32_t *__restrict__ seg, int n_rows,
+    const int4 *__restrict__ chunks, int n_chunks, int n_grp, int64_t n_work, float *__restrict__ out_s,
+    int32_t *__restrict__ out_i)
+{
+    int chunk, grp;
+    if (!screen_item(n_work, n_grp, chunk, grp)) return;
+    const int4 ch = chunks[chunk];
+    const uint16_t *lut_c = lut_ig + ch.y;
+    const unsigned utid = threadIdx.x;
+    const uint32_t *rq = kq4 + (size_t)ch.x * (n_rows >> 2);   // four rows' codes per word
+    const int32_t *sg = seg + (size_t)ch.x * (n_win + 1);
+
+    uint32_t ss[kPerLane8][8], sr[kPerLane8][8];
+#pragma unroll
+    for (int g = 0; g < kPerLane8; ++g)
+#pragma unroll
+        for (int r = 0; r < 8; ++r) ss[g][r] = sr[g][r] = 0u;
+
+    for (int w = 0; w < n_win; ++w) {
+        const int j0 = sg[w], j1 = sg[w + 1];
+        if (j0 == j1) continue;
+        __syncthreads();
+        fill_slab(q8 + ((size_t)grp * n_win + w) * (slab >> 2), slab);
+        __syncthreads();
+        // rows j .. j + 3 of the lane's two orientations: node ids in pr, the
+        // four rows' reference codes in R4
+        auto score4 = [&](const uint32_t (&pr)[4], int j) {
+            const uint32_t R4 = rq[j >> 2];
+            u32x2 x[kPerLane8][4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                x[0][u] = *lds_at<const u32x2>(node_offset<3, 0>(pr[u]));
+                x[1][u] = *lds_at<const u32x2>(node_offset<3, 1>(pr[u]));
+            }
+#pragma unroll
+            for (int g = 0; g < kPerLane8; ++g) {
+                uint32_t t[4];
+                transpose4(x[g][0].x, x[g][1].x, x[g][2].x, x[g][3].x, t);
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    ss[g][r] = __builtin_amdgcn_udot4(t[r], t[r], ss[g][r], false);
+                    sr[g][r] = __builtin_amdgcn_udot4(t[r], R4, sr[g][r], false);
+                }
+                transpose4(x[g][0].y, x[g][1].y, x[g][2].y, x[g][3].y, t);
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    ss[g][4 + r] = __builtin_amdgcn_udot4(t[r], t[r], ss[g][4 + r], false);
+                    sr[g][4 + r] = __builtin_amdgcn_udot4(t[r], R4, sr[g][4 + r], false);
+                }
+            }
+        };
+        // the node ids of the next four rows load while these are scored: an
+        // odd leading group alone, then pairs of groups in two register sets
+        // (the last prefetch repeats the final rows)
+        const int64_t step = ld >> 1;   // one row in 4-byte words
+        const uint32_t *base = reinterpret_cast<const uint32_t *>(lut_c) + utid;
+        auto load4 = [&](uint32_t (&pr)[4], int j) {
+            const uint32_t *p = base + (int64_t)j * step;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) pr[u] = p[u * step];
+        };
+        uint32_t pa[4], pb[4];
+        int j = j0;
+        if (((j1 - j0) >> 2) & 1) {
+            load4(pa, j);
+            score4(pa, j);
+            j += 4;
+        }
+        if (j < j1) {
+            load4(pa, j);
+            for (; j < j1; j += 8) {
+                load4(pb, j + 4);
+                __builtin_amdgcn_sched_barrier(0);   // keep each load a half-iteration ahead of its use
+                score4(pa, j);
+                load4(pa, j + 8 < j1 ? j + 8 : j1 - 4);
+                __builtin_amdgcn_sched_barrier(0);
+                score4(pb, j + 4);
+            }
+        }
+    }
+    const int64_t c2 = (int64_t)q2sum[ch.x];
+    screen_topk<kPerLane8, 8, CAND>(
+        ch, chunk, grp, n_chunks,
+        [&](int g, int r) { return (float)((int64_t)ss[g][r] - 2 * (int64_t)sr[g][r] + c2); }, out_s, out_i);
 }
 
 // One wave per ROI: the CAND best over its n_lists lists.
@@ -495,60 +665,108 @@ __global__ __launch_bounds__(256) void k_sparse_rescore(
     }
 }
 
-// ROIs per screen workgroup: the largest of 4, 2, 1 whose window slab fits
-// the LDS of one workgroup.
-int rois_per_block(const ar_context *ctx, int n_dir)
+// Slab bytes of one (ROI group, window): n_dir + 1 nodes (the last is the
+// zero node of the padding rows) of `per_node` bytes, rounded up to 16.
+int64_t slab_bytes(int n_dir, int per_node) { return ((int64_t)(n_dir + 1) * per_node + 15) / 16 * 16; }
+
+// The screen for a mesh: 8 (8-bit codes, 8 ROIs per node) if that slab fits
+// the LDS of one workgroup, else 2 or 1 FP16 ROIs per node; 0 if none fits.
+int pick_screen(const ar_context *ctx, int n_dir)
 {
-    for (int rb = 4; rb > 1; rb >>= 1)
-        if ((int64_t)(n_dir * rb + 7) / 8 * 16 <= ctx->lds_per_block) return rb;
-    return 1;
+    if (slab_bytes(n_dir, 8) <= ctx->lds_per_block) return 8;
+    if (slab_bytes(n_dir, 4) <= ctx->lds_per_block) return 2;
+    if (slab_bytes(n_dir, 2) <= ctx->lds_per_block) return 1;
+    return 0;
 }
 
-int64_t slab_halves(int n_dir, int rb) { return ((int64_t)n_dir * rb + 7) / 8 * 8; }
+// Shared tail of both screens: merge the chunk lists, rescore the candidates.
+template <int CAND>
+ar_status merge_rescore(ar_context *ctx, const ar_sparse_lut *lut, const float *images, int64_t n_roi, int k,
+                        int32_t *top_idx, float *top_score, hipStream_t s)
+{
+    k_sparse_merge<CAND><<<(unsigned)((n_roi + 3) / 4), 256, 0, s>>>(
+        ctx->sp_cand_s.as<float>(), ctx->sp_cand_i.as<int32_t>(), lut->n_chunks, n_roi, ctx->sp_merge.as<int32_t>());
+    AR_HIP(hipGetLastError());
+    k_sparse_rescore<CAND><<<(unsigned)n_roi, 256, 0, s>>>(
+        images, ctx->sp_inv.as<float>(), lut->n_win, lut->n_dir, lut->strong_idx.as<int32_t>(),
+        lut->strong_val.as<float>(), lut->lut_gi.as<uint16_t>(), lut->n_hat, lut->phase_start.as<int64_t>(),
+        lut->n_phase, lut->n_lib, ctx->sp_merge.as<int32_t>(), k, top_idx, top_score);
+    AR_HIP(hipGetLastError());
+    return AR_OK;
+}
+
+// RB ROIs per group (8 for the 8-bit screen): workspace and launch shape.
+struct ScreenPlan {
+    int64_t n_grp, slab, n_work, blocks;
+    size_t lds;
+};
+
+template <int RB, int CAND>
+ar_status plan_screen(ar_context *ctx, const ar_sparse_lut *lut, int64_t n_roi, int per_node, ScreenPlan &p)
+{
+    p.n_grp = (n_roi + RB - 1) / RB;
+    p.slab = slab_bytes(lut->n_dir, per_node);
+    p.lds = std::max((size_t)p.slab, (size_t)kWaves * RB * CAND * 8);
+    AR_CHECK((size_t)ctx->lds_per_block >= p.lds, "sparse screen needs %zu bytes of LDS", p.lds);
+    AR_CHECK(p.n_grp < (int64_t)INT32_MAX, "too many ROIs");
+    p.n_work = p.n_grp * lut->n_chunks;
+    p.blocks = (p.n_work + 7) / 8 * 8;
+    AR_CHECK(p.blocks < (int64_t)INT32_MAX, "too many screen workgroups");
+    AR_TRY(ctx->sp_half.reserve((size_t)(p.n_grp * lut->n_win * p.slab)));
+    AR_TRY(ctx->sp_inv.reserve(sizeof(float) * (size_t)(n_roi * lut->n_win)));
+    AR_TRY(ctx->sp_cand_s.reserve(sizeof(float) * (size_t)(p.n_grp * RB * lut->n_chunks * CAND)));
+    AR_TRY(ctx->sp_cand_i.reserve(sizeof(int32_t) * (size_t)(p.n_grp * RB * lut->n_chunks * CAND)));
+    AR_TRY(ctx->sp_merge.reserve(sizeof(int32_t) * (size_t)(n_roi * CAND)));
+    return AR_OK;
+}
+
+template <typename K>
+ar_status allow_lds(K kernel, size_t lds, bool &done)
+{
+    if (!done && lds > 65536) {
+        AR_HIP(hipFuncSetAttribute((const void *)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+        done = true;
+    }
+    return AR_OK;
+}
 
 template <int RB, int CAND>
 ar_status run_screen(ar_context *ctx, const ar_sparse_lut *lut, const float *images, int64_t n_roi, int k,
                      int32_t *top_idx, float *top_score, hipStream_t s)
 {
-    const int n_win = lut->n_win, n_dir = lut->n_dir;
-    const int64_t n_grp = (n_roi + RB - 1) / RB;
-    const int64_t slab = slab_halves(n_dir, RB);
-    const size_t lds = std::max((size_t)slab * 2, (size_t)kWaves * RB * CAND * 8);
-    AR_CHECK((size_t)ctx->lds_per_block >= lds, "sparse screen needs %zu bytes of LDS", lds);
-    AR_CHECK(n_grp < (int64_t)INT32_MAX, "too many ROIs");
-    const int64_t n_work = n_grp * lut->n_chunks;
-    const int64_t blocks = (n_work + 7) / 8 * 8;
-    AR_CHECK(blocks < (int64_t)INT32_MAX, "too many screen workgroups");
-
-    AR_TRY(ctx->sp_half.reserve(sizeof(_Float16) * (size_t)(n_grp * n_win * slab)));
-    AR_TRY(ctx->sp_inv.reserve(sizeof(float) * (size_t)(n_roi * n_win)));
-    AR_TRY(ctx->sp_cand_s.reserve(sizeof(float) * (size_t)(n_grp * RB * lut->n_chunks * CAND)));
-    AR_TRY(ctx->sp_cand_i.reserve(sizeof(int32_t) * (size_t)(n_grp * RB * lut->n_chunks * CAND)));
-    AR_TRY(ctx->sp_merge.reserve(sizeof(int32_t) * (size_t)(n_roi * CAND)));
-
-    k_sparse_norm<RB><<<dim3((unsigned)n_grp, (unsigned)n_win), 256, 0, s>>>(
-        images, n_roi, n_win, n_dir, slab, ctx->sp_inv.as<float>(), ctx->sp_half.as<_Float16>());
+    ScreenPlan p;
+    AR_TRY((plan_screen<RB, CAND>(ctx, lut, n_roi, 2 * RB, p)));
+    k_sparse_norm<RB><<<dim3((unsigned)p.n_grp, (unsigned)lut->n_win), 256, 0, s>>>(
+        images, n_roi, lut->n_win, lut->n_dir, p.slab / 2, ctx->sp_inv.as<float>(), ctx->sp_half.as<_Float16>());
     AR_HIP(hipGetLastError());
     static bool attr_set = false;   // per instantiation
-    if (!attr_set && lds > 65536) {
-        AR_HIP(hipFuncSetAttribute((const void *)k_sparse_screen<RB, CAND>,
-                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-        attr_set = true;
-    }
-    k_sparse_screen<RB, CAND><<<(unsigned)blocks, kThreads, lds, s>>>(
-        ctx->sp_half.as<_Float16>(), n_win, slab, lut->lut_ig.as<uint16_t>(), lut->ld, lut->kval2.as<uint32_t>(),
-        lut->seg.as<int32_t>(), lut->n_hat, lut->chunks.as<int4>(), lut->n_chunks, (int)n_grp, n_work,
-        ctx->sp_cand_s.as<float>(), ctx->sp_cand_i.as<int32_t>());
+    AR_TRY(allow_lds(k_sparse_screen<RB, CAND>, p.lds, attr_set));
+    k_sparse_screen<RB, CAND><<<(unsigned)p.blocks, kThreads, p.lds, s>>>(
+        ctx->sp_half.as<_Float16>(), lut->n_win, p.slab / 2, lut->lut_ig.as<uint16_t>(), lut->ld,
+        lut->kval2.as<uint32_t>(), lut->seg.as<int32_t>(), lut->n_rows, lut->chunks.as<int4>(), lut->n_chunks,
+        (int)p.n_grp, p.n_work, ctx->sp_cand_s.as<float>(), ctx->sp_cand_i.as<int32_t>());
     AR_HIP(hipGetLastError());
-    k_sparse_merge<CAND><<<(unsigned)((n_roi + 3) / 4), 256, 0, s>>>(
-        ctx->sp_cand_s.as<float>(), ctx->sp_cand_i.as<int32_t>(), lut->n_chunks, n_roi, ctx->sp_merge.as<int32_t>());
+    return merge_rescore<CAND>(ctx, lut, images, n_roi, k, top_idx, top_score, s);
+}
+
+template <int CAND>
+ar_status run_screen8(ar_context *ctx, const ar_sparse_lut *lut, const float *images, int64_t n_roi, int k,
+                      int32_t *top_idx, float *top_score, hipStream_t s)
+{
+    ScreenPlan p;
+    AR_TRY((plan_screen<8, CAND>(ctx, lut, n_roi, 8, p)));
+    k_sparse_norm8<<<dim3((unsigned)p.n_grp, (unsigned)lut->n_win), 256, 0, s>>>(
+        images, n_roi, lut->n_win, lut->n_dir, p.slab, ctx->sp_inv.as<float>(), ctx->sp_half.as<uint32_t>());
     AR_HIP(hipGetLastError());
-    k_sparse_rescore<CAND><<<(unsigned)n_roi, 256, 0, s>>>(
-        images, ctx->sp_inv.as<float>(), n_win, n_dir, lut->strong_idx.as<int32_t>(), lut->strong_val.as<float>(),
-        lut->lut_gi.as<uint16_t>(), lut->n_hat, lut->phase_start.as<int64_t>(), lut->n_phase, lut->n_lib,
-        ctx->sp_merge.as<int32_t>(), k, top_idx, top_score);
+    static bool attr_set = false;   // per instantiation
+    AR_TRY(allow_lds(k_sparse_screen8<CAND>, p.lds, attr_set));
+    k_sparse_screen8<CAND><<<(unsigned)p.blocks, kThreads, p.lds, s>>>(
+        ctx->sp_half.as<uint32_t>(), lut->n_win, p.slab, lut->lut_ig.as<uint16_t>(), lut->ld,
+        lut->kq8.as<uint32_t>(), lut->q2sum.as<uint32_t>(), lut->seg.as<int32_t>(), lut->n_rows,
+        lut->chunks.as<int4>(), lut->n_chunks, (int)p.n_grp, p.n_work, ctx->sp_cand_s.as<float>(),
+        ctx->sp_cand_i.as<int32_t>());
     AR_HIP(hipGetLastError());
-    return AR_OK;
+    return merge_rescore<CAND>(ctx, lut, images, n_roi, k, top_idx, top_score, s);
 }
 
 }  // namespace sparse
@@ -581,13 +799,14 @@ ar_status ar_sparse_lut_create(ar_context *ctx, const float *reference, int32_t 
     AR_HIP(hipSetDevice(ctx->device));
     hipStream_t s = (hipStream_t)stream;
 
-    // screen chunks: per phase, columns from the multiple of four at or below its start
+    // screen chunks: per phase, columns from the multiple of four at or below
+    // its start, as many per chunk as the screen's workgroup covers
+    const int screen = sparse::pick_screen(ctx, n_dir);
+    const int64_t chunk = (screen == 8 ? sparse::kPerLane8 : sparse::kPerLane) * sparse::kThreads;
     std::vector<int4> ch;
     for (int c = 0; c < n_phase; ++c)
-        for (int64_t a = start[c] & ~(int64_t)(sparse::kPerLane - 1); start[c] < start[c + 1] && a < start[c + 1];
-             a += sparse::kChunk)
-            ch.push_back(make_int4(c, (int)a, (int)std::max(a, start[c]),
-                                   (int)std::min(a + sparse::kChunk, start[c + 1])));
+        for (int64_t a = start[c] & ~(int64_t)3; start[c] < start[c + 1] && a < start[c + 1]; a += chunk)
+            ch.push_back(make_int4(c, (int)a, (int)std::max(a, start[c]), (int)std::min(a + chunk, start[c + 1])));
 
     auto *lut = new (std::nothrow) ar_sparse_lut();
     if (!lut) return fail(AR_ENOMEM, "look-up table allocation failed");
@@ -599,9 +818,10 @@ ar_status ar_sparse_lut_create(ar_context *ctx, const float *reference, int32_t 
     lut->n_lib = n_lib;
     lut->ld = (n_lib + sparse::kChunk + 63) / 64 * 64;
     lut->n_chunks = (int32_t)ch.size();
+    lut->screen = screen;
     const size_t nh = (size_t)n_phase * n_hat;
-    ar::DeviceBuffer ref_max;
-    ar_status st = AR_OK;
+    ar::DeviceBuffer ref_max, count;
+    ar_status st = lut->screen ? AR_OK : fail(AR_EINVAL, "no screen layout fits %d nodes in LDS", n_dir);
     auto step = [&](ar_status x) {
         if (st == AR_OK) st = x;
     };
@@ -609,23 +829,24 @@ ar_status ar_sparse_lut_create(ar_context *ctx, const float *reference, int32_t 
         hipError_t e = hipGetLastError();
         if (st == AR_OK && e != hipSuccess) st = fail(AR_EDEVICE, "%s: %s", name, hipGetErrorString(e));
     };
+    auto hip = [&](hipError_t e, const char *what) {
+        if (st == AR_OK && e != hipSuccess) st = fail(AR_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+    };
     step(lut->phase_start.reserve(sizeof(int64_t) * (n_phase + 1)));
     step(lut->strong_idx.reserve(sizeof(int32_t) * nh));
     step(lut->strong_val.reserve(sizeof(float) * nh));
     step(lut->kpos.reserve(sizeof(int32_t) * nh));
-    step(lut->kval2.reserve(sizeof(uint32_t) * nh));
     step(lut->seg.reserve(sizeof(int32_t) * n_phase * (n_win + 1)));
-    step(lut->lut_ig.reserve(sizeof(uint16_t) * (size_t)n_hat * lut->ld));
     step(lut->lut_gi.reserve(sizeof(uint16_t) * (size_t)n_lib * n_hat));
     step(lut->chunks.reserve(sizeof(int4) * ch.size()));
     step(ref_max.reserve(sizeof(float) * n_phase * n_win));
+    step(count.reserve(sizeof(int32_t) * n_phase * n_win));
     if (st == AR_OK) {
-        hipError_t e = hipMemcpyAsync(lut->phase_start.ptr, start.data(), sizeof(int64_t) * (n_phase + 1),
-                                      hipMemcpyHostToDevice, s);
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(lut->chunks.ptr, ch.data(), sizeof(int4) * ch.size(), hipMemcpyHostToDevice, s);
-        if (e == hipSuccess) e = hipMemsetAsync(lut->lut_ig.ptr, 0, sizeof(uint16_t) * (size_t)n_hat * lut->ld, s);
-        if (e != hipSuccess) st = fail(AR_EDEVICE, "look-up table upload: %s", hipGetErrorString(e));
+        hip(hipMemcpyAsync(lut->phase_start.ptr, start.data(), sizeof(int64_t) * (n_phase + 1), hipMemcpyHostToDevice,
+                           s), "look-up table upload");
+        hip(hipMemcpyAsync(lut->chunks.ptr, ch.data(), sizeof(int4) * ch.size(), hipMemcpyHostToDevice, s),
+            "look-up table upload");
+        hip(hipMemsetAsync(count.ptr, 0, sizeof(int32_t) * n_phase * n_win, s), "look-up table upload");
     }
     if (st == AR_OK) {
         sparse::k_ref_max<<<(unsigned)(n_phase * n_win), 256, 0, s>>>(reference, n_dir, ref_max.as<float>());
@@ -638,9 +859,47 @@ ar_status ar_sparse_lut_create(ar_context *ctx, const float *reference, int32_t 
         launched("k_strong_rank");
     }
     if (st == AR_OK) {
+        sparse::k_window_count<<<dim3((unsigned)((n_hat + 255) / 256), (unsigned)n_phase), 256, 0, s>>>(
+            lut->strong_idx.as<int32_t>(), n_hat, n_win, n_dir, count.as<int32_t>());
+        launched("k_window_count");
+    }
+    // padded window segments: every window starts on a multiple of 4 rows
+    std::vector<int32_t> cnt((size_t)n_phase * n_win, 0), seg((size_t)n_phase * (n_win + 1), 0);
+    if (st == AR_OK) {
+        hip(hipMemcpyAsync(cnt.data(), count.ptr, sizeof(int32_t) * cnt.size(), hipMemcpyDeviceToHost, s),
+            "window counts");
+        hip(hipStreamSynchronize(s), "window counts");
+    }
+    int32_t n_rows = 4;
+    for (int c = 0; c < n_phase; ++c) {
+        int32_t *sc = seg.data() + (size_t)c * (n_win + 1);
+        for (int w = 0; w < n_win; ++w) sc[w + 1] = sc[w] + (cnt[(size_t)c * n_win + w] + 3) / 4 * 4;
+        n_rows = std::max(n_rows, sc[n_win]);
+    }
+    lut->n_rows = n_rows;
+    const size_t nr = (size_t)n_phase * n_rows;
+    step(lut->kval2.reserve(sizeof(uint32_t) * nr));
+    step(lut->kq8.reserve(nr));
+    step(lut->q2sum.reserve(sizeof(uint32_t) * n_phase));
+    step(lut->lut_ig.reserve(sizeof(uint16_t) * (size_t)n_rows * lut->ld));
+    if (st == AR_OK) {
+        hip(hipMemcpyAsync(lut->seg.ptr, seg.data(), sizeof(int32_t) * seg.size(), hipMemcpyHostToDevice, s),
+            "look-up table upload");
+        hip(hipMemsetAsync(lut->kval2.ptr, 0, sizeof(uint32_t) * nr, s), "look-up table upload");
+        hip(hipMemsetAsync(lut->kq8.ptr, 0, nr, s), "look-up table upload");
+        hip(hipMemsetAsync(lut->q2sum.ptr, 0, sizeof(uint32_t) * n_phase, s), "look-up table upload");
+    }
+    if (st == AR_OK) {
+        const int64_t n = (int64_t)n_rows * lut->ld;   // padding rows and columns: the zero node
+        sparse::k_fill_u16<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(lut->lut_ig.as<uint16_t>(), n,
+                                                                       (uint16_t)n_dir);
+        launched("k_fill_u16");
+    }
+    if (st == AR_OK) {
         sparse::k_window_order<<<dim3((unsigned)((n_hat + 255) / 256), (unsigned)n_phase), 256, 0, s>>>(
-            lut->strong_idx.as<int32_t>(), lut->strong_val.as<float>(), n_hat, n_win, n_dir, lut->kpos.as<int32_t>(),
-            lut->kval2.as<uint32_t>(), lut->seg.as<int32_t>());
+            lut->strong_idx.as<int32_t>(), lut->strong_val.as<float>(), n_hat, n_win, n_dir, lut->seg.as<int32_t>(),
+            n_rows, lut->kpos.as<int32_t>(), lut->kval2.as<uint32_t>(), lut->kq8.as<uint8_t>(),
+            lut->q2sum.as<uint32_t>());
         launched("k_window_order");
     }
     if (st == AR_OK) {
@@ -703,14 +962,14 @@ ar_status index_orientations_sparse(ar_context *ctx, const float *images, int64_
     AR_CHECK(lut->ctx == ctx, "look-up table belongs to another context");
     AR_HIP(hipSetDevice(ctx->device));
     hipStream_t s = (hipStream_t)stream;
-    const int rb = sparse::rois_per_block(ctx, lut->n_dir);
+    const int sc = lut->screen;
     if (k <= 16) {
-        if (rb == 4) return sparse::run_screen<4, 16>(ctx, lut, images, n_roi, k, top_idx, top_score, s);
-        if (rb == 2) return sparse::run_screen<2, 16>(ctx, lut, images, n_roi, k, top_idx, top_score, s);
+        if (sc == 8) return sparse::run_screen8<16>(ctx, lut, images, n_roi, k, top_idx, top_score, s);
+        if (sc == 2) return sparse::run_screen<2, 16>(ctx, lut, images, n_roi, k, top_idx, top_score, s);
         return sparse::run_screen<1, 16>(ctx, lut, images, n_roi, k, top_idx, top_score, s);
     }
-    if (rb == 4) return sparse::run_screen<4, 32>(ctx, lut, images, n_roi, k, top_idx, top_score, s);
-    if (rb == 2) return sparse::run_screen<2, 32>(ctx, lut, images, n_roi, k, top_idx, top_score, s);
+    if (sc == 8) return sparse::run_screen8<32>(ctx, lut, images, n_roi, k, top_idx, top_score, s);
+    if (sc == 2) return sparse::run_screen<2, 32>(ctx, lut, images, n_roi, k, top_idx, top_score, s);
     return sparse::run_screen<1, 32>(ctx, lut, images, n_roi, k, top_idx, top_score, s);
 }
 
