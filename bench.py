@@ -402,8 +402,6 @@ def compare(nat, synth, torch, dev):
     sparse = {"rois": int(images.shape[0]), "orientations": n_rot, "k": 16,
               "dense_ms": t_bf16, "dense_top1_disorientation_median_deg": float(np.median(dis_dense))}
     peaks = nat.ar_measure_peaks(ctx)
-    rb = 4 if images.shape[2] * 8 <= 163840 else (2 if images.shape[2] * 4 <= 163840 else 1)
-    sparse["screen_rois_per_lds_read"] = rb
     sparse["measured_lds_gather8_per_s"] = peaks["lds_gather8_per_s"]
     for n_hat in (250, 1000, 4000):
         torch.cuda.synchronize()
@@ -411,6 +409,8 @@ def compare(nat, synth, torch, dev):
         lut = nat.SparseLUT(ctx, ref.contiguous(), dirs, lib_q, [n_rot], n_hat)
         torch.cuda.synchronize()
         t_lut = (time.perf_counter() - t0) * 1e3
+        rb = lut.screen
+        sparse["screen_rois_per_lds_read"] = rb
         t_sp = best_ms(lambda: nat.index_orientations_sparse(ctx, images, lut, 16))
         idx_sp, _ = nat.index_orientations_sparse(ctx, images, lut, 16)
         dis_sp = nat.ar_disorientation_cubic(lib_q[idx_sp[:, 0].long()].contiguous(), truth).cpu().numpy()

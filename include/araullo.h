@@ -297,14 +297,20 @@ ar_status ar_sparse_lut_destroy(ar_sparse_lut *lut);
  *   nodes      device int32 [n_lib][n_hat]: p(g, i) */
 ar_status ar_sparse_lut_export(const ar_sparse_lut *lut, int32_t *strong_idx, float *strong_val,
                                int32_t *nodes, void *stream);
+/* The screen the table's mesh gets, as ROIs per LDS read (host int32, out):
+ * 8 (8-bit codes, when the 8-ROI window slab and the phase's reference codes
+ * fit the LDS of one workgroup), else 2 or 1 (FP16). */
+ar_status ar_sparse_lut_screen(const ar_sparse_lut *lut, int32_t *rois_per_read);
 
 /*
  * The k library entries with the smallest sparse Eq. S1
  *   Delta(r, g) = sum_i (S_r[w_i][p(g, i)] / max_v S_r[w_i] - R_i)^2
- * (w_i the window of strong entry i of g's phase).  A screen in FP16 image
- * values with FP32 accumulation keeps 16 (k <= 16) or 32 candidates per
- * ROI, which are rescored in FP32 from the FP32 image; the output is sorted
- * ascending by (FP32 Delta, library index).
+ * (w_i the window of strong entry i of g's phase).  A screen keeps 16
+ * (k <= 16) or 32 candidates per ROI and chunk of orientations: in 8-bit
+ * codes round(255 x) of the normalised image and of R_i with exact integer
+ * sums, or (meshes too large for that) in FP16 values with FP32
+ * accumulation.  The merged candidates are rescored in FP32 from the FP32
+ * image; the output is sorted ascending by (FP32 Delta, library index).
  *   images    device float [n_roi][n_win][n_dir] (raw signatures), n_roi >= 1
  *   k         1 .. 32
  *   top_idx   device int32 [n_roi][k], out;  top_score device float [n_roi][k], out

@@ -325,32 +325,71 @@ __global__ __launch_bounds__(256) void k_sparse_norm(const float *__restrict__ i
 
 // grid (n_grp, n_win), 8 ROIs per group.  q8[grp][w][slab bytes]: byte
 // v * 8 + j = round(255 s) of ROI grp * 8 + j at node v, s the normalised value
-// (clamped to [0, 1]); node n_dir, ROIs past n_roi and padding are zero.
+// (clamped to [0, 1]); node n_dir, ROIs past n_roi and padding are zero.  The
+// eight window maxima are taken together (one pass, eight loads in flight).
 __global__ __launch_bounds__(256) void k_sparse_norm8(const float *__restrict__ img, int64_t n_roi, int n_win,
                                                       int n_dir, int64_t slab, float *__restrict__ inv_s,
                                                       uint32_t *__restrict__ q8)
 {
-    __shared__ float red[256];
+    __shared__ float part[4][8];
     __shared__ float inv[8];
     const int64_t grp = blockIdx.x;
     const int w = blockIdx.y;
-    group_inverse_max<8>(img, n_roi, n_win, n_dir, grp, w, red, inv, inv_s);
-    uint32_t *dst = q8 + ((size_t)grp * n_win + w) * (slab >> 2);
-    // one thread per (node, half of the 8 ROIs): a 4-byte word
-    for (int64_t t = threadIdx.x; t < (slab >> 2); t += 256) {
-        const int v = (int)(t >> 1), h = (int)(t & 1);
-        uint32_t word = 0;
-        if (v < n_dir)
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int nr = (int)min((int64_t)8, n_roi - grp * 8);
+    const float *src = img + ((size_t)grp * 8 * n_win + w) * n_dir;   // ROI j at src + j * n_win * n_dir
+    const size_t rs = (size_t)n_win * n_dir;
+    // a thread takes four nodes (stride 256) of all eight ROIs per step: 32
+    // independent loads in flight
+    float m[8];
 #pragma unroll
-            for (int b = 0; b < 4; ++b) {
-                const int j = 4 * h + b;
-                const int64_t r = grp * 8 + j;
-                if (r < n_roi) {
-                    const float x = img[((size_t)r * n_win + w) * n_dir + v] * inv[j];
-                    word |= (uint32_t)rintf(255.0f * fminf(fmaxf(x, 0.0f), 1.0f)) << (8 * b);
-                }
+    for (int j = 0; j < 8; ++j) m[j] = 0.0f;
+    for (int v0 = tid; v0 < n_dir; v0 += 1024)
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int v = v0 + 256 * e;
+                if (j < nr && v < n_dir) m[j] = fmaxf(m[j], src[j * rs + v]);
             }
-        dst[t] = word;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) m[j] = fmaxf(m[j], __shfl_xor(m[j], off));
+        if (lane == 0) part[wave][j] = m[j];
+    }
+    __syncthreads();
+    if (tid < 8) {
+        const float mx = fmaxf(fmaxf(part[0][tid], part[1][tid]), fmaxf(part[2][tid], part[3][tid]));
+        inv[tid] = mx > 0.0f ? 1.0f / mx : 0.0f;
+        if (tid < nr) inv_s[(size_t)(grp * 8 + tid) * n_win + w] = inv[tid];
+    }
+    __syncthreads();
+    float iv[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) iv[j] = inv[j];
+    // node v's two words (ROIs 0-3, 4-7); four nodes per thread and step
+    uint2 *dst = reinterpret_cast<uint2 *>(q8 + ((size_t)grp * n_win + w) * (slab >> 2));
+    const int n_nodes = (int)(slab >> 3);   // slab / 8 bytes: nodes incl. the zero node and padding
+    for (int v0 = tid; v0 < n_nodes; v0 += 1024) {
+        float x[4][8];
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int v = v0 + 256 * e;
+                x[e][j] = (j < nr && v < n_dir) ? src[j * rs + v] : 0.0f;
+            }
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int v = v0 + 256 * e;
+            if (v >= n_nodes) break;
+            uint32_t word[2] = {0u, 0u};
+#pragma unroll
+            for (int j = 0; j < 8; ++j)
+                word[j >> 2] |= (uint32_t)rintf(255.0f * fminf(fmaxf(x[e][j] * iv[j], 0.0f), 1.0f)) << (8 * (j & 3));
+            dst[v] = make_uint2(word[0], word[1]);
+        }
     }
 }
 
@@ -493,7 +532,22 @@ __global__ __launch_bounds__(kThreads) void k_sparse_screen(
 // orientations (a 4-byte load of their node ids per row).  Per lane and
 // orientation, the reads of four rows are byte-transposed so that one
 // v_dot4_u32_u8 adds four rows of s^2 (or s R) for one ROI.  Score in 255^2
-// units: sum s^2 - 2 sum s R + sum R^2 (exact integers, as FP32).
+// units: sum s^2 - 2 sum s R + sum R^2, an exact integer, as FP32.
+//
+// Software pipeline over groups of four rows: the node ids of group i + 2
+// load from global memory and the LDS reads of group i + 1 are in flight
+// while group i is scored; the reference codes of the phase sit in LDS
+// behind the slab, so every LDS wait is in order.  LDS layout: the slab
+// [0, slab), the phase's codes [slab, slab + n_rows); after the last window
+// the scores [8][kChunk8] from 0.  Two waves per ROI then take the CAND best
+// of 1024 orientations each: out_s/out_i [n_grp * 8][n_chunks][2][CAND].
+constexpr int kChunk8 = kPerLane8 * kThreads;
+
+size_t screen8_lds(int64_t slab, int n_rows)
+{
+    return std::max((size_t)slab + (size_t)(n_rows + 15) / 16 * 16, sizeof(float) * 8 * kChunk8);
+}
+
 template <int CAND>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_sparse_screen8(
     const uint32_t *__restrict__ q8, int n_win, int64_t slab, const uint16_t *__restrict__ lut_ig, int64_t ld,
@@ -504,10 +558,13 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 4))
     int chunk, grp;
     if (!screen_item(n_work, n_grp, chunk, grp)) return;
     const int4 ch = chunks[chunk];
-    const uint16_t *lut_c = lut_ig + ch.y;
-    const unsigned utid = threadIdx.x;
-    const uint32_t *rq = kq4 + (size_t)ch.x * (n_rows >> 2);   // four rows' codes per word
+    const int tid = threadIdx.x;
     const int32_t *sg = seg + (size_t)ch.x * (n_win + 1);
+    const uint32_t rq = (uint32_t)slab;   // LDS byte offset of row 0's code
+    {
+        const uint32_t *src = kq4 + (size_t)ch.x * (n_rows >> 2);
+        for (int q = tid; q < (n_rows >> 2); q += kThreads) *lds_at<uint32_t>(rq + 4u * q) = src[q];
+    }
 
     uint32_t ss[kPerLane8][8], sr[kPerLane8][8];
 #pragma unroll
@@ -515,72 +572,109 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 4))
 #pragma unroll
         for (int r = 0; r < 8; ++r) ss[g][r] = sr[g][r] = 0u;
 
+    struct Rows {
+        u32x2 x[kPerLane8][4];   // 8 codes per node, rows j .. j + 3
+        uint32_t R4;             // the four rows' reference codes
+    };
+    const int64_t step = ld >> 1;   // one row of node ids in 4-byte words
+    const uint32_t *base = reinterpret_cast<const uint32_t *>(lut_ig + ch.y) + tid;
+    auto load4 = [&](uint32_t (&pr)[4], int j) {
+        const uint32_t *p = base + (int64_t)j * step;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) pr[u] = p[u * step];
+    };
+    auto gather = [&](const uint32_t (&pr)[4], int j, Rows &v) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            v.x[0][u] = *lds_at<const u32x2>(node_offset<3, 0>(pr[u]));
+            v.x[1][u] = *lds_at<const u32x2>(node_offset<3, 1>(pr[u]));
+        }
+        v.R4 = *lds_at<const uint32_t>(rq + (uint32_t)j);
+    };
+    auto score = [&](const Rows &v) {
+#pragma unroll
+        for (int g = 0; g < kPerLane8; ++g) {
+            uint32_t t[4];
+            transpose4(v.x[g][0].x, v.x[g][1].x, v.x[g][2].x, v.x[g][3].x, t);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                ss[g][r] = __builtin_amdgcn_udot4(t[r], t[r], ss[g][r], false);
+                sr[g][r] = __builtin_amdgcn_udot4(t[r], v.R4, sr[g][r], false);
+            }
+            transpose4(v.x[g][0].y, v.x[g][1].y, v.x[g][2].y, v.x[g][3].y, t);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                ss[g][4 + r] = __builtin_amdgcn_udot4(t[r], t[r], ss[g][4 + r], false);
+                sr[g][4 + r] = __builtin_amdgcn_udot4(t[r], v.R4, sr[g][4 + r], false);
+            }
+        }
+    };
+
     for (int w = 0; w < n_win; ++w) {
         const int j0 = sg[w], j1 = sg[w + 1];
         if (j0 == j1) continue;
-        __syncthreads();
+        __syncthreads();   // every wave is done with the previous window
         fill_slab(q8 + ((size_t)grp * n_win + w) * (slab >> 2), slab);
         __syncthreads();
-        // rows j .. j + 3 of the lane's two orientations: node ids in pr, the
-        // four rows' reference codes in R4
-        auto score4 = [&](const uint32_t (&pr)[4], int j) {
-            const uint32_t R4 = rq[j >> 2];
-            u32x2 x[kPerLane8][4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                x[0][u] = *lds_at<const u32x2>(node_offset<3, 0>(pr[u]));
-                x[1][u] = *lds_at<const u32x2>(node_offset<3, 1>(pr[u]));
-            }
-#pragma unroll
-            for (int g = 0; g < kPerLane8; ++g) {
-                uint32_t t[4];
-                transpose4(x[g][0].x, x[g][1].x, x[g][2].x, x[g][3].x, t);
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    ss[g][r] = __builtin_amdgcn_udot4(t[r], t[r], ss[g][r], false);
-                    sr[g][r] = __builtin_amdgcn_udot4(t[r], R4, sr[g][r], false);
-                }
-                transpose4(x[g][0].y, x[g][1].y, x[g][2].y, x[g][3].y, t);
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    ss[g][4 + r] = __builtin_amdgcn_udot4(t[r], t[r], ss[g][4 + r], false);
-                    sr[g][4 + r] = __builtin_amdgcn_udot4(t[r], R4, sr[g][4 + r], false);
-                }
-            }
-        };
-        // the node ids of the next four rows load while these are scored: an
-        // odd leading group alone, then pairs of groups in two register sets
-        // (the last prefetch repeats the final rows)
-        const int64_t step = ld >> 1;   // one row in 4-byte words
-        const uint32_t *base = reinterpret_cast<const uint32_t *>(lut_c) + utid;
-        auto load4 = [&](uint32_t (&pr)[4], int j) {
-            const uint32_t *p = base + (int64_t)j * step;
-#pragma unroll
-            for (int u = 0; u < 4; ++u) pr[u] = p[u * step];
-        };
         uint32_t pa[4], pb[4];
+        Rows va, vb;
         int j = j0;
-        if (((j1 - j0) >> 2) & 1) {
+        if (((j1 - j0) >> 2) & 1) {   // an odd leading group, unpipelined
             load4(pa, j);
-            score4(pa, j);
+            gather(pa, j, va);
+            score(va);
             j += 4;
         }
         if (j < j1) {
+            // an even number of groups from j: the prefetches past the end
+            // repeat the final group and are not scored
+            const int last = j1 - 4;
             load4(pa, j);
+            load4(pb, j + 4);
+            gather(pa, j, va);
             for (; j < j1; j += 8) {
-                load4(pb, j + 4);
-                __builtin_amdgcn_sched_barrier(0);   // keep each load a half-iteration ahead of its use
-                score4(pa, j);
-                load4(pa, j + 8 < j1 ? j + 8 : j1 - 4);
+                load4(pa, min(j + 8, last));
+                gather(pb, j + 4, vb);
                 __builtin_amdgcn_sched_barrier(0);
-                score4(pb, j + 4);
+                score(va);
+                __builtin_amdgcn_sched_barrier(0);
+                load4(pb, min(j + 12, last));
+                gather(pa, min(j + 8, last), va);
+                __builtin_amdgcn_sched_barrier(0);
+                score(vb);
+                __builtin_amdgcn_sched_barrier(0);
             }
         }
     }
+
+    // scores to LDS, then one merge wave per ROI
+    __syncthreads();
     const int64_t c2 = (int64_t)q2sum[ch.x];
-    screen_topk<kPerLane8, 8, CAND>(
-        ch, chunk, grp, n_chunks,
-        [&](int g, int r) { return (float)((int64_t)ss[g][r] - 2 * (int64_t)sr[g][r] + c2); }, out_s, out_i);
+#pragma unroll
+    for (int r = 0; r < 8; ++r)
+#pragma unroll
+        for (int g = 0; g < kPerLane8; ++g)
+            *lds_at<float>(4u * (uint32_t)(r * kChunk8 + kPerLane8 * tid + g)) =
+                (float)((int64_t)ss[g][r] - 2 * (int64_t)sr[g][r] + c2);
+    __syncthreads();
+    const int wave = tid >> 6, lane = tid & 63;
+    const int r = wave >> 1, half = wave & 1;   // two waves per ROI, 1024 orientations each
+    constexpr int PER = kChunk8 / 128;
+    TopList<PER> tl;
+    tl.init();
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        const int e = half * (kChunk8 / 2) + lane + 64 * q;
+        const int gi = ch.y + e;
+        if (gi >= ch.z && gi < ch.w) tl.insert(*lds_at<const float>(4u * (uint32_t)(r * kChunk8 + e)), gi);
+    }
+    const size_t o = ((((size_t)grp * 8 + r) * n_chunks + chunk) * 2 + half) * CAND;
+    wave_select<CAND>(tl, [&](int jj, float bs, int bi) {
+        if (lane == 0) {
+            out_s[o + jj] = bs;
+            out_i[o + jj] = bi;
+        }
+    });
 }
 
 // One wave per ROI: the CAND best over its n_lists lists.
@@ -602,8 +696,9 @@ __global__ __launch_bounds__(256) void k_sparse_merge(const float *__restrict__ 
     });
 }
 
-// One workgroup per ROI: exact FP32 Eq. S1 for each candidate (entries in
-// decreasing-value order), then the k best by (Delta, index).
+// One workgroup per ROI: exact FP32 Eq. S1 for each candidate, one wave per
+// candidate (lane l sums the entries l, l + 64, ... in decreasing-value
+// order, then a butterfly over the lanes), then the k best by (Delta, index).
 template <int CAND>
 __global__ __launch_bounds__(256) void k_sparse_rescore(
     const float *__restrict__ S, const float *__restrict__ inv_s, int n_win, int n_dir,
@@ -612,13 +707,13 @@ __global__ __launch_bounds__(256) void k_sparse_rescore(
     const int32_t *__restrict__ cand_idx, int k, int32_t *__restrict__ top_idx, float *__restrict__ top_score)
 {
 #pragma clang fp contract(off)
-    __shared__ float red[256];
     __shared__ float ds[CAND];
     __shared__ int di[CAND];
     const int64_t r = blockIdx.x;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const float *srow = S + (size_t)r * n_win * n_dir;
     const float *is = inv_s + (size_t)r * n_win;
-    for (int c = 0; c < CAND; ++c) {
+    for (int c = wave; c < CAND; c += 4) {
         const int l = cand_idx[(size_t)r * CAND + c];
         const bool ok = l >= 0 && l < n_lib;
         float acc = 0.0f;
@@ -627,24 +722,21 @@ __global__ __launch_bounds__(256) void k_sparse_rescore(
             const int32_t *si = strong_idx + (size_t)ph * n_hat;
             const float *sv = strong_val + (size_t)ph * n_hat;
             const uint16_t *row = lut_gi + (size_t)l * n_hat;
-            for (int i = threadIdx.x; i < n_hat; i += 256) {
+#pragma unroll 4
+            for (int i = lane; i < n_hat; i += 64) {
                 const int w = si[i] / n_dir;
                 const float d = srow[(size_t)w * n_dir + row[i]] * is[w] - sv[i];
                 acc = fmaf(d, d, acc);
             }
         }
-        red[threadIdx.x] = acc;
-        __syncthreads();
-        for (int s = 128; s > 0; s >>= 1) {
-            if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
-            __syncthreads();
-        }
-        if (threadIdx.x == 0) {
-            ds[c] = ok ? red[0] : INFINITY;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+        if (lane == 0) {
+            ds[c] = ok ? acc : INFINITY;
             di[c] = ok ? l : 0x7fffffff;
         }
-        __syncthreads();
     }
+    __syncthreads();
     if (threadIdx.x == 0) {
         for (int a = 1; a < CAND; ++a) {
             const float vs = ds[a];
@@ -669,23 +761,25 @@ __global__ __launch_bounds__(256) void k_sparse_rescore(
 // zero node of the padding rows) of `per_node` bytes, rounded up to 16.
 int64_t slab_bytes(int n_dir, int per_node) { return ((int64_t)(n_dir + 1) * per_node + 15) / 16 * 16; }
 
-// The screen for a mesh: 8 (8-bit codes, 8 ROIs per node) if that slab fits
-// the LDS of one workgroup, else 2 or 1 FP16 ROIs per node; 0 if none fits.
-int pick_screen(const ar_context *ctx, int n_dir)
+// The screen for a mesh: 8 (8-bit codes, 8 ROIs per node) if that slab and
+// n_rows reference codes fit the LDS of one workgroup, else 2 or 1 FP16 ROIs
+// per node; 0 if none fits.
+int pick_screen(const ar_context *ctx, int n_dir, int n_rows)
 {
-    if (slab_bytes(n_dir, 8) <= ctx->lds_per_block) return 8;
+    if ((int64_t)screen8_lds(slab_bytes(n_dir, 8), n_rows) <= ctx->lds_per_block) return 8;
     if (slab_bytes(n_dir, 4) <= ctx->lds_per_block) return 2;
     if (slab_bytes(n_dir, 2) <= ctx->lds_per_block) return 1;
     return 0;
 }
 
-// Shared tail of both screens: merge the chunk lists, rescore the candidates.
+// Shared tail of both screens: merge the n_lists lists of each ROI, rescore
+// the candidates.
 template <int CAND>
-ar_status merge_rescore(ar_context *ctx, const ar_sparse_lut *lut, const float *images, int64_t n_roi, int k,
-                        int32_t *top_idx, float *top_score, hipStream_t s)
+ar_status merge_rescore(ar_context *ctx, const ar_sparse_lut *lut, const float *images, int64_t n_roi, int n_lists,
+                        int k, int32_t *top_idx, float *top_score, hipStream_t s)
 {
     k_sparse_merge<CAND><<<(unsigned)((n_roi + 3) / 4), 256, 0, s>>>(
-        ctx->sp_cand_s.as<float>(), ctx->sp_cand_i.as<int32_t>(), lut->n_chunks, n_roi, ctx->sp_merge.as<int32_t>());
+        ctx->sp_cand_s.as<float>(), ctx->sp_cand_i.as<int32_t>(), n_lists, n_roi, ctx->sp_merge.as<int32_t>());
     AR_HIP(hipGetLastError());
     k_sparse_rescore<CAND><<<(unsigned)n_roi, 256, 0, s>>>(
         images, ctx->sp_inv.as<float>(), lut->n_win, lut->n_dir, lut->strong_idx.as<int32_t>(),
@@ -746,7 +840,7 @@ ar_status run_screen(ar_context *ctx, const ar_sparse_lut *lut, const float *ima
         lut->kval2.as<uint32_t>(), lut->seg.as<int32_t>(), lut->n_rows, lut->chunks.as<int4>(), lut->n_chunks,
         (int)p.n_grp, p.n_work, ctx->sp_cand_s.as<float>(), ctx->sp_cand_i.as<int32_t>());
     AR_HIP(hipGetLastError());
-    return merge_rescore<CAND>(ctx, lut, images, n_roi, k, top_idx, top_score, s);
+    return merge_rescore<CAND>(ctx, lut, images, n_roi, lut->n_chunks, k, top_idx, top_score, s);
 }
 
 template <int CAND>
@@ -755,6 +849,10 @@ ar_status run_screen8(ar_context *ctx, const ar_sparse_lut *lut, const float *im
 {
     ScreenPlan p;
     AR_TRY((plan_screen<8, CAND>(ctx, lut, n_roi, 8, p)));
+    p.lds = screen8_lds(p.slab, lut->n_rows);
+    AR_CHECK((size_t)ctx->lds_per_block >= p.lds, "sparse screen needs %zu bytes of LDS", p.lds);
+    AR_TRY(ctx->sp_cand_s.reserve(sizeof(float) * (size_t)(p.n_grp * 8 * lut->n_chunks * 2 * CAND)));
+    AR_TRY(ctx->sp_cand_i.reserve(sizeof(int32_t) * (size_t)(p.n_grp * 8 * lut->n_chunks * 2 * CAND)));
     k_sparse_norm8<<<dim3((unsigned)p.n_grp, (unsigned)lut->n_win), 256, 0, s>>>(
         images, n_roi, lut->n_win, lut->n_dir, p.slab, ctx->sp_inv.as<float>(), ctx->sp_half.as<uint32_t>());
     AR_HIP(hipGetLastError());
@@ -766,7 +864,7 @@ ar_status run_screen8(ar_context *ctx, const ar_sparse_lut *lut, const float *im
         lut->chunks.as<int4>(), lut->n_chunks, (int)p.n_grp, p.n_work, ctx->sp_cand_s.as<float>(),
         ctx->sp_cand_i.as<int32_t>());
     AR_HIP(hipGetLastError());
-    return merge_rescore<CAND>(ctx, lut, images, n_roi, k, top_idx, top_score, s);
+    return merge_rescore<CAND>(ctx, lut, images, n_roi, 2 * lut->n_chunks, k, top_idx, top_score, s);
 }
 
 }  // namespace sparse
@@ -801,7 +899,7 @@ ar_status ar_sparse_lut_create(ar_context *ctx, const float *reference, int32_t 
 
     // screen chunks: per phase, columns from the multiple of four at or below
     // its start, as many per chunk as the screen's workgroup covers
-    const int screen = sparse::pick_screen(ctx, n_dir);
+    const int screen = sparse::pick_screen(ctx, n_dir, n_hat + 3 * n_win);   // bound on the padded rows
     const int64_t chunk = (screen == 8 ? sparse::kPerLane8 : sparse::kPerLane) * sparse::kThreads;
     std::vector<int4> ch;
     for (int c = 0; c < n_phase; ++c)
@@ -949,6 +1047,13 @@ ar_status ar_sparse_lut_export(const ar_sparse_lut *lut, int32_t *strong_idx, fl
         sparse::k_lut_export<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(lut->lut_gi.as<uint16_t>(), n, nodes);
         AR_HIP(hipGetLastError());
     }
+    return AR_OK;
+}
+
+ar_status ar_sparse_lut_screen(const ar_sparse_lut *lut, int32_t *rois_per_read)
+{
+    AR_CHECK(lut != nullptr && rois_per_read != nullptr, "look-up table or rois_per_read is NULL");
+    *rois_per_read = lut->screen;
     return AR_OK;
 }
 

@@ -50,6 +50,7 @@ _SIGS = {
     "ar_sparse_lut_create": ([vp, vp, i32, i32, vp, i32, vp, P(i64), i32, vp, P(vp)], ctypes.c_int),
     "ar_sparse_lut_destroy": ([vp], ctypes.c_int),
     "ar_sparse_lut_export": ([vp, vp, vp, vp, vp], ctypes.c_int),
+    "ar_sparse_lut_screen": ([vp, vp], ctypes.c_int),
     "index_orientations_sparse": ([vp, vp, i64, vp, i32, vp, vp, vp], ctypes.c_int),
     "ar_fsp_amplitudes": ([vp, vp, vp, i64, i32, f32, vp, vp], ctypes.c_int),
     "ar_refine_roi_grid": ([vp, vp, vp, vp, i64, i32, i32, ctypes.c_uint32, f32, f32, i32, vp, vp, i64, P(i64), vp],
@@ -390,6 +391,13 @@ class SparseLUT:
         nodes = torch.empty((self.n_lib, self.n_hat), dtype=torch.int32, device=d)
         _call("ar_sparse_lut_export", self.handle, si.data_ptr(), sv.data_ptr(), nodes.data_ptr(), _stream(d))
         return si, sv, nodes
+
+    @property
+    def screen(self):
+        """ROIs per LDS read of the screen: 8 (8-bit codes), 2 or 1 (FP16)."""
+        out = ctypes.c_int32()
+        _call("ar_sparse_lut_screen", self.handle, ctypes.byref(out))
+        return out.value
 
     def close(self):
         if getattr(self, "handle", None) and self.handle.value:

@@ -6,7 +6,8 @@ with no orientations, odd phase boundaries).  Indexing: GPU top-1 equals the
 oracle's top-1 or is a tie within the indexing tolerance, and every returned
 FP32 score is within 1e-5 relative (+1e-6) of the FP64 score of the same
 (ROI, orientation); sizes span several orientation chunks, a ragged ROI
-group and all three ROI-per-workgroup layouts.  The bench configuration
+group and all three screens (8-bit codes with 8 ROIs per LDS read, FP16 with
+2 and with 1).  The bench configuration
 (2000 ROIs, 20000 orientations, 1000 strong entries, 10242 nodes, 4 windows)
 is checked on sampled ROIs and orientations."""
 import numpy as np
@@ -131,14 +132,15 @@ def _planted(dirs, counts, q, n_roi, seed):
 
 @pytest.fixture(scope="module")
 def chunks_world(nat, ctx, orc):
-    """10242 nodes (four ROIs per workgroup), 2 phases with 2500 + 1701
-    orientations (3 chunks of 2048, an odd phase start), 300 strong entries,
-    45 ROIs (a ragged last group of one)."""
+    """10242 nodes (the 8-bit screen, eight ROIs per workgroup), 2 phases
+    with 2500 + 1701 orientations (chunks of 2048, an odd phase start), 300
+    strong entries, 45 ROIs (a ragged last group of five)."""
     dirs = synth.icosphere(5)
     counts = [2500, 1701]
     ref = synth.bump_images(dirs, np.tile([1.0, 0, 0, 0], (2, 1)), [0, 1], 4)
     q = synth.library_orientations(sum(counts), 7)
     lut, si, sv, nodes = build(nat, ctx, ref, dirs, q, counts, 300)
+    assert lut.screen == 8
     osi, osv, olut = check_lut(orc, ref, dirs, q, counts, 300, si, sv, nodes)
     S, truth, qt = _planted(dirs, counts, q, 45, 41)
     return dict(lut=lut, osi=osi, osv=osv, olut=olut, S=S, ph=phases_of(counts), q=q, qt=qt)
@@ -155,10 +157,31 @@ def test_index_parity_several_chunks(nat, ctx, orc, chunks_world, k):
           flush=True)
 
 
+@pytest.mark.parametrize("n_hat", [150, 4 * 642])
+def test_index_parity_empty_window_and_all_entries(nat, ctx, orc, n_hat):
+    """642 nodes, 2 phases (700 + 650 orientations); phase 1's reference has
+    an all-zero window, which gets no strong entry at N^ = 150 (an empty
+    screen segment) and 642 zero-valued entries when all 4 x 642 entries are
+    kept (segments of 642 rows, padded to 644)."""
+    dirs = synth.icosphere(3)
+    counts = [700, 650]
+    ref = synth.bump_images(dirs, np.tile([1.0, 0, 0, 0], (2, 1)), [0, 1], 4)
+    ref[1, 2] = 0.0
+    q = synth.library_orientations(sum(counts), 9)
+    lut, si, sv, nodes = build(nat, ctx, ref, dirs, q, counts, n_hat)
+    assert lut.screen == 8
+    osi, osv, olut = check_lut(orc, ref, dirs, q, counts, n_hat, si, sv, nodes)
+    if n_hat == 150:
+        assert not np.any(osi[1] // len(dirs) == 2)
+    S, truth, qt = _planted(dirs, counts, q, 20, 47)
+    gidx, gsc = nat.index_orientations_sparse(ctx, dev(S), lut, 16)
+    check_index(orc, S, osi, osv, phases_of(counts), olut, gidx.cpu().numpy(), gsc.cpu().numpy(), 16)
+
+
 @pytest.mark.parametrize("mesh", ["random30000", "icosphere6"])
 def test_index_parity_wide_meshes(nat, ctx, orc, mesh):
-    """Meshes too large for four ROIs per workgroup: 30000 random unit
-    directions (two ROIs per workgroup) and the paper's 40962-node mesh (one
+    """Meshes too large for the 8-bit screen: 30000 random unit directions
+    (FP16, two ROIs per workgroup) and the paper's 40962-node mesh (FP16, one
     ROI per workgroup)."""
     if mesh == "icosphere6":
         dirs = synth.icosphere(6)
@@ -169,6 +192,7 @@ def test_index_parity_wide_meshes(nat, ctx, orc, mesh):
     ref = synth.bump_images(dirs, np.tile([1.0, 0, 0, 0], (2, 1)), [0, 1], 4)
     q = synth.library_orientations(sum(counts), 8)
     lut, si, sv, nodes = build(nat, ctx, ref, dirs, q, counts, 200)
+    assert lut.screen == (2 if mesh == "random30000" else 1)
     osi, osv, olut = check_lut(orc, ref, dirs, q, counts, 200, si, sv, nodes)
     S, truth, qt = _planted(dirs, counts, q, 9, 42)
     gidx, gsc = nat.index_orientations_sparse(ctx, dev(S), lut, 16)
