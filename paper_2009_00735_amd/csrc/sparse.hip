@@ -17,7 +17,8 @@
 //                       rows: value 0, node = the zero node n_dir).
 //   5. k_sparse_lut     for every orientation g of phase c and strong entry i:
 //                       the mesh node closest to R(q_g) n_{v_i}.
-//   6. k_lut_rows       the same table transposed to one row per orientation.
+//   6. k_lut_rows       the same table transposed to one row per orientation,
+//                       entries in window order (unpadded), for the rescore.
 //
 // Indexing (index_orientations_sparse): a screen keeps CAND candidates per
 // ROI, k_sparse_merge combines the orientation chunks and k_sparse_rescore
@@ -63,7 +64,10 @@ struct ar_sparse_lut {
     ar::DeviceBuffer q2sum;              // uint32 [n_phase]: sum of the squared 8-bit codes
     ar::DeviceBuffer seg;                // int32 [n_phase][n_win + 1], padded window segments of the screen rows
     ar::DeviceBuffer lut_ig;             // uint16 [n_rows][ld], screen rows of each column's phase
-    ar::DeviceBuffer lut_gi;             // uint16 [n_lib][n_hat], decreasing-value order
+    ar::DeviceBuffer kcmp;               // int32 [n_phase][n_hat], unpadded window-order position of entry i
+    ar::DeviceBuffer cseg;               // int32 [n_phase][n_win + 1], unpadded window segments
+    ar::DeviceBuffer sval_w;             // float [n_phase][n_hat], strong values in window order
+    ar::DeviceBuffer lut_gi;             // uint16 [n_lib][n_hat], window order (kcmp)
     ar::DeviceBuffer chunks;             // int4 [n_chunks]: phase, first column (multiple of 4), valid [lo, hi)
 };
 
@@ -144,8 +148,10 @@ __global__ __launch_bounds__(256) void k_window_count(const int32_t *__restrict_
 // the row's FP16 pair and 8-bit code; q2sum[c] accumulates the squared codes.
 __global__ __launch_bounds__(256) void k_window_order(const int32_t *__restrict__ strong_idx,
                                                       const float *__restrict__ strong_val, int n_hat, int n_win,
-                                                      int n_dir, const int32_t *__restrict__ seg, int n_rows,
-                                                      int32_t *__restrict__ kpos, uint32_t *__restrict__ kval2,
+                                                      int n_dir, const int32_t *__restrict__ seg,
+                                                      const int32_t *__restrict__ cseg, int n_rows,
+                                                      int32_t *__restrict__ kpos, int32_t *__restrict__ kcmp,
+                                                      float *__restrict__ sval_w, uint32_t *__restrict__ kval2,
                                                       uint8_t *__restrict__ kq8, uint32_t *__restrict__ q2sum)
 {
     const int c = blockIdx.y;
@@ -153,10 +159,14 @@ __global__ __launch_bounds__(256) void k_window_order(const int32_t *__restrict_
     const int i = blockIdx.x * 256 + threadIdx.x;
     if (i >= n_hat) return;
     const int wi = si[i] / n_dir;
-    int pos = seg[(size_t)c * (n_win + 1) + wi];
-    for (int j = 0; j < i; ++j) pos += (si[j] / n_dir == wi) ? 1 : 0;
+    int rank = 0;
+    for (int j = 0; j < i; ++j) rank += (si[j] / n_dir == wi) ? 1 : 0;
+    const int pos = seg[(size_t)c * (n_win + 1) + wi] + rank;
+    const int cpos = cseg[(size_t)c * (n_win + 1) + wi] + rank;
     kpos[(size_t)c * n_hat + i] = pos;
+    kcmp[(size_t)c * n_hat + i] = cpos;
     const float v = strong_val[(size_t)c * n_hat + i];
+    sval_w[(size_t)c * n_hat + cpos] = v;
     const _Float16 h = (_Float16)v;
     kval2[(size_t)c * n_rows + pos] = __builtin_bit_cast(uint32_t, half2_t{h, h});
     const uint32_t q = (uint32_t)rintf(255.0f * fminf(fmaxf(v, 0.0f), 1.0f));
@@ -203,7 +213,7 @@ __global__ __launch_bounds__(256) void k_sparse_lut(const double *__restrict__ q
 
 // one thread per (orientation, entry in decreasing-value order)
 __global__ __launch_bounds__(256) void k_lut_rows(const uint16_t *__restrict__ lut_ig, int64_t ld,
-                                                  const int32_t *__restrict__ kpos,
+                                                  const int32_t *__restrict__ kpos, const int32_t *__restrict__ kcmp,
                                                   const int64_t *__restrict__ phase_start, int n_phase,
                                                   int64_t n_lib, int n_hat, uint16_t *__restrict__ lut_gi)
 {
@@ -212,14 +222,21 @@ __global__ __launch_bounds__(256) void k_lut_rows(const uint16_t *__restrict__ l
     const int64_t g = t / n_hat;
     const int i = (int)(t - g * n_hat);
     const int c = phase_of(g, phase_start, n_phase);
-    lut_gi[t] = lut_ig[(size_t)kpos[(size_t)c * n_hat + i] * ld + g];
+    lut_gi[(size_t)g * n_hat + kcmp[(size_t)c * n_hat + i]] = lut_ig[(size_t)kpos[(size_t)c * n_hat + i] * ld + g];
 }
 
-__global__ __launch_bounds__(256) void k_lut_export(const uint16_t *__restrict__ lut_gi, int64_t n,
-                                                    int32_t *__restrict__ out)
+// out[g][i] in decreasing-value order from the window-ordered rows
+__global__ __launch_bounds__(256) void k_lut_export(const uint16_t *__restrict__ lut_gi,
+                                                    const int32_t *__restrict__ kcmp,
+                                                    const int64_t *__restrict__ phase_start, int n_phase,
+                                                    int64_t n_lib, int n_hat, int32_t *__restrict__ out)
 {
     const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (t < n) out[t] = lut_gi[t];
+    if (t >= n_lib * n_hat) return;
+    const int64_t g = t / n_hat;
+    const int i = (int)(t - g * n_hat);
+    const int c = phase_of(g, phase_start, n_phase);
+    out[t] = lut_gi[(size_t)g * n_hat + kcmp[(size_t)c * n_hat + i]];
 }
 
 // ------------------------------------------------------------ indexing
@@ -697,43 +714,78 @@ __global__ __launch_bounds__(256) void k_sparse_merge(const float *__restrict__ 
 }
 
 // One workgroup per ROI: exact FP32 Eq. S1 for each candidate, one wave per
-// candidate (lane l sums the entries l, l + 64, ... in decreasing-value
-// order, then a butterfly over the lanes), then the k best by (Delta, index).
-template <int CAND>
+// candidate, then the k best by (Delta, index).  The entries of a candidate's
+// row come in window order (cseg segments); lane l sums entries l, l + 64, ...
+// of each window, windows in order, then a butterfly over the lanes.  STAGE:
+// each window of the ROI, normalised in FP32, is first staged in LDS
+// (n_dir floats), so the per-entry gathers read LDS; otherwise they read the
+// image in global memory.  Either way d = x * (1 / max) - R_i as in the
+// screens' normalisation, the square accumulated with one FMA.
+template <int CAND, bool STAGE>
 __global__ __launch_bounds__(256) void k_sparse_rescore(
     const float *__restrict__ S, const float *__restrict__ inv_s, int n_win, int n_dir,
-    const int32_t *__restrict__ strong_idx, const float *__restrict__ strong_val, const uint16_t *__restrict__ lut_gi,
+    const int32_t *__restrict__ cseg, const float *__restrict__ sval_w, const uint16_t *__restrict__ lut_gi,
     int n_hat, const int64_t *__restrict__ phase_start, int n_phase, int64_t n_lib,
     const int32_t *__restrict__ cand_idx, int k, int32_t *__restrict__ top_idx, float *__restrict__ top_score)
 {
 #pragma clang fp contract(off)
+    extern __shared__ float stage[];
     __shared__ float ds[CAND];
     __shared__ int di[CAND];
+    constexpr int PER = CAND / 4;   // candidates per wave
     const int64_t r = blockIdx.x;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const float *srow = S + (size_t)r * n_win * n_dir;
     const float *is = inv_s + (size_t)r * n_win;
-    for (int c = wave; c < CAND; c += 4) {
-        const int l = cand_idx[(size_t)r * CAND + c];
-        const bool ok = l >= 0 && l < n_lib;
-        float acc = 0.0f;
-        if (ok) {
-            const int ph = phase_of(l, phase_start, n_phase);
-            const int32_t *si = strong_idx + (size_t)ph * n_hat;
-            const float *sv = strong_val + (size_t)ph * n_hat;
-            const uint16_t *row = lut_gi + (size_t)l * n_hat;
-#pragma unroll 4
-            for (int i = lane; i < n_hat; i += 64) {
-                const int w = si[i] / n_dir;
-                const float d = srow[(size_t)w * n_dir + row[i]] * is[w] - sv[i];
-                acc = fmaf(d, d, acc);
+    int cl[PER], cph[PER];
+    float acc[PER];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        const int l = cand_idx[(size_t)r * CAND + wave + 4 * q];
+        cl[q] = l;
+        cph[q] = (l >= 0 && l < n_lib) ? phase_of(l, phase_start, n_phase) : -1;
+        acc[q] = 0.0f;
+    }
+    for (int w = 0; w < n_win; ++w) {
+        const float iw = is[w];
+        const float *src = srow + (size_t)w * n_dir;
+        if (STAGE) {
+            __syncthreads();
+            // sixteen loads in flight per thread
+            for (int v0 = threadIdx.x; v0 < n_dir; v0 += 256 * 16) {
+                float x[16];
+#pragma unroll
+                for (int e = 0; e < 16; ++e) x[e] = v0 + 256 * e < n_dir ? src[v0 + 256 * e] : 0.0f;
+#pragma unroll
+                for (int e = 0; e < 16; ++e)
+                    if (v0 + 256 * e < n_dir) stage[v0 + 256 * e] = x[e] * iw;
             }
+            __syncthreads();
         }
 #pragma unroll
-        for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+        for (int q = 0; q < PER; ++q) {
+            if (cph[q] < 0) continue;
+            const int32_t *sg = cseg + (size_t)cph[q] * (n_win + 1);
+            const float *sv = sval_w + (size_t)cph[q] * n_hat;
+            const uint16_t *row = lut_gi + (size_t)cl[q] * n_hat;
+            const int j1 = sg[w + 1];
+#pragma unroll 4
+            for (int j = sg[w] + lane; j < j1; j += 64) {
+                const float x = STAGE ? stage[row[j]] : src[row[j]] * iw;
+                const float d = x - sv[j];
+                acc[q] = fmaf(d, d, acc[q]);
+            }
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        float a = acc[q];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) a += __shfl_xor(a, off);
         if (lane == 0) {
-            ds[c] = ok ? acc : INFINITY;
-            di[c] = ok ? l : 0x7fffffff;
+            const bool ok = cph[q] >= 0;
+            ds[wave + 4 * q] = ok ? a : INFINITY;
+            di[wave + 4 * q] = ok ? cl[q] : 0x7fffffff;
         }
     }
     __syncthreads();
@@ -772,6 +824,16 @@ int pick_screen(const ar_context *ctx, int n_dir, int n_rows)
     return 0;
 }
 
+template <typename K>
+ar_status allow_lds(K kernel, size_t lds, bool &done)
+{
+    if (!done && lds > 65536) {
+        AR_HIP(hipFuncSetAttribute((const void *)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+        done = true;
+    }
+    return AR_OK;
+}
+
 // Shared tail of both screens: merge the n_lists lists of each ROI, rescore
 // the candidates.
 template <int CAND>
@@ -781,10 +843,21 @@ ar_status merge_rescore(ar_context *ctx, const ar_sparse_lut *lut, const float *
     k_sparse_merge<CAND><<<(unsigned)((n_roi + 3) / 4), 256, 0, s>>>(
         ctx->sp_cand_s.as<float>(), ctx->sp_cand_i.as<int32_t>(), n_lists, n_roi, ctx->sp_merge.as<int32_t>());
     AR_HIP(hipGetLastError());
-    k_sparse_rescore<CAND><<<(unsigned)n_roi, 256, 0, s>>>(
-        images, ctx->sp_inv.as<float>(), lut->n_win, lut->n_dir, lut->strong_idx.as<int32_t>(),
-        lut->strong_val.as<float>(), lut->lut_gi.as<uint16_t>(), lut->n_hat, lut->phase_start.as<int64_t>(),
-        lut->n_phase, lut->n_lib, ctx->sp_merge.as<int32_t>(), k, top_idx, top_score);
+    // stage each ROI window in LDS when n_dir floats fit beside the static arrays
+    const size_t stage = sizeof(float) * (size_t)lut->n_dir;
+    if (stage + 4096 <= (size_t)ctx->lds_per_block) {
+        static bool attr_set = false;   // per instantiation
+        AR_TRY(allow_lds(k_sparse_rescore<CAND, true>, stage, attr_set));
+        k_sparse_rescore<CAND, true><<<(unsigned)n_roi, 256, stage, s>>>(
+            images, ctx->sp_inv.as<float>(), lut->n_win, lut->n_dir, lut->cseg.as<int32_t>(),
+            lut->sval_w.as<float>(), lut->lut_gi.as<uint16_t>(), lut->n_hat, lut->phase_start.as<int64_t>(),
+            lut->n_phase, lut->n_lib, ctx->sp_merge.as<int32_t>(), k, top_idx, top_score);
+    } else {
+        k_sparse_rescore<CAND, false><<<(unsigned)n_roi, 256, 0, s>>>(
+            images, ctx->sp_inv.as<float>(), lut->n_win, lut->n_dir, lut->cseg.as<int32_t>(),
+            lut->sval_w.as<float>(), lut->lut_gi.as<uint16_t>(), lut->n_hat, lut->phase_start.as<int64_t>(),
+            lut->n_phase, lut->n_lib, ctx->sp_merge.as<int32_t>(), k, top_idx, top_score);
+    }
     AR_HIP(hipGetLastError());
     return AR_OK;
 }
@@ -814,15 +887,6 @@ ar_status plan_screen(ar_context *ctx, const ar_sparse_lut *lut, int64_t n_roi, 
     return AR_OK;
 }
 
-template <typename K>
-ar_status allow_lds(K kernel, size_t lds, bool &done)
-{
-    if (!done && lds > 65536) {
-        AR_HIP(hipFuncSetAttribute((const void *)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-        done = true;
-    }
-    return AR_OK;
-}
 
 template <int RB, int CAND>
 ar_status run_screen(ar_context *ctx, const ar_sparse_lut *lut, const float *images, int64_t n_roi, int k,
@@ -934,6 +998,9 @@ ar_status ar_sparse_lut_create(ar_context *ctx, const float *reference, int32_t 
     step(lut->strong_idx.reserve(sizeof(int32_t) * nh));
     step(lut->strong_val.reserve(sizeof(float) * nh));
     step(lut->kpos.reserve(sizeof(int32_t) * nh));
+    step(lut->kcmp.reserve(sizeof(int32_t) * nh));
+    step(lut->sval_w.reserve(sizeof(float) * nh));
+    step(lut->cseg.reserve(sizeof(int32_t) * n_phase * (n_win + 1)));
     step(lut->seg.reserve(sizeof(int32_t) * n_phase * (n_win + 1)));
     step(lut->lut_gi.reserve(sizeof(uint16_t) * (size_t)n_lib * n_hat));
     step(lut->chunks.reserve(sizeof(int4) * ch.size()));
@@ -962,7 +1029,8 @@ ar_status ar_sparse_lut_create(ar_context *ctx, const float *reference, int32_t 
         launched("k_window_count");
     }
     // padded window segments: every window starts on a multiple of 4 rows
-    std::vector<int32_t> cnt((size_t)n_phase * n_win, 0), seg((size_t)n_phase * (n_win + 1), 0);
+    std::vector<int32_t> cnt((size_t)n_phase * n_win, 0), seg((size_t)n_phase * (n_win + 1), 0),
+        cseg((size_t)n_phase * (n_win + 1), 0);
     if (st == AR_OK) {
         hip(hipMemcpyAsync(cnt.data(), count.ptr, sizeof(int32_t) * cnt.size(), hipMemcpyDeviceToHost, s),
             "window counts");
@@ -970,8 +1038,11 @@ ar_status ar_sparse_lut_create(ar_context *ctx, const float *reference, int32_t 
     }
     int32_t n_rows = 4;
     for (int c = 0; c < n_phase; ++c) {
-        int32_t *sc = seg.data() + (size_t)c * (n_win + 1);
-        for (int w = 0; w < n_win; ++w) sc[w + 1] = sc[w] + (cnt[(size_t)c * n_win + w] + 3) / 4 * 4;
+        int32_t *sc = seg.data() + (size_t)c * (n_win + 1), *cc = cseg.data() + (size_t)c * (n_win + 1);
+        for (int w = 0; w < n_win; ++w) {
+            sc[w + 1] = sc[w] + (cnt[(size_t)c * n_win + w] + 3) / 4 * 4;
+            cc[w + 1] = cc[w] + cnt[(size_t)c * n_win + w];
+        }
         n_rows = std::max(n_rows, sc[n_win]);
     }
     lut->n_rows = n_rows;
@@ -982,6 +1053,8 @@ ar_status ar_sparse_lut_create(ar_context *ctx, const float *reference, int32_t 
     step(lut->lut_ig.reserve(sizeof(uint16_t) * (size_t)n_rows * lut->ld));
     if (st == AR_OK) {
         hip(hipMemcpyAsync(lut->seg.ptr, seg.data(), sizeof(int32_t) * seg.size(), hipMemcpyHostToDevice, s),
+            "look-up table upload");
+        hip(hipMemcpyAsync(lut->cseg.ptr, cseg.data(), sizeof(int32_t) * cseg.size(), hipMemcpyHostToDevice, s),
             "look-up table upload");
         hip(hipMemsetAsync(lut->kval2.ptr, 0, sizeof(uint32_t) * nr, s), "look-up table upload");
         hip(hipMemsetAsync(lut->kq8.ptr, 0, nr, s), "look-up table upload");
@@ -996,8 +1069,8 @@ ar_status ar_sparse_lut_create(ar_context *ctx, const float *reference, int32_t 
     if (st == AR_OK) {
         sparse::k_window_order<<<dim3((unsigned)((n_hat + 255) / 256), (unsigned)n_phase), 256, 0, s>>>(
             lut->strong_idx.as<int32_t>(), lut->strong_val.as<float>(), n_hat, n_win, n_dir, lut->seg.as<int32_t>(),
-            n_rows, lut->kpos.as<int32_t>(), lut->kval2.as<uint32_t>(), lut->kq8.as<uint8_t>(),
-            lut->q2sum.as<uint32_t>());
+            lut->cseg.as<int32_t>(), n_rows, lut->kpos.as<int32_t>(), lut->kcmp.as<int32_t>(),
+            lut->sval_w.as<float>(), lut->kval2.as<uint32_t>(), lut->kq8.as<uint8_t>(), lut->q2sum.as<uint32_t>());
         launched("k_window_order");
     }
     if (st == AR_OK) {
@@ -1009,8 +1082,8 @@ ar_status ar_sparse_lut_create(ar_context *ctx, const float *reference, int32_t 
     if (st == AR_OK) {
         const int64_t n = n_lib * n_hat;
         sparse::k_lut_rows<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(
-            lut->lut_ig.as<uint16_t>(), lut->ld, lut->kpos.as<int32_t>(), lut->phase_start.as<int64_t>(), n_phase,
-            n_lib, n_hat, lut->lut_gi.as<uint16_t>());
+            lut->lut_ig.as<uint16_t>(), lut->ld, lut->kpos.as<int32_t>(), lut->kcmp.as<int32_t>(),
+            lut->phase_start.as<int64_t>(), n_phase, n_lib, n_hat, lut->lut_gi.as<uint16_t>());
         launched("k_lut_rows");
     }
     // ref_max is freed on return: hipFree waits for the kernels that read it
@@ -1044,7 +1117,9 @@ ar_status ar_sparse_lut_export(const ar_sparse_lut *lut, int32_t *strong_idx, fl
         AR_HIP(hipMemcpyAsync(strong_val, lut->strong_val.ptr, sizeof(float) * nh, hipMemcpyDeviceToDevice, s));
     if (nodes) {
         const int64_t n = lut->n_lib * lut->n_hat;
-        sparse::k_lut_export<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(lut->lut_gi.as<uint16_t>(), n, nodes);
+        sparse::k_lut_export<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(
+            lut->lut_gi.as<uint16_t>(), lut->kcmp.as<int32_t>(), lut->phase_start.as<int64_t>(), lut->n_phase,
+            lut->n_lib, lut->n_hat, nodes);
         AR_HIP(hipGetLastError());
     }
     return AR_OK;
