@@ -20,6 +20,8 @@
 //   4. k_rescore          exact FP32 sum of squared differences of the
 //                         normalised FP32 images for the CAND candidates,
 //                         sorted by (Delta, index); the first k are returned.
+//                         One workgroup per ROI and one wave per candidate;
+//                         each normalised ROI window is staged in LDS once.
 #include <math.h>
 #include <string.h>
 
@@ -349,7 +351,7 @@ __global__ __launch_bounds__(256) void k_merge(const float *__restrict__ in_s, c
 // ------------------------------------------------------------ FP32 rescore
 // One workgroup per ROI row: Delta for each candidate from the FP32 images,
 // then the k best by (Delta, index).
-template <int CAND>
+template <int CAND, bool STAGE>
 __global__ __launch_bounds__(256) void k_rescore(const float *__restrict__ S, const float *__restrict__ inv_s,
                                                  const float *__restrict__ L, const float *__restrict__ inv_l,
                                                  const int32_t *__restrict__ cand_idx, int n_win, int n_dir,
@@ -357,40 +359,63 @@ __global__ __launch_bounds__(256) void k_rescore(const float *__restrict__ S, co
                                                  float *__restrict__ top_score)
 {
 #pragma clang fp contract(off)
-    __shared__ float red[256];
+    extern __shared__ float stage[];
     __shared__ float ds[CAND];
     __shared__ int di[CAND];
+    constexpr int PER = CAND / 4;   // candidates per wave
     const int64_t r = blockIdx.x;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const float *srow = S + (size_t)r * n_win * n_dir;
-    for (int c = 0; c < CAND; ++c) {
-        const int l = cand_idx[(size_t)r * CAND + c];
-        float acc = 0.0f;
-        if (l >= 0 && l < n_lib) {
-            const float *lrow = L + (size_t)l * n_win * n_dir;
-            for (int w = 0; w < n_win; ++w) {
-                const float is = inv_s[(size_t)r * n_win + w], il = inv_l[(size_t)l * n_win + w];
-                for (int v = threadIdx.x; v < n_dir; v += blockDim.x) {
-                    // both normalised values rounded alike (no contraction in this
-                    // kernel): identical images give Delta = 0 exactly
-                    const float d = srow[(size_t)w * n_dir + v] * is - lrow[(size_t)w * n_dir + v] * il;
-                    acc = fmaf(d, d, acc);
-                }
+    int cl[PER];
+    float acc[PER];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        const int l = cand_idx[(size_t)r * CAND + wave + 4 * q];
+        cl[q] = (l >= 0 && l < n_lib) ? l : -1;
+        acc[q] = 0.0f;
+    }
+    for (int w = 0; w < n_win; ++w) {
+        const float is = inv_s[(size_t)r * n_win + w];
+        const float *src = srow + (size_t)w * n_dir;
+        if (STAGE) {
+            __syncthreads();
+            // the ROI's normalised window, sixteen loads in flight per thread
+            for (int v0 = threadIdx.x; v0 < n_dir; v0 += 256 * 16) {
+                float x[16];
+#pragma unroll
+                for (int e = 0; e < 16; ++e) x[e] = v0 + 256 * e < n_dir ? src[v0 + 256 * e] : 0.0f;
+#pragma unroll
+                for (int e = 0; e < 16; ++e)
+                    if (v0 + 256 * e < n_dir) stage[v0 + 256 * e] = x[e] * is;
             }
-        } else {
-            acc = INFINITY;
-        }
-        red[threadIdx.x] = acc;
-        __syncthreads();
-        for (int s = 128; s > 0; s >>= 1) {
-            if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
             __syncthreads();
         }
-        if (threadIdx.x == 0) {
-            ds[c] = red[0];
-            di[c] = (l >= 0 && l < n_lib) ? l : 0x7fffffff;
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            if (cl[q] < 0) continue;
+            const float il = inv_l[(size_t)cl[q] * n_win + w];
+            const float *lrow = L + ((size_t)cl[q] * n_win + w) * n_dir;
+#pragma unroll 8
+            for (int v = lane; v < n_dir; v += 64) {
+                // both normalised values rounded alike (no contraction in this
+                // kernel): identical images give Delta = 0 exactly
+                const float a = STAGE ? stage[v] : src[v] * is;
+                const float d = a - lrow[v] * il;
+                acc[q] = fmaf(d, d, acc[q]);
+            }
         }
-        __syncthreads();
     }
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        float a = acc[q];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) a += __shfl_xor(a, off);
+        if (lane == 0) {
+            ds[wave + 4 * q] = cl[q] >= 0 ? a : INFINITY;
+            di[wave + 4 * q] = cl[q] >= 0 ? cl[q] : 0x7fffffff;
+        }
+    }
+    __syncthreads();
     if (threadIdx.x == 0) {
         // insertion sort of CAND entries by (Delta, index)
         for (int a = 1; a < CAND; ++a) {
@@ -410,6 +435,34 @@ __global__ __launch_bounds__(256) void k_rescore(const float *__restrict__ S, co
             top_score[(size_t)r * k + j] = ds[j];
         }
     }
+}
+
+// The ROI window is staged in LDS when n_dir floats fit beside the static
+// arrays; otherwise both rows are read from global memory.
+template <int CAND>
+ar_status launch_rescore(ar_context *ctx, const float *images, const ar_library *lib, int64_t n_roi, int k,
+                         int32_t *top_idx, float *top_score, hipStream_t s)
+{
+    const size_t stage = sizeof(float) * (size_t)lib->n_dir;
+    if (stage + 4096 <= (size_t)ctx->lds_per_block) {
+        static bool attr_set = false;   // per instantiation
+        if (!attr_set && stage > 65536) {
+            AR_HIP(hipFuncSetAttribute((const void *)k_rescore<CAND, true>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)stage));
+            attr_set = true;
+        }
+        k_rescore<CAND, true><<<(unsigned)n_roi, 256, stage, s>>>(images, ctx->i_inv.as<float>(), lib->ref,
+                                                                  lib->inv_max.as<float>(),
+                                                                  ctx->i_merge_idx.as<int32_t>(), lib->n_win,
+                                                                  lib->n_dir, lib->n_lib, k, top_idx, top_score);
+    } else {
+        k_rescore<CAND, false><<<(unsigned)n_roi, 256, 0, s>>>(images, ctx->i_inv.as<float>(), lib->ref,
+                                                               lib->inv_max.as<float>(),
+                                                               ctx->i_merge_idx.as<int32_t>(), lib->n_win,
+                                                               lib->n_dir, lib->n_lib, k, top_idx, top_score);
+    }
+    AR_HIP(hipGetLastError());
+    return AR_OK;
 }
 
 template <int CAND>
@@ -584,20 +637,14 @@ ar_status index_orientations_ex(ar_context *ctx, const float *images, int64_t n_
         idx::k_merge<16><<<(unsigned)((n_roi + 3) / 4), 256, 0, s>>>(
             ctx->i_cand_score.as<float>(), ctx->i_cand_idx.as<int32_t>(), n_lists, n_roi, ctx->i_merge_idx.as<int32_t>());
         AR_HIP(hipGetLastError());
-        idx::k_rescore<16><<<(unsigned)n_roi, 256, 0, s>>>(images, ctx->i_inv.as<float>(), lib->ref,
-                                                          lib->inv_max.as<float>(), ctx->i_merge_idx.as<int32_t>(),
-                                                          lib->n_win, lib->n_dir, lib->n_lib, k, top_idx, top_score);
-        AR_HIP(hipGetLastError());
+        AR_TRY(idx::launch_rescore<16>(ctx, images, lib, n_roi, k, top_idx, top_score, s));
     } else {
         AR_TRY(idx::launch_corr<32>(ctx, cfg, ctx->i_bf16.as<uint16_t>(), lib, m_blocks, n_tiles, tiles_per_seg,
                                     n_seg, ctx->i_cand_score.as<float>(), ctx->i_cand_idx.as<int32_t>(), s));
         idx::k_merge<32><<<(unsigned)((n_roi + 3) / 4), 256, 0, s>>>(
             ctx->i_cand_score.as<float>(), ctx->i_cand_idx.as<int32_t>(), n_lists, n_roi, ctx->i_merge_idx.as<int32_t>());
         AR_HIP(hipGetLastError());
-        idx::k_rescore<32><<<(unsigned)n_roi, 256, 0, s>>>(images, ctx->i_inv.as<float>(), lib->ref,
-                                                          lib->inv_max.as<float>(), ctx->i_merge_idx.as<int32_t>(),
-                                                          lib->n_win, lib->n_dir, lib->n_lib, k, top_idx, top_score);
-        AR_HIP(hipGetLastError());
+        AR_TRY(idx::launch_rescore<32>(ctx, images, lib, n_roi, k, top_idx, top_score, s));
     }
     if (cand_idx) {
         const int64_t n = n_roi * cand;
