@@ -52,7 +52,9 @@ const char *ar_last_error(void);
 const char *ar_version(void);
 
 /* Create a context on HIP device `device`: it owns reusable device
- * workspace and the tables the kernels read.  Destroy frees them. */
+ * workspace and the tables the kernels read.  Destroy frees them.  Calls
+ * that share a context share its workspace: issue them on one stream, or
+ * synchronise before switching streams. */
 ar_status ar_context_create(int device, ar_context **out);
 ar_status ar_context_destroy(ar_context *ctx);
 

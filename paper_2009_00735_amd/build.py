@@ -22,7 +22,7 @@ LIB = os.path.join(PKG, "libaraullo.so")
 ARCH = os.environ.get("ARAULLO_OFFLOAD_ARCH", "gfx950")
 
 SOURCES = ["context.hip", "gather.hip", "signatures.hip", "indexing.hip", "orientation.hip", "refine.hip",
-           "peaks.hip", "sparse.hip", "fsp.hip", "roigrid.hip"]
+           "peaks.hip", "sparse.hip", "fsp.hip", "roigrid.hip", "mesh.hip"]
 
 COMMON = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",

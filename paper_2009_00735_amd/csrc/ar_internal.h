@@ -87,6 +87,8 @@ struct ar_context {
     ar::DeviceBuffer sp_half, sp_inv, sp_cand_s, sp_cand_i, sp_merge;
     // refinement workspace
     ar::DeviceBuffer r_partials, r_state, r_dirs;
+    // nearest-node candidate lists of the last mesh (count [6 G^2], lists [6 G^2][cap])
+    ar::DeviceBuffer m_cells;
     // twiddle tables exp(-2 pi i j / nbins), j < nbins, per nbins
     std::map<int, std::unique_ptr<ar::DeviceBuffer>> twiddles;
     ar_status twiddle_table(int nbins, const float2 **out);
@@ -110,4 +112,7 @@ namespace ar {
 ar_status gather_csr(ar_context *ctx, const float *positions, const int32_t *types, int64_t n_atoms,
                      const float *centres, int64_t n_roi, float radius, uint64_t type_mask, int64_t *offsets,
                      float *rel, int64_t cap, int64_t *total, hipStream_t stream);
+struct MeshCells;
+// cube-map nearest-node candidate lists of `dirs` in ctx->m_cells (mesh.hip)
+ar_status build_mesh_cells(ar_context *ctx, const float *dirs, int n_dir, hipStream_t stream, MeshCells &mc);
 }

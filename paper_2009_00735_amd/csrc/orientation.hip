@@ -57,13 +57,13 @@ __global__ __launch_bounds__(256) void k_disorientation(const double *__restrict
 }
 
 // One thread per (entry, node): rotate n_v by R(q)^T and take the reference
-// value at the closest node (nearest_node: FP32 scan, FP64 re-rank, ties to
-// the lower index).
+// value at the closest node (nearest_node over the cell's candidate list:
+// FP32 scan, FP64 re-rank, ties to the lower index).
 __global__ __launch_bounds__(256) void k_rotate_reference(const float *__restrict__ ref, int n_win,
                                                           const float *__restrict__ dirs, int n_dir,
                                                           const double *__restrict__ quats,
                                                           const int32_t *__restrict__ phase, int64_t n_lib,
-                                                          float *__restrict__ out)
+                                                          MeshCells mc, float *__restrict__ out)
 {
     const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t l = gid / n_dir;
@@ -75,7 +75,7 @@ __global__ __launch_bounds__(256) void k_rotate_reference(const float *__restric
     const double rx = M[0] * nx + M[3] * ny + M[6] * nz;
     const double ry = M[1] * nx + M[4] * ny + M[7] * nz;
     const double rz = M[2] * nx + M[5] * ny + M[8] * nz;
-    const int arg = nearest_node(rx, ry, rz, dirs, n_dir);
+    const int arg = nearest_node(rx, ry, rz, dirs, n_dir, mc);
     if (!valid) return;
     const int p = phase[l];
     for (int w = 0; w < n_win; ++w)
@@ -108,8 +108,10 @@ ar_status ar_rotate_reference(ar_context *ctx, const float *reference, int32_t n
     AR_HIP(hipSetDevice(ctx->device));
     const int64_t n = n_lib * n_dir;
     AR_CHECK((n + 255) / 256 < (int64_t)INT32_MAX, "too many items");
+    ar::MeshCells mc;
+    AR_TRY(ar::build_mesh_cells(ctx, directions, n_dir, (hipStream_t)stream, mc));
     ar::k_rotate_reference<<<(unsigned)((n + 255) / 256), 256, 0, (hipStream_t)stream>>>(
-        reference, n_win, directions, n_dir, quats, phase, n_lib, out);
+        reference, n_win, directions, n_dir, quats, phase, n_lib, mc, out);
     AR_HIP(hipGetLastError());
     return AR_OK;
 }

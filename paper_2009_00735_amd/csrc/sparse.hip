@@ -5,10 +5,10 @@
 //
 // Look-up table (ar_sparse_lut_create), per phase c:
 //   1. k_ref_max        per window, the maximum of the raw reference image.
-//   2. k_strong_rank    every entry's key x / max in FP64; its rank among all
-//                       entries (larger key first, equal keys by lower flat
-//                       index w * n_dir + v) by counting; ranks < n_hat are
-//                       the strong entries in decreasing order.
+//   2. k_strong_keys    every entry's key x / max in FP64 (+0 for -0); a
+//                       stable radix sort per phase (hipCUB, descending key,
+//                       so equal keys keep the lower flat index w * n_dir + v
+//                       first); k_strong_take keeps the first n_hat.
 //   3. k_window_count   strong entries per window; the host pads every
 //                       window's segment to a multiple of 4 rows.
 //   4. k_window_order   the strong entries regrouped by window (stable) into
@@ -38,6 +38,8 @@
 // Either way the workgroup keeps the CAND best orientations per ROI
 // (per-wave selection, then a merge in LDS).
 #include <math.h>
+
+#include <hipcub/hipcub.hpp>
 
 #include <algorithm>
 #include <new>
@@ -101,37 +103,32 @@ __global__ __launch_bounds__(256) void k_ref_max(const float *__restrict__ ref, 
     if (threadIdx.x == 0) out[blockIdx.x] = red[0];
 }
 
-// grid (ceil(K / 256), n_phase)
-__global__ __launch_bounds__(256) void k_strong_rank(const float *__restrict__ ref, const float *__restrict__ ref_max,
-                                                     int n_win, int n_dir, int n_hat, int32_t *__restrict__ strong_idx,
-                                                     float *__restrict__ strong_val)
+// grid (ceil(K / 256), n_phase): key[c][e] = x / max of window e / n_dir in
+// FP64 (0 for an all-zero window), -0 made +0 so that equal keys compare
+// equal in the radix order; val[c][e] = e.
+__global__ __launch_bounds__(256) void k_strong_keys(const float *__restrict__ ref, const float *__restrict__ ref_max,
+                                                     int n_win, int n_dir, double *__restrict__ key,
+                                                     int32_t *__restrict__ val)
 {
-    __shared__ double tile[256];
     const int c = blockIdx.y;
     const int64_t K = (int64_t)n_win * n_dir;
     const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    const float *img = ref + (size_t)c * K;
-    const float *mx = ref_max + (size_t)c * n_win;
-    auto key = [&](int64_t j) -> double {
-        const float m = mx[j / n_dir];
-        return m > 0.0f ? (double)img[j] / (double)m : 0.0;
-    };
-    const double mine = e < K ? key(e) : 0.0;
-    int64_t rank = 0;
-    for (int64_t t0 = 0; t0 < K; t0 += 256) {
-        __syncthreads();
-        if (t0 + threadIdx.x < K) tile[threadIdx.x] = key(t0 + threadIdx.x);
-        __syncthreads();
-        const int n = (int)min((int64_t)256, K - t0);
-        for (int j = 0; j < n; ++j) {
-            const double o = tile[j];
-            rank += (o > mine || (o == mine && t0 + j < e)) ? 1 : 0;
-        }
-    }
-    if (e < K && rank < n_hat) {
-        strong_idx[(size_t)c * n_hat + rank] = (int32_t)e;
-        strong_val[(size_t)c * n_hat + rank] = (float)mine;
-    }
+    if (e >= K) return;
+    const float m = ref_max[(size_t)c * n_win + e / n_dir];
+    key[(size_t)c * K + e] = (m > 0.0f ? (double)ref[(size_t)c * K + e] / (double)m : 0.0) + 0.0;
+    val[(size_t)c * K + e] = (int32_t)e;
+}
+
+// grid (ceil(n_hat / 256), n_phase): the first n_hat of each phase's sorted run
+__global__ __launch_bounds__(256) void k_strong_take(const double *__restrict__ key, const int32_t *__restrict__ val,
+                                                     int64_t K, int n_hat, int32_t *__restrict__ strong_idx,
+                                                     float *__restrict__ strong_val)
+{
+    const int c = blockIdx.y;
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= n_hat) return;
+    strong_idx[(size_t)c * n_hat + i] = val[(size_t)c * K + i];
+    strong_val[(size_t)c * n_hat + i] = (float)key[(size_t)c * K + i];
 }
 
 // grid (ceil(n_hat / 256), n_phase): strong entries per window (count is zeroed)
@@ -192,7 +189,7 @@ __global__ __launch_bounds__(256) void k_sparse_lut(const double *__restrict__ q
                                                     const int64_t *__restrict__ phase_start, int n_phase,
                                                     int64_t n_lib, const int32_t *__restrict__ strong_idx,
                                                     const int32_t *__restrict__ kpos, int n_hat,
-                                                    const float *__restrict__ dirs, int n_dir,
+                                                    const float *__restrict__ dirs, int n_dir, MeshCells mc,
                                                     uint16_t *__restrict__ lut_ig, int64_t ld)
 {
     const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -207,7 +204,7 @@ __global__ __launch_bounds__(256) void k_sparse_lut(const double *__restrict__ q
     const double rx = M[0] * nx + M[1] * ny + M[2] * nz;
     const double ry = M[3] * nx + M[4] * ny + M[5] * nz;
     const double rz = M[6] * nx + M[7] * ny + M[8] * nz;
-    const int p = nearest_node(rx, ry, rz, dirs, n_dir);
+    const int p = nearest_node(rx, ry, rz, dirs, n_dir, mc);
     if (valid) lut_ig[(size_t)kpos[(size_t)c * n_hat + i] * ld + g] = (uint16_t)p;
 }
 
@@ -949,6 +946,7 @@ ar_status ar_sparse_lut_create(ar_context *ctx, const float *reference, int32_t 
     AR_CHECK(n_phase >= 1 && n_win >= 1, "n_phase and n_win must be >= 1");
     AR_CHECK(n_dir >= 1 && n_dir <= 65535, "n_dir must be in [1, 65535] (16-bit node ids), got %d", n_dir);
     const int64_t K = (int64_t)n_win * n_dir;
+    AR_CHECK(K < (int64_t)INT32_MAX, "n_win * n_dir must be below 2^31");
     AR_CHECK(n_hat >= 1 && n_hat <= K && n_hat <= 65535, "n_hat must be in [1, min(n_win * n_dir, 65535)], got %d",
              n_hat);
     std::vector<int64_t> start(n_phase + 1, 0);
@@ -1017,11 +1015,37 @@ ar_status ar_sparse_lut_create(ar_context *ctx, const float *reference, int32_t 
         sparse::k_ref_max<<<(unsigned)(n_phase * n_win), 256, 0, s>>>(reference, n_dir, ref_max.as<float>());
         launched("k_ref_max");
     }
+    // strong lists: keys, one stable descending radix sort per phase, the first n_hat
+    ar::DeviceBuffer keys, keys_out, vals, vals_out, sort_temp;
+    size_t sort_bytes = 0;
+    if (st == AR_OK)
+        hip(hipcub::DeviceRadixSort::SortPairsDescending(nullptr, sort_bytes, (const double *)nullptr,
+                                                         (double *)nullptr, (const int32_t *)nullptr,
+                                                         (int32_t *)nullptr, (int)K, 0, 64, s),
+            "strong-entry sort");
+    step(keys.reserve(sizeof(double) * (size_t)n_phase * K));
+    step(keys_out.reserve(sizeof(double) * (size_t)n_phase * K));
+    step(vals.reserve(sizeof(int32_t) * (size_t)n_phase * K));
+    step(vals_out.reserve(sizeof(int32_t) * (size_t)n_phase * K));
+    step(sort_temp.reserve(std::max<size_t>(sort_bytes, 256)));   // non-null: a null pointer is a size query
     if (st == AR_OK) {
-        sparse::k_strong_rank<<<dim3((unsigned)((K + 255) / 256), (unsigned)n_phase), 256, 0, s>>>(
-            reference, ref_max.as<float>(), n_win, n_dir, n_hat, lut->strong_idx.as<int32_t>(),
+        sparse::k_strong_keys<<<dim3((unsigned)((K + 255) / 256), (unsigned)n_phase), 256, 0, s>>>(
+            reference, ref_max.as<float>(), n_win, n_dir, keys.as<double>(), vals.as<int32_t>());
+        launched("k_strong_keys");
+    }
+    for (int c = 0; c < n_phase && st == AR_OK; ++c) {
+        size_t tb = sort_bytes;
+        hip(hipcub::DeviceRadixSort::SortPairsDescending(sort_temp.ptr, tb, keys.as<double>() + (size_t)c * K,
+                                                         keys_out.as<double>() + (size_t)c * K,
+                                                         vals.as<int32_t>() + (size_t)c * K,
+                                                         vals_out.as<int32_t>() + (size_t)c * K, (int)K, 0, 64, s),
+            "strong-entry sort");
+    }
+    if (st == AR_OK) {
+        sparse::k_strong_take<<<dim3((unsigned)((n_hat + 255) / 256), (unsigned)n_phase), 256, 0, s>>>(
+            keys_out.as<double>(), vals_out.as<int32_t>(), K, n_hat, lut->strong_idx.as<int32_t>(),
             lut->strong_val.as<float>());
-        launched("k_strong_rank");
+        launched("k_strong_take");
     }
     if (st == AR_OK) {
         sparse::k_window_count<<<dim3((unsigned)((n_hat + 255) / 256), (unsigned)n_phase), 256, 0, s>>>(
@@ -1073,10 +1097,12 @@ ar_status ar_sparse_lut_create(ar_context *ctx, const float *reference, int32_t 
             lut->sval_w.as<float>(), lut->kval2.as<uint32_t>(), lut->kq8.as<uint8_t>(), lut->q2sum.as<uint32_t>());
         launched("k_window_order");
     }
+    MeshCells mc;
+    if (st == AR_OK) step(build_mesh_cells(ctx, directions, n_dir, s, mc));
     if (st == AR_OK) {
         sparse::k_sparse_lut<<<dim3((unsigned)((n_lib + 255) / 256), (unsigned)n_hat), 256, 0, s>>>(
             quats, lut->phase_start.as<int64_t>(), n_phase, n_lib, lut->strong_idx.as<int32_t>(),
-            lut->kpos.as<int32_t>(), n_hat, directions, n_dir, lut->lut_ig.as<uint16_t>(), lut->ld);
+            lut->kpos.as<int32_t>(), n_hat, directions, n_dir, mc, lut->lut_ig.as<uint16_t>(), lut->ld);
         launched("k_sparse_lut");
     }
     if (st == AR_OK) {

@@ -131,6 +131,37 @@ def test_rotate_reference_matches_oracle(nat, ctx, orc):
     assert np.array_equal(got, expect)
 
 
+def _mesh(kind):
+    gen = np.random.default_rng(12)
+    if kind == "icosphere0":                      # 12 nodes: one cube-map cell per face, every node listed
+        return synth.icosphere(0)
+    if kind == "clustered":                       # 2000 nodes in a 3 deg cap + 100 elsewhere: lists past the
+        c = gen.standard_normal((2000, 3)) * np.radians(1.5)   # cap of 256 fall back to the full scan
+        c[:, 2] = 1.0
+        o = gen.standard_normal((100, 3))
+        d = np.concatenate([c, o])
+        return (d / np.linalg.norm(d, axis=1, keepdims=True)).astype(np.float32)
+    d = synth.icosphere(3)                        # duplicated nodes: exact ties go to the lower index
+    return np.concatenate([d, d[::7]]).astype(np.float32)
+
+
+@pytest.mark.parametrize("kind", ["icosphere0", "clustered", "duplicates"])
+def test_rotate_reference_nearest_node_edge_meshes(nat, ctx, orc, kind):
+    """The reference value of node u is u itself, so the output is the chosen
+    node: it must equal the oracle's exhaustive FP32-scan / FP64-re-rank
+    choice on meshes that stress the cube-map candidate lists."""
+    dirs = _mesh(kind)
+    n = len(dirs)
+    ref = np.tile(np.arange(n, dtype=np.float32), (1, 1, 1))
+    q = synth.library_orientations(200, 13)
+    q[0] = [1.0, 0.0, 0.0, 0.0]                   # identity and 180 deg about z: rotated nodes land on nodes
+    q[1] = [0.0, 0.0, 0.0, 1.0]
+    ph = np.zeros(200, np.int32)
+    got = nat.ar_rotate_reference(ctx, dev(ref), dev(dirs), dev(q, torch.float64), dev(ph, torch.int32)).cpu().numpy()
+    lut = orc.rotated_nodes(q, dirs)
+    assert np.array_equal(got[:, 0, :].astype(np.int64), lut.astype(np.int64))
+
+
 def test_disorientation_matches_oracle(nat, orc):
     gen = np.random.default_rng(5)
     qa = synth.shoemake(5000, gen)
