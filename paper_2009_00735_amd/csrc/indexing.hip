@@ -480,6 +480,12 @@ struct CorrCfg {
     int bm() const { return 32 * wtm * 2; }
     int bn() const { return 32 * wtn * wgn(); }
     int threads() const { return 64 * waves; }
+    // dynamic LDS of the tile (CorrShape::lds)
+    size_t lds() const
+    {
+        const size_t ab = (size_t)kStages * (bm() + bn()) * kBK * 2, c = (size_t)bm() * 65 * sizeof(float);
+        return ab > c ? ab : c;
+    }
 };
 
 template <int WGM, int WGN, int WTM, int WTN, int CAND>
@@ -616,11 +622,34 @@ ar_status index_orientations_ex(ar_context *ctx, const float *images, int64_t n_
     const int64_t m_pad = idx::round_up(n_roi, idx::kPadM);
     const int m_blocks = (int)(m_pad / cfg.bm());
     const int n_tiles = (int)(lib->n_pad / cfg.bn());
-    // segments: enough workgroups to fill the chip several times over
-    const int target = (cfg.waves == 8 ? 4 : 8) * ctx->cu_count;
-    int n_seg = std::max(1, std::min(n_tiles, (target + m_blocks - 1) / m_blocks));
-    const int tiles_per_seg = (n_tiles + n_seg - 1) / n_seg;
-    n_seg = (n_tiles + tiles_per_seg - 1) / tiles_per_seg;
+    // segments: a workgroup walks tiles_per_seg column tiles of one row block.
+    // The makespan is rounds of resident workgroups times tiles per
+    // workgroup (workgroups per CU from LDS and the 8 waves a CU holds at
+    // this register budget); the fewest segments within 5 % of the best
+    // makespan keep the candidate lists short.
+    int tiles_per_seg = n_tiles, n_seg = 1;
+    {
+        const int per_cu = std::max(1, std::min((int)(ctx->lds_per_block / cfg.lds()), 8 / cfg.waves));
+        const int64_t slots = (int64_t)per_cu * ctx->cu_count;
+        auto makespan = [&](int ns, int &tps, int &nsr) {
+            tps = (n_tiles + ns - 1) / ns;
+            nsr = (n_tiles + tps - 1) / tps;
+            return ((int64_t)m_blocks * nsr + slots - 1) / slots * tps;
+        };
+        int64_t best = INT64_MAX;
+        for (int ns = 1; ns <= n_tiles; ++ns) {
+            int tps, nsr;
+            best = std::min(best, makespan(ns, tps, nsr));
+        }
+        for (int ns = 1; ns <= n_tiles; ++ns) {
+            int tps, nsr;
+            if (makespan(ns, tps, nsr) * 100 <= best * 105) {
+                tiles_per_seg = tps;
+                n_seg = nsr;
+                break;
+            }
+        }
+    }
     const int n_lists = n_seg * (cfg.threads() / cfg.bm());
 
     AR_TRY(ctx->i_bf16.reserve(sizeof(uint16_t) * (size_t)m_pad * lib->Kp));
