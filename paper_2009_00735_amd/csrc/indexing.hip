@@ -119,8 +119,10 @@ __global__ __launch_bounds__(256) void k_row_norm2(const uint16_t *__restrict__ 
 // bank conflicts.  One workgroup barrier per step: after it every wave's
 // loads of the step have landed and every wave has finished the previous
 // step, whose stage is then refilled.
-// grid.x = m_blocks * n_seg.  out_s/out_i: [M_pad][n_seg * TPR][CAND] where
-// TPR = THREADS / BM threads share a row in the epilogue.
+// grid.x = m_blocks * n_seg; the launch covers library rows from col0.
+// out_s/out_i: [M_pad][list_stride][CAND]; this launch writes lists
+// list_base .. list_base + n_seg * TPR - 1 of each row, where TPR =
+// THREADS / BM threads share a row in the epilogue.
 constexpr int kBK = 32;        // bf16 per K step
 constexpr int kStages = 4;     // LDS ring depth
 
@@ -204,8 +206,9 @@ __device__ __forceinline__ void fill_stage(unsigned char *smem, const uint16_t *
 template <int WGM, int WGN, int WTM, int WTN, int CAND>
 __global__ __launch_bounds__(64 * WGM * WGN) void k_corr_topk(const uint16_t *__restrict__ A, const uint16_t *__restrict__ B,
                                                         const float *__restrict__ norm2, int64_t Kp, int m_blocks,
-                                                        int n_tiles, int tiles_per_seg, int n_seg,
-                                                        float *__restrict__ out_s, int32_t *__restrict__ out_i)
+                                                        int n_tiles, int tiles_per_seg, int n_seg, int64_t col0,
+                                                        int list_stride, int list_base, float *__restrict__ out_s,
+                                                        int32_t *__restrict__ out_i)
 {
     using S = CorrShape<WGM, WGN, WTM, WTN>;
     constexpr int BM = S::BM, BN = S::BN, TPR = S::TPR, NB = S::BLK_PER_WAVE;
@@ -252,7 +255,7 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_corr_topk(const uint16_t *__
 
     const int KT = (int)(Kp / kBK);
     for (int nt = t0; nt < t1; ++nt) {
-        const int64_t n0 = (int64_t)nt * BN;
+        const int64_t n0 = col0 + (int64_t)nt * BN;
         f32x16 acc[WTM][WTN];
 #pragma unroll
         for (int a = 0; a < WTM; ++a)
@@ -319,7 +322,7 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_corr_topk(const uint16_t *__
             __syncthreads();
         }
     }
-    const size_t o = (((size_t)(m0 + e_row)) * (n_seg * TPR) + seg * TPR + e_part) * CAND;
+    const size_t o = (((size_t)(m0 + e_row)) * list_stride + list_base + seg * TPR + e_part) * CAND;
 #pragma unroll
     for (int j = 0; j < CAND; ++j) {
         out_s[o + j] = top.s[j];
@@ -488,10 +491,18 @@ struct CorrCfg {
     }
 };
 
+// One correlation launch over the library rows [col0, col0 + n_tiles * BN).
+struct CorrLaunch {
+    int m_blocks, n_tiles, tiles_per_seg, n_seg;
+    int64_t col0;
+    int list_stride, list_base;
+};
+
 template <int WGM, int WGN, int WTM, int WTN, int CAND>
-ar_status launch_corr_t(ar_context *ctx, const uint16_t *A, const ar_library *lib, int m_blocks, int n_tiles,
-                        int tiles_per_seg, int n_seg, float *out_s, int32_t *out_i, hipStream_t s)
+ar_status launch_corr_t(ar_context *ctx, const uint16_t *A, const ar_library *lib, const CorrLaunch &L,
+                        float *out_s, int32_t *out_i, hipStream_t s)
 {
+    const int m_blocks = L.m_blocks, n_tiles = L.n_tiles, tiles_per_seg = L.tiles_per_seg, n_seg = L.n_seg;
     using S = CorrShape<WGM, WGN, WTM, WTN>;
     const unsigned blocks = (unsigned)(m_blocks * n_seg);
     const size_t lds = S::lds();
@@ -503,8 +514,8 @@ ar_status launch_corr_t(ar_context *ctx, const uint16_t *A, const ar_library *li
         attr_set = true;
     }
     k_corr_topk<WGM, WGN, WTM, WTN, CAND><<<blocks, S::THREADS, lds, s>>>(
-        A, lib->bf16.as<uint16_t>(), lib->norm2.as<float>(), lib->Kp, m_blocks, n_tiles, tiles_per_seg, n_seg, out_s,
-        out_i);
+        A, lib->bf16.as<uint16_t>(), lib->norm2.as<float>(), lib->Kp, m_blocks, n_tiles, tiles_per_seg, n_seg, L.col0,
+        L.list_stride, L.list_base, out_s, out_i);
     AR_HIP(hipGetLastError());
     return AR_OK;
 }
@@ -521,13 +532,12 @@ bool corr_tile_supported(int waves, int wtm, int wtn, int bk)
 }
 
 template <int CAND>
-ar_status launch_corr(ar_context *ctx, const CorrCfg &c, const uint16_t *A, const ar_library *lib, int m_blocks,
-                      int n_tiles, int tiles_per_seg, int n_seg, float *out_s, int32_t *out_i, hipStream_t s)
+ar_status launch_corr(ar_context *ctx, const CorrCfg &c, const uint16_t *A, const ar_library *lib,
+                      const CorrLaunch &L, float *out_s, int32_t *out_i, hipStream_t s)
 {
 #define AR_CORR_CASE(w_, m_, n_)                                                                   \
     if (c.waves == w_ && c.wtm == m_ && c.wtn == n_)                                               \
-        return launch_corr_t<2, (w_) / 2, m_, n_, CAND>(ctx, A, lib, m_blocks, n_tiles, tiles_per_seg, n_seg, out_s, \
-                                                        out_i, s);
+        return launch_corr_t<2, (w_) / 2, m_, n_, CAND>(ctx, A, lib, L, out_s, out_i, s);
     AR_CORR_TILES(AR_CORR_CASE)
 #undef AR_CORR_CASE
     return fail(AR_EINVAL, "unsupported correlation tile %d waves %dx%dx%d", c.waves, c.wtm, c.wtn, c.bk);
@@ -628,9 +638,12 @@ ar_status index_orientations_ex(ar_context *ctx, const float *images, int64_t n_
     // this register budget); the fewest segments within 5 % of the best
     // makespan keep the candidate lists short.
     int tiles_per_seg = n_tiles, n_seg = 1;
+    auto per_cu_of = [&](const idx::CorrCfg &c) {
+        return std::max(1, std::min((int)(ctx->lds_per_block / c.lds()), 8 / c.waves));
+    };
+    const int per_cu = per_cu_of(cfg);
+    const int64_t slots = (int64_t)per_cu * ctx->cu_count;
     {
-        const int per_cu = std::max(1, std::min((int)(ctx->lds_per_block / cfg.lds()), 8 / cfg.waves));
-        const int64_t slots = (int64_t)per_cu * ctx->cu_count;
         auto makespan = [&](int ns, int &tps, int &nsr) {
             tps = (n_tiles + ns - 1) / ns;
             nsr = (n_tiles + tps - 1) / tps;
@@ -650,7 +663,36 @@ ar_status index_orientations_ex(ar_context *ctx, const float *images, int64_t n_
             }
         }
     }
-    const int n_lists = n_seg * (cfg.threads() / cfg.bm());
+    // One-tile segments whose last round is partial (small calls): the whole
+    // rounds run the main tile and the remaining columns a tile of the same
+    // height and half the width (4 waves), all in one more round.  Every
+    // score accumulates K in the same order in either tile, so the candidate
+    // lists are the same as from the main tile alone.
+    // Taken when its makespan, the whole rounds plus 0.75 of a main tile (the
+    // half-width tile runs at 4 waves per CU; measured ~0.7), beats the
+    // segmented one.
+    idx::CorrLaunch main_l{m_blocks, n_tiles, tiles_per_seg, n_seg, 0, 0, 0}, tail_l{};
+    const idx::CorrCfg tail_cfg{4, cfg.wtm, cfg.wtn, cfg.bk};
+    bool split = false;
+    {
+        const int64_t wgs = (int64_t)m_blocks * n_tiles;   // one tile per workgroup
+        const int64_t seg_cost = ((int64_t)m_blocks * n_seg + slots - 1) / slots * tiles_per_seg;
+        if (per_cu == 1 && cfg.waves == 8 && tail_cfg.bm() == cfg.bm() && 2 * tail_cfg.bn() == cfg.bn() &&
+            idx::corr_tile_supported(4, cfg.wtm, cfg.wtn, cfg.bk) && wgs > slots && wgs % slots != 0 &&
+            (wgs / slots) * 4 + 3 < seg_cost * 4) {
+            const int main_cols = (int)((wgs / slots) * slots / m_blocks);
+            const int tail_tiles = 2 * (n_tiles - main_cols);
+            if (main_cols >= 1 && (int64_t)m_blocks * tail_tiles <= (int64_t)per_cu_of(tail_cfg) * ctx->cu_count) {
+                split = true;
+                main_l = idx::CorrLaunch{m_blocks, main_cols, 1, main_cols, 0, 0, 0};
+                tail_l = idx::CorrLaunch{m_blocks, tail_tiles, 1, tail_tiles, (int64_t)main_cols * cfg.bn(), 0,
+                                         main_cols * (cfg.threads() / cfg.bm())};
+            }
+        }
+    }
+    const int n_lists = main_l.n_seg * (cfg.threads() / cfg.bm()) +
+                        (split ? tail_l.n_seg * (tail_cfg.threads() / tail_cfg.bm()) : 0);
+    main_l.list_stride = tail_l.list_stride = n_lists;
 
     AR_TRY(ctx->i_bf16.reserve(sizeof(uint16_t) * (size_t)m_pad * lib->Kp));
     AR_TRY(ctx->i_inv.reserve(sizeof(float) * (size_t)n_roi * lib->n_win));
@@ -661,15 +703,21 @@ ar_status index_orientations_ex(ar_context *ctx, const float *images, int64_t n_
     AR_TRY(idx::normalise_cast(images, n_roi, m_pad, lib->n_win, lib->n_dir, lib->Kp, ctx->i_inv.as<float>(),
                                ctx->i_bf16.as<uint16_t>(), s));
     if (cand == 16) {
-        AR_TRY(idx::launch_corr<16>(ctx, cfg, ctx->i_bf16.as<uint16_t>(), lib, m_blocks, n_tiles, tiles_per_seg,
-                                    n_seg, ctx->i_cand_score.as<float>(), ctx->i_cand_idx.as<int32_t>(), s));
+        AR_TRY(idx::launch_corr<16>(ctx, cfg, ctx->i_bf16.as<uint16_t>(), lib, main_l, ctx->i_cand_score.as<float>(),
+                                    ctx->i_cand_idx.as<int32_t>(), s));
+        if (split)
+            AR_TRY(idx::launch_corr<16>(ctx, tail_cfg, ctx->i_bf16.as<uint16_t>(), lib, tail_l,
+                                        ctx->i_cand_score.as<float>(), ctx->i_cand_idx.as<int32_t>(), s));
         idx::k_merge<16><<<(unsigned)((n_roi + 3) / 4), 256, 0, s>>>(
             ctx->i_cand_score.as<float>(), ctx->i_cand_idx.as<int32_t>(), n_lists, n_roi, ctx->i_merge_idx.as<int32_t>());
         AR_HIP(hipGetLastError());
         AR_TRY(idx::launch_rescore<16>(ctx, images, lib, n_roi, k, top_idx, top_score, s));
     } else {
-        AR_TRY(idx::launch_corr<32>(ctx, cfg, ctx->i_bf16.as<uint16_t>(), lib, m_blocks, n_tiles, tiles_per_seg,
-                                    n_seg, ctx->i_cand_score.as<float>(), ctx->i_cand_idx.as<int32_t>(), s));
+        AR_TRY(idx::launch_corr<32>(ctx, cfg, ctx->i_bf16.as<uint16_t>(), lib, main_l, ctx->i_cand_score.as<float>(),
+                                    ctx->i_cand_idx.as<int32_t>(), s));
+        if (split)
+            AR_TRY(idx::launch_corr<32>(ctx, tail_cfg, ctx->i_bf16.as<uint16_t>(), lib, tail_l,
+                                        ctx->i_cand_score.as<float>(), ctx->i_cand_idx.as<int32_t>(), s));
         idx::k_merge<32><<<(unsigned)((n_roi + 3) / 4), 256, 0, s>>>(
             ctx->i_cand_score.as<float>(), ctx->i_cand_idx.as<int32_t>(), n_lists, n_roi, ctx->i_merge_idx.as<int32_t>());
         AR_HIP(hipGetLastError());
