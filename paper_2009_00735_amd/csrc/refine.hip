@@ -49,8 +49,48 @@ __device__ __forceinline__ void rotation(const T *q, T *M)
     M[6] = 2 * (x * z - w * y);     M[7] = 2 * (y * z + w * x);     M[8] = 1 - 2 * (x * x + y * y);
 }
 
+// One evaluated direction v (antipode vm, or -1) from its sums: MODE 2 writes
+// the amplitudes; otherwise J gains e^2 + e'^2 per frequency and, for MODE 1,
+// gu the pair's dJ/du.
+template <int MODE, int NF>
+__device__ __forceinline__ void sf_direction(const float (&C)[NF], const float (&S)[NF], const float (&P)[NF][3],
+                                             const float (&Q)[NF][3], const float (&f)[NF], int nw, bool valid,
+                                             int v, int vm, int p, int n_dir, const float *__restrict__ targets,
+                                             float *__restrict__ amp, int64_t r, float &J, float (&gu)[3])
+{
+    const float inv_n = nw > 0 ? 1.0f / (float)nw : 0.f;
+#pragma unroll
+    for (int w = 0; w < NF; ++w) {
+        const float mag = sqrtf(fmaf(C[w], C[w], S[w] * S[w]));
+        const float A = mag * inv_n;
+        if (MODE == 2) {
+            if (valid) {
+                amp[((size_t)r * NF + w) * n_dir + v] = A;
+                if (vm >= 0) amp[((size_t)r * NF + w) * n_dir + vm] = A;
+            }
+            continue;
+        }
+        const float e = valid ? A - targets[((size_t)p * NF + w) * n_dir + v] : 0.f;
+        const float em = (valid && vm >= 0) ? A - targets[((size_t)p * NF + w) * n_dir + vm] : 0.f;
+        J = fmaf(e, e, J);
+        J = fmaf(em, em, J);
+        if (MODE == 1 && valid && mag >= 1e-12f * (float)nw && nw > 0) {
+            const float k = 2.0f * (e + em) * inv_n * 6.283185307179586f * f[w] / mag;
+            gu[0] = fmaf(k, S[w] * Q[w][0] - C[w] * P[w][0], gu[0]);
+            gu[1] = fmaf(k, S[w] * Q[w][1] - C[w] * P[w][1], gu[1]);
+            gu[2] = fmaf(k, S[w] * Q[w][2] - C[w] * P[w][2], gu[2]);
+        }
+    }
+}
+
+constexpr int kRemAtoms = 16;   // a last tile with fewer directions runs atom-parallel
+
 // MODE 0: score partials; MODE 1: score + gradient partials; MODE 2: amplitudes.
 // NF: number of frequencies (compile-time so the accumulators stay in VGPRs).
+// A last tile with fewer than kRemAtoms directions (e.g. the one direction
+// left after 20 full tiles of the 10242-node mesh's 5121 evaluated ones) is
+// left to k_sf_rem, which splits the atoms over the threads instead, so that
+// it costs a few atom passes rather than a full tile's.
 template <int MODE, int NF>
 __global__ __launch_bounds__(kTile) void k_sf(const float4 *__restrict__ rel, const int64_t *__restrict__ offsets,
                                               const float *__restrict__ quats, const int32_t *__restrict__ phase,
@@ -97,12 +137,18 @@ __global__ __launch_bounds__(kTile) void k_sf(const float4 *__restrict__ rel, co
     }
     const int64_t off0 = offsets[r];
     const int nw = (int)(offsets[r + 1] - off0);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (n_eval - tile * kTile < kRemAtoms) return;   // a short last tile: k_sf_rem writes it
+    // a wave whose 64 directions all lie past the evaluation list (in the
+    // last, partial tile) only helps stage the atoms
+    const bool wave_busy = __builtin_amdgcn_readfirstlane(tile * kTile + (int)(threadIdx.x & ~63u)) < n_eval;
     for (int c0 = 0; c0 < nw; c0 += kChunk) {
         const int nc = min(kChunk, nw - c0);
         __syncthreads();
         for (int i = threadIdx.x; i < nc; i += kTile) xs[i] = rel[off0 + c0 + i];
         __syncthreads();
-        for (int j = 0; j < nc; ++j) {
+        const int n_run = wave_busy ? nc : 0;
+        for (int j = 0; j < n_run; ++j) {
             const float4 x = xs[j];
             const float s = fmaf(uz, x.z, fmaf(uy, x.y, ux * x.x));
 #pragma unroll
@@ -123,37 +169,14 @@ __global__ __launch_bounds__(kTile) void k_sf(const float4 *__restrict__ rel, co
             }
         }
     }
-    const float inv_n = nw > 0 ? 1.0f / (float)nw : 0.f;
     float J = 0.f, gu[3] = {0.f, 0.f, 0.f};
-#pragma unroll
-    for (int w = 0; w < NF; ++w) {
-        const float mag = sqrtf(fmaf(C[w], C[w], S[w] * S[w]));
-        const float A = mag * inv_n;
-        if (MODE == 2) {
-            if (valid) {
-                amp[((size_t)r * NF + w) * n_dir + v] = A;
-                if (vm >= 0) amp[((size_t)r * NF + w) * n_dir + vm] = A;
-            }
-            continue;
-        }
-        const float e = valid ? A - targets[((size_t)p * NF + w) * n_dir + v] : 0.f;
-        const float em = (valid && vm >= 0) ? A - targets[((size_t)p * NF + w) * n_dir + vm] : 0.f;
-        J = fmaf(e, e, J);
-        J = fmaf(em, em, J);
-        if (MODE == 1 && valid && mag >= 1e-12f * (float)nw && nw > 0) {
-            const float k = 2.0f * (e + em) * inv_n * 6.283185307179586f * f[w] / mag;
-            gu[0] = fmaf(k, S[w] * Q[w][0] - C[w] * P[w][0], gu[0]);
-            gu[1] = fmaf(k, S[w] * Q[w][1] - C[w] * P[w][1], gu[1]);
-            gu[2] = fmaf(k, S[w] * Q[w][2] - C[w] * P[w][2], gu[2]);
-        }
-    }
+    sf_direction<MODE, NF>(C, S, P, Q, f, nw, valid, v, vm, p, n_dir, targets, amp, r, J, gu);
     if (MODE == 2) return;
     float part[kPartial];
     part[0] = J;
     part[1] = gu[0] * nx; part[2] = gu[0] * ny; part[3] = gu[0] * nz;
     part[4] = gu[1] * nx; part[5] = gu[1] * ny; part[6] = gu[1] * nz;
     part[7] = gu[2] * nx; part[8] = gu[2] * ny; part[9] = gu[2] * nz;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
     for (int k = 0; k < kPartial; ++k) {
         float x = part[k];
@@ -167,6 +190,109 @@ __global__ __launch_bounds__(kTile) void k_sf(const float4 *__restrict__ rel, co
 #pragma unroll
         for (int w = 0; w < kTile / 64; ++w) x += red[threadIdx.x][w];
         partials[((size_t)r * n_tiles + tile) * kPartial + threadIdx.x] = x;
+    }
+}
+
+// The short last tile of each ROI (fewer than kRemAtoms evaluated
+// directions left after the full tiles): one workgroup per ROI, each
+// direction with the 256 threads split over the atoms (thread t sums atoms
+// t, t + 256, ...), the block reducing the 8 NF sums (2 NF without the
+// gradient); writes that tile's partials (or amplitudes).  Same arguments
+// as k_sf.
+template <int MODE, int NF>
+__global__ __launch_bounds__(kTile) void k_sf_rem(const float4 *__restrict__ rel, const int64_t *__restrict__ offsets,
+                                                  const float *__restrict__ quats, const int32_t *__restrict__ phase,
+                                                  const float *__restrict__ dirs, int n_dir,
+                                                  const int32_t *__restrict__ rep, const int32_t *__restrict__ mate,
+                                                  const int32_t *__restrict__ n_eval_p, int n_tiles,
+                                                  const float *__restrict__ freqs, const float *__restrict__ targets,
+                                                  float *__restrict__ partials, float *__restrict__ amp)
+{
+    const int64_t r = blockIdx.x;
+    const int n_eval = *n_eval_p;
+    const int tile = n_eval / kTile;
+    const int rem = n_eval - tile * kTile;
+    if (rem == 0 || rem >= kRemAtoms) return;
+    const int p = phase[r];
+    float q[4] = {quats[4 * r], quats[4 * r + 1], quats[4 * r + 2], quats[4 * r + 3]};
+    float M[9];
+    rotation(q, M);
+    float f[NF];
+#pragma unroll
+    for (int w = 0; w < NF; ++w) f[w] = freqs[p * NF + w];
+    const int64_t off0 = offsets[r];
+    const int nw = (int)(offsets[r + 1] - off0);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    // atom-parallel: per direction, thread t sums atoms t, t + 256, ...,
+    // then the block reduces the 8 NF sums (2 NF without the gradient)
+    __shared__ float rs[8 * kMaxFreq][kTile / 64];
+    constexpr int NV = MODE == 1 ? 8 * NF : 2 * NF;
+    float Jt = 0.f, G[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    for (int d = 0; d < rem; ++d) {
+        const int vd = rep[tile * kTile + d], vmd = mate[tile * kTile + d];
+        const float dx = dirs[3 * vd], dy = dirs[3 * vd + 1], dz = dirs[3 * vd + 2];
+        const float wx = M[0] * dx + M[1] * dy + M[2] * dz;
+        const float wy = M[3] * dx + M[4] * dy + M[5] * dz;
+        const float wz = M[6] * dx + M[7] * dy + M[8] * dz;
+        float acc[NV];
+#pragma unroll
+        for (int k = 0; k < NV; ++k) acc[k] = 0.f;
+        for (int j = threadIdx.x; j < nw; j += kTile) {
+            const float4 x = rel[off0 + j];
+            const float sd = fmaf(wz, x.z, fmaf(wy, x.y, wx * x.x));
+#pragma unroll
+            for (int w = 0; w < NF; ++w) {
+                const float t = f[w] * sd;
+                const float sn = __builtin_amdgcn_sinf(t);
+                const float cs = __builtin_amdgcn_cosf(t);
+                acc[w] += cs;
+                acc[NF + w] += sn;
+                if (MODE == 1) {
+                    acc[2 * NF + 3 * w] = fmaf(x.x, sn, acc[2 * NF + 3 * w]);
+                    acc[2 * NF + 3 * w + 1] = fmaf(x.y, sn, acc[2 * NF + 3 * w + 1]);
+                    acc[2 * NF + 3 * w + 2] = fmaf(x.z, sn, acc[2 * NF + 3 * w + 2]);
+                    acc[5 * NF + 3 * w] = fmaf(x.x, cs, acc[5 * NF + 3 * w]);
+                    acc[5 * NF + 3 * w + 1] = fmaf(x.y, cs, acc[5 * NF + 3 * w + 1]);
+                    acc[5 * NF + 3 * w + 2] = fmaf(x.z, cs, acc[5 * NF + 3 * w + 2]);
+                }
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < NV; ++k) {
+            float x = acc[k];
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
+            if (lane == 0) rs[k][wave] = x;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            float tot[NV];
+#pragma unroll
+            for (int k = 0; k < NV; ++k) tot[k] = rs[k][0] + rs[k][1] + rs[k][2] + rs[k][3];
+            float Cd[NF], Sd[NF], Pd[NF][3], Qd[NF][3];
+#pragma unroll
+            for (int w = 0; w < NF; ++w) {
+                Cd[w] = tot[w];
+                Sd[w] = tot[NF + w];
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    Pd[w][c] = MODE == 1 ? tot[(2 * NF + 3 * w + c) % NV] : 0.f;
+                    Qd[w][c] = MODE == 1 ? tot[(5 * NF + 3 * w + c) % NV] : 0.f;
+                }
+            }
+            float gd[3] = {0.f, 0.f, 0.f};
+            sf_direction<MODE, NF>(Cd, Sd, Pd, Qd, f, nw, true, vd, vmd, p, n_dir, targets, amp, r, Jt, gd);
+            G[0] = fmaf(gd[0], dx, G[0]); G[1] = fmaf(gd[0], dy, G[1]); G[2] = fmaf(gd[0], dz, G[2]);
+            G[3] = fmaf(gd[1], dx, G[3]); G[4] = fmaf(gd[1], dy, G[4]); G[5] = fmaf(gd[1], dz, G[5]);
+            G[6] = fmaf(gd[2], dx, G[6]); G[7] = fmaf(gd[2], dy, G[7]); G[8] = fmaf(gd[2], dz, G[8]);
+        }
+        __syncthreads();
+    }
+    if (MODE != 2 && threadIdx.x == 0) {
+        float *o = partials + ((size_t)r * n_tiles + tile) * kPartial;
+        o[0] = Jt;
+#pragma unroll
+        for (int k = 0; k < 9; ++k) o[1 + k] = G[k];
     }
 }
 
@@ -474,6 +600,20 @@ template <int MODE> SfFn sf_kernel(int n_freq)
     }
 }
 
+template <int MODE> SfFn sf_rem_kernel(int n_freq)
+{
+    switch (n_freq) {
+    case 1: return sf::k_sf_rem<MODE, 1>;
+    case 2: return sf::k_sf_rem<MODE, 2>;
+    case 3: return sf::k_sf_rem<MODE, 3>;
+    case 4: return sf::k_sf_rem<MODE, 4>;
+    case 5: return sf::k_sf_rem<MODE, 5>;
+    case 6: return sf::k_sf_rem<MODE, 6>;
+    case 7: return sf::k_sf_rem<MODE, 7>;
+    default: return sf::k_sf_rem<MODE, 8>;
+    }
+}
+
 static ar_status sf_launch(ar_context *ctx, int mode, const float *rel, const int64_t *offsets, int64_t n_roi,
                            const float *quats, const int32_t *phase, const float *dirs, int32_t n_dir,
                            const float *freqs, const float *targets, int32_t n_freq, float *score, float *grad,
@@ -491,6 +631,10 @@ static ar_status sf_launch(ar_context *ctx, int mode, const float *rel, const in
         sf_kernel<2>(n_freq)<<<blocks, sf::kTile, 0, s>>>((const float4 *)rel, offsets, quats, phase, dirs, n_dir,
                                                           rep, mate, n_eval, n_tiles, freqs, targets, nullptr, amp);
         AR_HIP(hipGetLastError());
+        sf_rem_kernel<2>(n_freq)<<<(unsigned)n_roi, sf::kTile, 0, s>>>((const float4 *)rel, offsets, quats, phase,
+                                                                       dirs, n_dir, rep, mate, n_eval, n_tiles,
+                                                                       freqs, targets, nullptr, amp);
+        AR_HIP(hipGetLastError());
         return AR_OK;
     }
     AR_TRY(ctx->r_partials.reserve(sizeof(float) * (size_t)n_roi * n_tiles * sf::kPartial));
@@ -498,6 +642,10 @@ static ar_status sf_launch(ar_context *ctx, int mode, const float *rel, const in
     SfFn fn = mode == 1 ? sf_kernel<1>(n_freq) : sf_kernel<0>(n_freq);
     fn<<<blocks, sf::kTile, 0, s>>>((const float4 *)rel, offsets, quats, phase, dirs, n_dir, rep, mate, n_eval,
                                     n_tiles, freqs, targets, part, nullptr);
+    AR_HIP(hipGetLastError());
+    SfFn fr = mode == 1 ? sf_rem_kernel<1>(n_freq) : sf_rem_kernel<0>(n_freq);
+    fr<<<(unsigned)n_roi, sf::kTile, 0, s>>>((const float4 *)rel, offsets, quats, phase, dirs, n_dir, rep, mate,
+                                             n_eval, n_tiles, freqs, targets, part, nullptr);
     AR_HIP(hipGetLastError());
     sf::k_sf_reduce<<<(unsigned)((n_roi + 255) / 256), 256, 0, s>>>(part, n_tiles, n_roi, quats, score,
                                                                     mode == 1 ? grad : nullptr);

@@ -34,11 +34,12 @@ def qmul(a, b):
                      w1 * y2 - x1 * z2 + y1 * w2 + z1 * x2, w1 * z2 + x1 * y2 - y1 * x2 + z1 * w2])
 
 
-def make_case(orc, level, n_roi, sigma=0.05, eta=0.5, R=2.0, seed=0, off_deg=3.0):
+def make_case(orc, level, n_roi, sigma=0.05, eta=0.5, R=2.0, seed=0, off_deg=3.0, dirs=None):
     """ROIs cut from fcc Al crystals at random true orientations, start
     orientations rotated `off_deg` away; target from the unrotated crystal
-    (FP64 oracle, cast to float32 and shared by both sides)."""
-    dirs = synth.icosphere(level)
+    (FP64 oracle, cast to float32 and shared by both sides).  Directions:
+    the icosphere of `level` unless `dirs` is given."""
+    dirs = synth.icosphere(level) if dirs is None else dirs
     ref = synth.lattice_in_ball("fcc", 0.405, np.array([1.0, 0, 0, 0]), np.zeros(3), np.zeros(3), R + 0.5)
     rel0 = orc.roi_gather(ref.astype(np.float32), np.array([0.01, 0.02, -0.015], np.float32), R)
     T = orc.sf_amplitudes(rel0, np.array([1.0, 0, 0, 0]), dirs, F_AL).astype(np.float32)
@@ -64,8 +65,20 @@ def gpu_args(dirs, T, offsets, rel4, n_roi):
             dev(F_AL[None]), dev(T[None]))
 
 
-def test_amplitudes_and_score_match_fp64(nat, ctx, orc):
-    dirs, T, rels, offsets, rel4, q0, qt = make_case(orc, 3, 4)
+def _antipodal_mesh(n_pairs, seed):
+    g = np.random.default_rng(seed).standard_normal((n_pairs, 3))
+    g = (g / np.linalg.norm(g, axis=1, keepdims=True)).astype(np.float32)
+    return np.concatenate([g, -g])
+
+
+@pytest.mark.parametrize("mesh", ["icosphere3", "icosphere4", "pairs271", "pairs272"])
+def test_amplitudes_and_score_match_fp64(nat, ctx, orc, mesh):
+    """Evaluated directions per ROI: 321 (a last tile of 65, lane per
+    direction), 1281 and 271 (last tiles of 1 and 15 directions, atom-parallel
+    short-tile kernel), 272 (a last tile of 16, lane per direction)."""
+    dirs = {"icosphere3": None, "icosphere4": synth.icosphere(4), "pairs271": _antipodal_mesh(271, 61),
+            "pairs272": _antipodal_mesh(272, 62)}[mesh]
+    dirs, T, rels, offsets, rel4, q0, qt = make_case(orc, 3, 4, dirs=dirs)
     rel, off, ph, d, f, t = gpu_args(dirs, T, offsets, rel4, 4)
     amp = nat.ar_sf_amplitudes(ctx, rel, off, dev(q0), ph, d, f).cpu().numpy()
     score, _ = nat.ar_sf_score_grad(ctx, rel, off, dev(q0), ph, d, f, t, grad=False)
@@ -159,11 +172,12 @@ def test_refinement_recovers_orientation_and_tracks_oracle(nat, ctx, orc):
 
 def test_unpaired_and_mixed_directions(nat, ctx, orc):
     """Directions without antipodes are evaluated alone; a mixed set (mesh
-    plus random extra directions) matches the oracle and FD on both paths."""
+    plus random extra directions) matches the oracle and FD on both paths.
+    The 10-direction set runs entirely in the short-tile kernel."""
     gen = np.random.default_rng(9)
     extra = gen.normal(size=(37, 3))
     extra = (extra / np.linalg.norm(extra, axis=1, keepdims=True)).astype(np.float32)
-    for dirs in (extra, np.concatenate([synth.icosphere(2), extra])):
+    for dirs in (extra, extra[:10], np.concatenate([synth.icosphere(2), extra])):
         dirs = np.ascontiguousarray(dirs)
         p = synth.lattice_in_ball("fcc", 0.405, synth.random_orientations(1, 11)[0], gen.random(3), np.zeros(3), 2.5)
         rel = orc.roi_gather(p.astype(np.float32), np.zeros(3, np.float32), 2.0)
