@@ -1,6 +1,6 @@
 #!/usr/bin/env python3
 """Benchmark of the real-space signature + orientation indexing hot path on
-one MI355X, on the single-grain fcc Al workload (config 2 of the benchmark
+one MI355X, on the single-grain fcc Al workload (the benchmark
 definition): a 20 x 20 x 40 nm box at 30 atoms/nm^3, sigma = 0.05 nm,
 2000 ROIs of R = 2 nm on a 2 nm grid, 10242 icosphere directions, 1024 bins,
 4 peak windows, indexed against 20000 rotated fcc references.
@@ -71,7 +71,7 @@ def parse():
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain device copy of 1 GiB (scale factor for HBM counters)")
     ap.add_argument("--compare", action="store_true",
-                    help="instead of the step: plain vs batched signatures (configs 2 and 3) and BF16-MFMA vs "
+                    help="instead of the step: plain vs batched signatures (single-grain box, polycrystal cone) and BF16-MFMA vs "
                          "plain FP32 indexing on the same GPU; prints one JSON line")
     return ap.parse_args()
 
@@ -115,7 +115,7 @@ def main():
 
     # ------------------------------------------------------------ setup (untimed)
     t_setup = time.perf_counter()
-    s = synth.config2()
+    s = synth.single_grain_box()
     n_roi, n_dir, nb, R = len(s.centres), len(s.directions), s.nbins, s.radius
     ctx = nat.Context(0)
     peaks = nat.ar_measure_peaks(ctx)      # measured roofline denominators (probe loops, ~1 s)
@@ -229,7 +229,7 @@ def main():
         "peak": PEAK_FP32_VECTOR / 1e12,
         "unit": "TFLOP/s",
         "frac": achieved_terms * flop_per_term / PEAK_FP32_VECTOR,
-        "traffic": measured_traffic("k_sf_adjoint_cfg2_hbm_counters.md", "paper_2009_00735_amd/csrc/refine.hip"),
+        "traffic": measured_traffic("k_sf_adjoint_single_grain_hbm_counters.md", "paper_2009_00735_amd/csrc/refine.hip"),
         "traffic_unit": "bytes per launch (FETCH_SIZE x2.0 + WRITE_SIZE x1.0, copy-probe scaled)",
         "terms_per_s": achieved_terms,
         "evaluated_directions": n_eval,
@@ -293,7 +293,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "cfg2 single-grain fcc Al box 20x20x40 nm, 30 atoms/nm^3, sigma 0.05 nm; "
+        "config": {"workload": "single-grain fcc Al box 20x20x40 nm, 30 atoms/nm^3, sigma 0.05 nm; "
                                "2000 ROIs R=2 nm; 10242 directions; 1024 bins; 4 windows; "
                                "20000-orientation library; 50-step refinement",
                    "n_roi": n_roi, "n_dir": n_dir, "nbins": nb, "n_win": n_win, "n_lib": n_lib,
@@ -328,11 +328,12 @@ def compare(nat, synth, torch, dev):
     """The batched and BF16 forms against the plain method on the same GPU.
     Signatures: the plain per-launch kernel (one workgroup per ROI and
     256-direction tile) against the autotuned persistent plan replayed as a
-    graph, on config 2 (even ROIs) and config 3 (uneven, surface-clipped);
+    graph, on the single-grain box (even ROIs) and the polycrystal cone (uneven,
+    surface-clipped);
     the images must be bit-identical.  Indexing: the BF16 MFMA correlation
     with fused top-16 and FP32 rescore against a plain FP32 evaluation of the
     same dense score (library GEMM in FP32 through torch, then top-16) on the
-    config-2 images and 20000-reference library; reported: times and top-1
+    single-grain images and 20000-reference library; reported: times and top-1
     agreement."""
     def best_ms(fn, reps=3):
         fn()
@@ -349,7 +350,7 @@ def compare(nat, synth, torch, dev):
 
     ctx = nat.Context(0)
     rec = {"compare": "plain vs batched signatures; BF16 MFMA + FP32 rescore vs plain FP32 indexing"}
-    for name, s in (("cfg2", synth.config2()), ("cfg3", synth.config3())):
+    for name, s in (("single_grain", synth.single_grain_box()), ("polycrystal", synth.polycrystal_cone())):
         w = nat.windows_for(s.radius, s.nbins, s.spacings)
         pos = torch.from_numpy(s.positions).to(dev)
         cen = torch.from_numpy(s.centres).to(dev)
@@ -367,7 +368,7 @@ def compare(nat, synth, torch, dev):
             "plain_ms": t_plain, "batched_ms": t_plan, "speedup": t_plain / t_plan,
             "batched_roi_dir_per_s": units / (t_plan / 1e3), "identical": bool(torch.equal(out, plain)),
             "plan": dict(zip(["dirs_per_item", "atoms_per_stage", "blocks_per_cu", "min_waves"], plan.config()))}
-        if name == "cfg2":
+        if name == "single_grain":
             images = out.clone()
             rpos, roffs = synth.reference_rois(0, 16, R=s.radius, cfg=4)
             ref = nat.araullo_signatures(ctx, torch.from_numpy(rpos).to(dev), torch.from_numpy(roffs).to(dev),
@@ -389,14 +390,14 @@ def compare(nat, synth, torch, dev):
     t_fp32 = best_ms(plain_fp32)
     idx_fp32 = plain_fp32()
     agree = float((idx_fp32[:, 0] == idx_bf16[:, 0].long()).float().mean())
-    rec["indexing_cfg2"] = {
+    rec["indexing_single_grain"] = {
         "rois": int(images.shape[0]), "references": int(L.shape[0]), "k": 16,
         "bf16_mfma_rescored_ms": t_bf16, "plain_fp32_ms": t_fp32, "speedup": t_fp32 / t_bf16,
         "top1_agreement": agree,
         "plain_fp32": "normalise, FP32 GEMM S L^T (torch / hipBLASLt), |L|^2 - 2 S.L, torch.topk"}
     # the paper's sparse form of Eq. S1 (strongest reference entries through a
     # look-up table) against the dense score, same images and orientations
-    truth = torch.from_numpy(synth.config2().truth_q).to(dev)
+    truth = torch.from_numpy(synth.single_grain_box().truth_q).to(dev)
     n_rot = lib_q.shape[0]
     dis_dense = nat.ar_disorientation_cubic(lib_q[idx_bf16[:, 0].long()].contiguous(), truth).cpu().numpy()
     sparse = {"rois": int(images.shape[0]), "orientations": n_rot, "k": 16,
@@ -446,7 +447,7 @@ def compare(nat, synth, torch, dev):
                   "for 16 ROIs against those 400",
         "lut_rows_per_s": len(sub) / t_olut, "terms_per_s": 16 * len(sub) * 1000 / t_oidx,
         "full_call_estimate_s": 2000 * n_rot * 1000 / (16 * len(sub) * 1000 / t_oidx)}
-    rec["sparse_indexing_cfg2"] = sparse
+    rec["sparse_indexing_single_grain"] = sparse
     log("compare: indexing done")
     # sub-lattice signatures: an L1_2 Al3Sc crystal (eta 0.5, sigma 0.03 nm),
     # 2000 ROIs of R = 2 nm, 10242 directions, 1024 bins, the four windows plus
@@ -509,13 +510,13 @@ def compare(nat, synth, torch, dev):
     rec["fsp_cubic_grid"] = fsp
     log("compare: reciprocal-space grid done")
     del rel, off
-    # adaptive ROI-grid refinement on config 3: a coarse 2 nm grid over the
+    # adaptive ROI-grid refinement on the polycrystal cone: a coarse 2 nm grid over the
     # specimen's bounding box (ROIs with >= 100 atoms), batched signatures,
     # kappa = 0.75 on any window, 5^3 split, batched signatures of the refined
     # ROIs; a naive 5^3 refinement of every coarse ROI is priced at the
     # measured refined rate
-    log("compare: adaptive grid on config 3")
-    s3 = synth.config3()
+    log("compare: adaptive grid on the polycrystal cone")
+    s3 = synth.polycrystal_cone()
     pos3 = torch.from_numpy(s3.positions).to(dev)
     dirs3 = torch.from_numpy(s3.directions).to(dev)
     w3 = nat.windows_for(s3.radius, s3.nbins, s3.spacings)
@@ -544,7 +545,7 @@ def compare(nat, synth, torch, dev):
     log(f"adaptive grid: {refined.shape[0]} refined ROIs")
     off_r, img_r, t_refined, _ = batch(refined.contiguous(), cfg_c)
     n_c, n_r = int(coarse.shape[0]), int(refined.shape[0])
-    rec["adaptive_grid_cfg3"] = {
+    rec["adaptive_grid_polycrystal"] = {
         "coarse_rois": n_c, "kept": n_r // 125, "refined_rois": n_r, "directions": int(dirs3.shape[0]),
         "coarse_signatures_ms": t_coarse, "selection_and_split_ms": t_refine, "refined_signatures_ms": t_refined,
         "total_ms": t_coarse + t_refine + t_refined,

@@ -57,7 +57,7 @@ def indexing(reps: int) -> None:
 
 def signatures(reps: int) -> None:
     ctx = nat.Context(0)
-    s = synth.config2()
+    s = synth.single_grain_box()
     w = nat.windows_for(s.radius, s.nbins, s.spacings)
     pos = torch.from_numpy(s.positions).cuda()
     cen = torch.from_numpy(s.centres).cuda()
@@ -71,7 +71,7 @@ def signatures(reps: int) -> None:
 
 def sparse(reps: int) -> None:
     ctx = nat.Context(0)
-    s = synth.config2()
+    s = synth.single_grain_box()
     w = nat.windows_for(s.radius, s.nbins, s.spacings)
     dirs = torch.from_numpy(s.directions).cuda()
     rpos, roffs = synth.reference_rois(0, 16, R=s.radius, cfg=4)

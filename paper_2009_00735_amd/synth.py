@@ -287,7 +287,7 @@ class Specimen:
 PHASES = (("fcc", A_AL), ("bcc", A_FE))
 
 
-def config1(nbins: int = 256, level: int = 3) -> Specimen:
+def single_roi(nbins: int = 256, level: int = 3) -> Specimen:
     """Single ROI R = 1 nm in a rotated fcc Al crystal, 50 % deletion, sigma 0.05 nm."""
     cfg = 1
     q = shoemake(1, rng(cfg, STREAM_ORIENTATION))[0]
@@ -299,10 +299,10 @@ def config1(nbins: int = 256, level: int = 3) -> Specimen:
     return Specimen(positions=pts.astype(np.float32), centres=np.zeros((1, 3), np.float32), radius=R,
                     directions=icosphere(level), nbins=nbins, spacings=window_spacings(),
                     truth_q=q[None], truth_phase=np.zeros(1, np.int32), truth_share=np.ones(1),
-                    name="cfg1: single ROI R=1 nm fcc Al, 642 directions, 256 bins")
+                    name="single ROI R=1 nm fcc Al, 642 directions, 256 bins")
 
 
-def config2(level: int = 5, nbins: int = 1024, grid: Tuple[int, int, int] = (10, 10, 20)) -> Specimen:
+def single_grain_box(level: int = 5, nbins: int = 1024, grid: Tuple[int, int, int] = (10, 10, 20)) -> Specimen:
     """Single-grain fcc Al box 20x20x40 nm at 30 atoms/nm^3, ROIs on a 2 nm grid."""
     cfg = 2
     q = shoemake(1, rng(cfg, STREAM_ORIENTATION))[0]
@@ -322,7 +322,7 @@ def config2(level: int = 5, nbins: int = 1024, grid: Tuple[int, int, int] = (10,
                     directions=icosphere(level), nbins=nbins, spacings=window_spacings(),
                     truth_q=np.repeat(q[None], n, 0), truth_phase=np.zeros(n, np.int32),
                     truth_share=np.ones(n),
-                    name=f"cfg2: fcc Al box {2*gx}x{2*gy}x{2*gz} nm, {n} ROIs R=2 nm, "
+                    name=f"single-grain fcc Al box {2*gx}x{2*gy}x{2*gz} nm, {n} ROIs R=2 nm, "
                          f"{len(icosphere(level)) if level < 6 else 40962} directions, {nbins} bins")
 
 
@@ -456,7 +456,7 @@ def polycrystal_rois(n_roi: int, min_atoms: int = 100, max_atoms: Optional[int] 
             np.concatenate(acc_n)[:n_roi])
 
 
-def config3(n_roi: int = 8000, level: int = 5, nbins: int = 1024) -> Specimen:
+def polycrystal_cone(n_roi: int = 8000, level: int = 5, nbins: int = 1024) -> Specimen:
     """Fcc Al / bcc Fe Voronoi polycrystal in a truncated cone; uneven,
     surface-clipped ROIs of R = 2 nm with at least 100 atoms."""
     pos, grain, gq, gphase = polycrystal(cfg=3)
@@ -464,10 +464,10 @@ def config3(n_roi: int = 8000, level: int = 5, nbins: int = 1024) -> Specimen:
     return Specimen(positions=pos, centres=centres, radius=2.0, directions=icosphere(level), nbins=nbins,
                     spacings=window_spacings(), truth_q=gq[dom], truth_phase=gphase[dom].astype(np.int32),
                     truth_share=share, atom_grain=grain, grain_q=gq, grain_phase=gphase,
-                    name=f"cfg3: 20-grain fcc Al + bcc Fe cone, {n_roi} uneven ROIs R=2 nm")
+                    name=f"20-grain fcc Al + bcc Fe cone, {n_roi} uneven ROIs R=2 nm")
 
 
-def config5_rois(n_roi: int = 4096):
+def refinement_rois(n_roi: int = 4096):
     """ROIs of the polycrystal with 800-1200 atoms and dominant share >= 0.9."""
     pos, grain, gq, gphase = polycrystal(cfg=3)
     centres, dom, share, counts = polycrystal_rois(n_roi, min_atoms=800, max_atoms=1200, min_share=0.9,

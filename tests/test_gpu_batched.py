@@ -22,8 +22,8 @@ def ctx(nat):
 
 
 @pytest.fixture(scope="module")
-def cfg3(nat, ctx):
-    s = synth.config3()
+def cone(nat, ctx):
+    s = synth.polycrystal_cone()
     pos = torch.from_numpy(s.positions).cuda()
     cen = torch.from_numpy(s.centres).cuda()
     dirs = torch.from_numpy(s.directions).cuda()
@@ -32,8 +32,8 @@ def cfg3(nat, ctx):
     return s, pos, cen, dirs, off, rel, w
 
 
-def test_plan_equals_plain_and_replays(nat, ctx, cfg3):
-    s, pos, cen, dirs, off, rel, w = cfg3
+def test_plan_equals_plain_and_replays(nat, ctx, cone):
+    s, pos, cen, dirs, off, rel, w = cone
     counts = torch.diff(off).cpu().numpy()
     assert counts.min() >= 100 and counts.max() > 1000
     plain = nat.araullo_signatures_csr(ctx, rel, off, s.radius, dirs, s.nbins, w)
@@ -55,12 +55,12 @@ def test_plan_equals_plain_and_replays(nat, ctx, cfg3):
 
 
 @pytest.mark.parametrize("dpi,cap,bpc,occ", [(7, 256, 2, 1), (64, 512, 4, 4), (33, 1024, 3, 1), (128, 4096, 1, 4)])
-def test_every_plan_configuration_is_bit_identical(nat, ctx, cfg3, dpi, cap, bpc, occ):
+def test_every_plan_configuration_is_bit_identical(nat, ctx, cone, dpi, cap, bpc, occ):
     """Stages smaller than the largest ROI stream atoms in chunks (workgroup
     barriers per refill); direction chunks that do not divide the mesh leave
     idle wavefronts in the last round.  Histograms are exact and the
     transform code is shared, so every configuration writes the same bits."""
-    s, pos, cen, dirs, off, rel, w = cfg3
+    s, pos, cen, dirs, off, rel, w = cone
     plain = nat.araullo_signatures_csr(ctx, rel, off, s.radius, dirs, s.nbins, w)
     plan = nat.SignaturePlan(ctx, len(s.centres), int(off[-1]), len(s.directions), s.nbins, len(w))
     plan.set_config(dpi, cap, bpc, occ)
@@ -71,8 +71,8 @@ def test_every_plan_configuration_is_bit_identical(nat, ctx, cfg3, dpi, cap, bpc
         assert torch.equal(img, plain), graph
 
 
-def test_plan_sampled_oracle_parity(nat, ctx, orc, cfg3):
-    s, pos, cen, dirs, off, rel, w = cfg3
+def test_plan_sampled_oracle_parity(nat, ctx, orc, cone):
+    s, pos, cen, dirs, off, rel, w = cone
     plan = nat.SignaturePlan(ctx, len(s.centres), int(off[-1]), len(s.directions), s.nbins, len(w))
     img = plan.run(rel, off, s.radius, dirs, w, use_graph=True)
     torch.cuda.synchronize()
@@ -86,8 +86,8 @@ def test_plan_sampled_oracle_parity(nat, ctx, orc, cfg3):
         assert np.abs(got[i] - ref[i]).max() <= 1e-5 * rcnt[i]
 
 
-def test_plan_argument_checks(nat, ctx, cfg3):
-    s, pos, cen, dirs, off, rel, w = cfg3
+def test_plan_argument_checks(nat, ctx, cone):
+    s, pos, cen, dirs, off, rel, w = cone
     plan = nat.SignaturePlan(ctx, 10, 100, len(s.directions), s.nbins, len(w))
     with pytest.raises(nat.AraulloError):
         plan.run(rel, off, s.radius, dirs, w, use_graph=False)      # n_roi above the plan capacity

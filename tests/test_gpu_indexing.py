@@ -60,10 +60,10 @@ def reference_library(orc, R, nbins, dirs, windows, n_lib, cfg):
     return R0, q, L
 
 
-def test_index_cfg1_rotated_library(nat, ctx, orc):
-    """Config 1: 1000 rotated fcc references (level-3 mesh, 256 bins); the
-    config-1 ROI plus 36 ROIs of other random crystals (ragged M, N, K)."""
-    s = synth.config1()
+def test_index_single_roi_rotated_library(nat, ctx, orc):
+    """Single ROI: 1000 rotated fcc references (level-3 mesh, 256 bins); the
+    single-ROI specimen's ROI plus 36 ROIs of other random crystals (ragged M, N, K)."""
+    s = synth.single_roi()
     w = orc.windows_for(s.radius, s.nbins, s.spacings)
     R0, q, L = reference_library(orc, s.radius, s.nbins, s.directions, w, 1000, 1)
     cents = np.zeros((36, 3), np.float32)
@@ -77,7 +77,7 @@ def test_index_cfg1_rotated_library(nat, ctx, orc):
     gidx, gsc = nat.index_orientations(ctx, dev(S), lib, 16)
     rep = {}
     check_topk(orc, S, L, gidx.cpu().numpy(), gsc.cpu().numpy(), 16, rep)
-    print("cfg1 indexing:", rep)
+    print("single-ROI indexing:", rep)
 
 
 def test_index_self(nat, ctx, orc):

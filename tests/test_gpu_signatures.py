@@ -34,8 +34,8 @@ def _sorted_rows(a):
     return a[np.lexsort((a[:, 2], a[:, 1], a[:, 0]))]
 
 
-def test_gather_bitexact_cfg1(nat, ctx, orc):
-    s = synth.config1()
+def test_gather_bitexact_single_roi(nat, ctx, orc):
+    s = synth.single_roi()
     off, rel = nat.ar_roi_gather(ctx, dev(s.positions), dev(s.centres), s.radius)
     ref = orc.roi_gather(s.positions, s.centres[0], s.radius)
     assert int(off[-1]) == len(ref)
@@ -43,8 +43,8 @@ def test_gather_bitexact_cfg1(nat, ctx, orc):
     assert np.all(rel[:, 3].cpu().numpy() == 0)
 
 
-def test_gather_cfg2_full_counts(nat, ctx, orc):
-    s = synth.config2()
+def test_gather_single_grain_full_counts(nat, ctx, orc):
+    s = synth.single_grain_box()
     off, rel = nat.ar_roi_gather(ctx, dev(s.positions), dev(s.centres), s.radius)
     off = off.cpu().numpy()
     counts = np.diff(off)
@@ -64,7 +64,7 @@ def test_gather_cfg2_full_counts(nat, ctx, orc):
 
 @pytest.mark.parametrize("nbins", [256, 512, 1024, 2048, 4096])
 def test_sdm_histograms_bitexact_and_spectra(nat, ctx, orc, nbins):
-    s = synth.config1()
+    s = synth.single_roi()
     dirs = s.directions[::5]
     hist, amp = nat.araullo_sdm(ctx, dev(s.positions), dev(s.centres), s.radius, dev(dirs), nbins)
     rel = orc.roi_gather(s.positions, s.centres[0], s.radius)
@@ -77,8 +77,8 @@ def test_sdm_histograms_bitexact_and_spectra(nat, ctx, orc, nbins):
     assert np.allclose(a[:, 0], len(rel))
 
 
-def test_images_cfg1(nat, ctx, orc):
-    s = synth.config1()
+def test_images_single_roi(nat, ctx, orc):
+    s = synth.single_roi()
     w = nat.windows_for(s.radius, s.nbins, s.spacings)
     assert np.array_equal(w.numpy(), orc.windows_for(s.radius, s.nbins, s.spacings))
     img, cnt = nat.araullo_signatures(ctx, dev(s.positions), dev(s.centres), s.radius, dev(s.directions), s.nbins, w)
@@ -88,10 +88,10 @@ def test_images_cfg1(nat, ctx, orc):
     assert err.max() <= TOL * rcnt[0]
 
 
-def test_images_cfg2_sampled(nat, ctx, orc):
-    """Full config-2 launch (2000 ROIs x 10242 directions, 1024 bins);
+def test_images_single_grain_sampled(nat, ctx, orc):
+    """Full single-grain launch (2000 ROIs x 10242 directions, 1024 bins);
     sampled (ROI, direction) outputs against the oracle."""
-    s = synth.config2()
+    s = synth.single_grain_box()
     w = nat.windows_for(s.radius, s.nbins, s.spacings)
     img, cnt = nat.araullo_signatures(ctx, dev(s.positions), dev(s.centres), s.radius, dev(s.directions), s.nbins, w)
     torch.cuda.synchronize()
@@ -135,7 +135,7 @@ def test_edge_cases_empty_single_and_large_roi(nat, ctx, orc):
 
 
 def test_csr_entry_matches_position_entry(nat, ctx):
-    s = synth.config1()
+    s = synth.single_roi()
     w = nat.windows_for(s.radius, s.nbins, s.spacings)
     img, _ = nat.araullo_signatures(ctx, dev(s.positions), dev(s.centres), s.radius, dev(s.directions), s.nbins, w)
     off, rel = nat.ar_roi_gather(ctx, dev(s.positions), dev(s.centres), s.radius)
@@ -144,7 +144,7 @@ def test_csr_entry_matches_position_entry(nat, ctx):
 
 
 def test_invalid_arguments_write_nothing(nat, ctx):
-    s = synth.config1()
+    s = synth.single_roi()
     with pytest.raises(nat.AraulloError):
         nat.araullo_signatures(ctx, dev(s.positions), dev(s.centres), s.radius, dev(s.directions), 300, [[8, 9]])
     with pytest.raises(nat.AraulloError):

@@ -1,10 +1,10 @@
-"""Configurations 3 -> 4 -> 5 at full size on the GPU.
+"""Polycrystal signatures -> two-phase indexing -> refinement at full size on the GPU.
 
 Pipeline (throughput and accuracy against the synthetic ground truth): the
-20000 config-4 ROIs of the fcc-Al / bcc-Fe polycrystal (surface-clipped,
+20000 ROIs of the fcc-Al / bcc-Fe polycrystal (surface-clipped,
 100..1500 atoms) are indexed against a library of 2 phases x 50000 Shoemake
 orientations (100000 rotated references, K = 4 x 10242; BF16 MFMA
-correlation, top-16, FP32 rescore); 4096 config-5 ROIs (800..1200 atoms,
+correlation, top-16, FP32 rescore); 4096 refinement ROIs (800..1200 atoms,
 dominant-grain share >= 0.9) are refined for 50 steps from their top-1 with
 the per-phase structure-factor score.
 
@@ -13,11 +13,11 @@ drawn from seeded generators (never taken from the GPU path):
   * signatures of sampled polycrystal ROIs and of the reference crystals, on
     sampled directions (1e-5 N_w);
   * rotated library rows of sampled orientations, level-5 mesh (exact);
-  * indexing at the config-4 shape (20000 ROIs x 100000 references x
+  * indexing at the two-phase shape (20000 ROIs x 100000 references x
     40968 nodes) on seeded images generated on the device by torch: on 8
     sampled ROIs the GPU top-1 equals the FP64 top-1 over all 100000
     references or is a tie, and every returned score is within 1e-5 of FP64;
-  * the structure-factor adjoint of sampled config-5 ROIs at a seeded
+  * the structure-factor adjoint of sampled refinement ROIs at a seeded
     orientation 2 deg from the truth, with the oracle's target, against FP64
     central differences (relative 1e-3)."""
 import concurrent.futures as cf
@@ -89,7 +89,7 @@ def world(nat, ctx):
                 lib=lib, libq=libq, libph=libph, T=T, ref_imgs=refs, ref_in=ref_in)
 
 
-def test_cfg4_signatures_and_references_sampled(nat, ctx, orc, world):
+def test_polycrystal_signatures_and_references_sampled(nat, ctx, orc, world):
     """GPU images of sampled polycrystal ROIs and of every reference-crystal
     ROI against the oracle's, on 400 sampled directions."""
     centres, dom, share, counts = synth.polycrystal_rois(20000)
@@ -110,7 +110,7 @@ def test_cfg4_signatures_and_references_sampled(nat, ctx, orc, world):
             assert np.abs(g[i] - oref[i]).max() <= 1e-5 * ocnt[i]
 
 
-def test_cfg4_rotated_rows_sampled(nat, ctx, orc, world):
+def test_two_phase_rotated_rows_sampled(nat, ctx, orc, world):
     """Rotated reference rows on the level-5 mesh for sampled library
     orientations of both phases, from an oracle-side (seeded) reference."""
     ref = np.random.default_rng(37).random((2, 4, len(world["dirs"]))).astype(np.float32)
@@ -141,7 +141,7 @@ def oracle_top16(orc, S_sel, L_dev, chunk=10000):
     return Sh, best_i, best_s
 
 
-def test_cfg4_indexing_shape_parity(nat, ctx, orc):
+def test_two_phase_100k_indexing_shape_parity(nat, ctx, orc):
     """20000 ROI images x 100000 references x (4 x 10242) nodes, seeded on the
     device (torch generator): library rows are squared uniforms, ROI r is row
     truth[r] with a per-window gain and 5 % multiplicative noise."""
@@ -171,10 +171,10 @@ def test_cfg4_indexing_shape_parity(nat, ctx, orc):
         if gidx[r, 0] != oi[a, 0]:
             assert d64[0] - osc[a, 0] <= 1e-5 * osc[a, 0] + 1e-6, (r, gidx[r, 0], oi[a, 0], d64[0], osc[a, 0])
             ties += 1
-    print(f"\ncfg4 shape: {n_roi} x {n_lib} indexed in {dt * 1e3:.1f} ms; ties on the sample {ties}/8", flush=True)
+    print(f"\ntwo-phase shape: {n_roi} x {n_lib} indexed in {dt * 1e3:.1f} ms; ties on the sample {ties}/8", flush=True)
 
 
-def test_cfg4_pipeline_accuracy(nat, ctx, orc, world):
+def test_two_phase_pipeline_accuracy(nat, ctx, orc, world):
     centres, dom, share, counts = synth.polycrystal_rois(20000)
     S = nat.araullo_signatures(ctx, world["pos_d"], dev(centres), R, world["dirs_d"], NB, world["w"], counts=False)
     torch.cuda.synchronize()
@@ -187,7 +187,7 @@ def test_cfg4_pipeline_accuracy(nat, ctx, orc, world):
     phase_ok = world["libph"][top] == world["gphase"][dom]
     dis = orc.disorientation_cubic(world["libq"][top], world["gq"][dom])
     m = good & phase_ok
-    print(f"cfg4: {len(centres)} ROIs x {len(world['libq'])} references in {dt * 1e3:.1f} ms "
+    print(f"two-phase: {len(centres)} ROIs x {len(world['libq'])} references in {dt * 1e3:.1f} ms "
           f"({len(centres) / dt:.0f} indexed ROIs/s); share>=0.9: {good.sum()} ROIs, phase correct "
           f"{phase_ok[good].mean():.3f}, top-1 disorientation median {np.median(dis[m]):.2f} "
           f"p95 {np.percentile(dis[m], 95):.2f} deg", flush=True)
@@ -195,12 +195,12 @@ def test_cfg4_pipeline_accuracy(nat, ctx, orc, world):
     assert np.median(dis[m]) < 5.0
 
 
-def test_cfg5_adjoint_parity_sampled(nat, ctx, orc, world):
-    """Gradient of the structure-factor score of sampled config-5 ROIs at a
+def test_refinement_adjoint_parity_sampled(nat, ctx, orc, world):
+    """Gradient of the structure-factor score of sampled refinement ROIs at a
     seeded orientation 2 deg from the truth, against FP64 central
     differences; the target is the oracle's amplitude image of one reference
     crystal ROI per phase (the same input on both sides)."""
-    centres, qt, pht, share = synth.config5_rois(4096)
+    centres, qt, pht, share = synth.refinement_rois(4096)
     sel = np.sort(np.random.default_rng(50).choice(len(centres), 8, replace=False))
     T64 = []
     for ph in (0, 1):
@@ -227,12 +227,12 @@ def test_cfg5_adjoint_parity_sampled(nat, ctx, orc, world):
     with cf.ThreadPoolExecutor(max_workers=8) as ex:
         fds = list(ex.map(fd, range(len(sel))))
     errs = [np.linalg.norm(grad[a] - g) / np.linalg.norm(g) for a, g in enumerate(fds)]
-    print(f"\ncfg5 adjoint vs FP64 central differences: max relative error {max(errs):.2e}", flush=True)
+    print(f"\nrefinement adjoint vs FP64 central differences: max relative error {max(errs):.2e}", flush=True)
     assert max(errs) <= 1e-3, errs
 
 
-def test_cfg5_refinement_from_top1(nat, ctx, orc, world):
-    centres, qt, pht, share = synth.config5_rois(4096)
+def test_refinement_from_top1(nat, ctx, orc, world):
+    centres, qt, pht, share = synth.refinement_rois(4096)
     off, rel = nat.ar_roi_gather(ctx, world["pos_d"], dev(centres), R)
     S = nat.araullo_signatures_csr(ctx, rel, off, R, world["dirs_d"], NB, world["w"])
     gidx, _ = nat.index_orientations(ctx, S, world["lib"], 16)
@@ -250,7 +250,7 @@ def test_cfg5_refinement_from_top1(nat, ctx, orc, world):
     ok = ph == pht
     d0 = orc.disorientation_cubic(q0.astype(np.float64), qt)[ok]
     d1 = orc.disorientation_cubic(qr, qt)[ok]
-    print(f"cfg5: {len(centres)} ROIs x 50 steps in {dt:.2f} s ({len(centres) * 50 / dt:.0f} ROI-steps/s); "
+    print(f"refinement: {len(centres)} ROIs x 50 steps in {dt:.2f} s ({len(centres) * 50 / dt:.0f} ROI-steps/s); "
           f"phase correct {ok.mean():.3f}; disorientation median {np.median(d0):.2f} -> {np.median(d1):.2f} deg, "
           f"p95 {np.percentile(d0, 95):.2f} -> {np.percentile(d1, 95):.2f} deg", flush=True)
     assert ok.mean() > 0.9

@@ -130,7 +130,7 @@ def test_eq1_hand_placed_atoms(orc):
 
 
 def test_count_conservation_and_gather(orc):
-    s = synth.config1()
+    s = synth.single_roi()
     rel = orc.roi_gather(s.positions, s.centres[0], s.radius)
     # brute force in float64: identical except atoms within 1e-6 nm of the sphere
     r64 = np.linalg.norm(s.positions.astype(np.float64) - s.centres[0].astype(np.float64), axis=1)
@@ -225,7 +225,7 @@ def test_paper_fig2_bin_on_a_crystal(orc):
 
 
 def test_signature_images_are_window_maxima(orc):
-    s = synth.config1()
+    s = synth.single_roi()
     w = orc.windows_for(s.radius, s.nbins, s.spacings)
     dirs = s.directions[:16]
     img, cnt = orc.signatures(s.positions, s.centres, s.radius, dirs, s.nbins, w)
