@@ -15,7 +15,8 @@
 // so the chosen node is the same.
 //
 // One wave per cell; the lists have a fixed capacity, and a cell whose list
-// would exceed it is marked (count -1) and searched over the whole mesh.
+// would exceed it is marked (count -1) and searched over the whole mesh, as
+// is every cell of a mesh whose nodes are not unit vectors.
 #include "ar_internal.h"
 #include "mesh_device.h"
 
@@ -59,14 +60,23 @@ __global__ __launch_bounds__(256) void k_mesh_cells(const float *__restrict__ di
         rc = fmax(rc, acos(fmin(1.0, c[0] * q[0] + c[1] * q[1] + c[2] * q[2])));
     }
     rc += 1e-9;   // rounding of the cell assignment
-    // nearest node to the centre (dot over the node's length)
+    // nearest node to the centre (dot over the node's length); the bounds
+    // assume unit nodes (FP32-rounded), so a mesh with any node off the unit
+    // sphere by more than 1e-5 in |n|^2 is searched in full
     double best = -2.0;
+    bool off_unit = false;
     for (int u = lane; u < n_dir; u += 64) {
         const double x = dirs[3 * u], y = dirs[3 * u + 1], z = dirs[3 * u + 2];
-        best = fmax(best, (c[0] * x + c[1] * y + c[2] * z) / sqrt(x * x + y * y + z * z));
+        const double n2 = x * x + y * y + z * z;
+        off_unit |= !(fabs(n2 - 1.0) <= 1e-5);
+        best = fmax(best, (c[0] * x + c[1] * y + c[2] * z) / sqrt(n2));
     }
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) best = fmax(best, __shfl_xor(best, off));
+    if (__ballot(off_unit) != 0ull) {
+        if (lane == 0) count[cell] = -1;
+        return;
+    }
     const double ac = acos(fmax(-1.0, fmin(1.0, best)));
     const double cmin = cos(fmin(M_PI, rc + ac)) - 2e-5;
     const double rho = acos(fmax(-1.0, cmin - 1e-7));

@@ -141,11 +141,14 @@ def _mesh(kind):
         o = gen.standard_normal((100, 3))
         d = np.concatenate([c, o])
         return (d / np.linalg.norm(d, axis=1, keepdims=True)).astype(np.float32)
+    if kind == "non_unit":                        # nodes off the unit sphere: the full scan is used
+        d = synth.icosphere(2).astype(np.float64)
+        return (d * gen.uniform(0.5, 1.5, (len(d), 1))).astype(np.float32)
     d = synth.icosphere(3)                        # duplicated nodes: exact ties go to the lower index
     return np.concatenate([d, d[::7]]).astype(np.float32)
 
 
-@pytest.mark.parametrize("kind", ["icosphere0", "clustered", "duplicates"])
+@pytest.mark.parametrize("kind", ["icosphere0", "clustered", "duplicates", "non_unit"])
 def test_rotate_reference_nearest_node_edge_meshes(nat, ctx, orc, kind):
     """The reference value of node u is u itself, so the output is the chosen
     node: it must equal the oracle's exhaustive FP32-scan / FP64-re-rank
