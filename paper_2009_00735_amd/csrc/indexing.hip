@@ -448,12 +448,9 @@ ar_status launch_rescore(ar_context *ctx, const float *images, const ar_library 
 {
     const size_t stage = sizeof(float) * (size_t)lib->n_dir;
     if (stage + 4096 <= (size_t)ctx->lds_per_block) {
-        static bool attr_set = false;   // per instantiation
-        if (!attr_set && stage > 65536) {
+        if (stage > 65536)   // on every launch: the attribute belongs to the current device
             AR_HIP(hipFuncSetAttribute((const void *)k_rescore<CAND, true>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)stage));
-            attr_set = true;
-        }
         k_rescore<CAND, true><<<(unsigned)n_roi, 256, stage, s>>>(images, ctx->i_inv.as<float>(), lib->ref,
                                                                   lib->inv_max.as<float>(),
                                                                   ctx->i_merge_idx.as<int32_t>(), lib->n_win,
@@ -507,12 +504,9 @@ ar_status launch_corr_t(ar_context *ctx, const uint16_t *A, const ar_library *li
     const unsigned blocks = (unsigned)(m_blocks * n_seg);
     const size_t lds = S::lds();
     AR_CHECK((size_t)ctx->lds_per_block >= lds, "correlation tile needs %zu bytes of LDS per workgroup", lds);
-    static bool attr_set = false;   // per instantiation
-    if (!attr_set && lds > 65536) {
+    if (lds > 65536)   // on every launch: the attribute belongs to the current device
         AR_HIP(hipFuncSetAttribute((const void *)k_corr_topk<WGM, WGN, WTM, WTN, CAND>,
                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-        attr_set = true;
-    }
     k_corr_topk<WGM, WGN, WTM, WTN, CAND><<<blocks, S::THREADS, lds, s>>>(
         A, lib->bf16.as<uint16_t>(), lib->norm2.as<float>(), lib->Kp, m_blocks, n_tiles, tiles_per_seg, n_seg, L.col0,
         L.list_stride, L.list_base, out_s, out_i);

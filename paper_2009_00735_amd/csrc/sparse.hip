@@ -821,13 +821,12 @@ int pick_screen(const ar_context *ctx, int n_dir, int n_rows)
     return 0;
 }
 
+// Dynamic LDS beyond 64 KB must be allowed per kernel; set on every launch
+// (on the calling context's device, current at this point).
 template <typename K>
-ar_status allow_lds(K kernel, size_t lds, bool &done)
+ar_status allow_lds(K kernel, size_t lds)
 {
-    if (!done && lds > 65536) {
-        AR_HIP(hipFuncSetAttribute((const void *)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-        done = true;
-    }
+    if (lds > 65536) AR_HIP(hipFuncSetAttribute((const void *)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     return AR_OK;
 }
 
@@ -843,8 +842,7 @@ ar_status merge_rescore(ar_context *ctx, const ar_sparse_lut *lut, const float *
     // stage each ROI window in LDS when n_dir floats fit beside the static arrays
     const size_t stage = sizeof(float) * (size_t)lut->n_dir;
     if (stage + 4096 <= (size_t)ctx->lds_per_block) {
-        static bool attr_set = false;   // per instantiation
-        AR_TRY(allow_lds(k_sparse_rescore<CAND, true>, stage, attr_set));
+        AR_TRY(allow_lds(k_sparse_rescore<CAND, true>, stage));
         k_sparse_rescore<CAND, true><<<(unsigned)n_roi, 256, stage, s>>>(
             images, ctx->sp_inv.as<float>(), lut->n_win, lut->n_dir, lut->cseg.as<int32_t>(),
             lut->sval_w.as<float>(), lut->lut_gi.as<uint16_t>(), lut->n_hat, lut->phase_start.as<int64_t>(),
@@ -894,8 +892,7 @@ ar_status run_screen(ar_context *ctx, const ar_sparse_lut *lut, const float *ima
     k_sparse_norm<RB><<<dim3((unsigned)p.n_grp, (unsigned)lut->n_win), 256, 0, s>>>(
         images, n_roi, lut->n_win, lut->n_dir, p.slab / 2, ctx->sp_inv.as<float>(), ctx->sp_half.as<_Float16>());
     AR_HIP(hipGetLastError());
-    static bool attr_set = false;   // per instantiation
-    AR_TRY(allow_lds(k_sparse_screen<RB, CAND>, p.lds, attr_set));
+    AR_TRY(allow_lds(k_sparse_screen<RB, CAND>, p.lds));
     k_sparse_screen<RB, CAND><<<(unsigned)p.blocks, kThreads, p.lds, s>>>(
         ctx->sp_half.as<_Float16>(), lut->n_win, p.slab / 2, lut->lut_ig.as<uint16_t>(), lut->ld,
         lut->kval2.as<uint32_t>(), lut->seg.as<int32_t>(), lut->n_rows, lut->chunks.as<int4>(), lut->n_chunks,
@@ -917,8 +914,7 @@ ar_status run_screen8(ar_context *ctx, const ar_sparse_lut *lut, const float *im
     k_sparse_norm8<<<dim3((unsigned)p.n_grp, (unsigned)lut->n_win), 256, 0, s>>>(
         images, n_roi, lut->n_win, lut->n_dir, p.slab, ctx->sp_inv.as<float>(), ctx->sp_half.as<uint32_t>());
     AR_HIP(hipGetLastError());
-    static bool attr_set = false;   // per instantiation
-    AR_TRY(allow_lds(k_sparse_screen8<CAND>, p.lds, attr_set));
+    AR_TRY(allow_lds(k_sparse_screen8<CAND>, p.lds));
     k_sparse_screen8<CAND><<<(unsigned)p.blocks, kThreads, p.lds, s>>>(
         ctx->sp_half.as<uint32_t>(), lut->n_win, p.slab, lut->lut_ig.as<uint16_t>(), lut->ld,
         lut->kq8.as<uint32_t>(), lut->q2sum.as<uint32_t>(), lut->seg.as<int32_t>(), lut->n_rows,
