@@ -15,7 +15,7 @@ One step = the whole hot path over that batch, inputs resident in HBM:
   a10     50-step structure-factor refinement of the top-1 orientation
           (ar_refine_orientations)
 
-Prints one JSON line.  `--gpus N` with N > 1 exits: this build targets one GPU.
+Prints one JSON line.  `--gpus N` with N > 1 exits: the benchmark measures one GPU.
 """
 from __future__ import annotations
 
@@ -91,8 +91,9 @@ def cpu_info():
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); this build has no multi-GPU path. "
-              "See DESIGN.md for how the ROI and library axes would shard.", file=sys.stderr)
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the library has no multi-GPU path. "
+              "ROIs would shard across GPUs with no exchange; a sharded library would need one all-gather of "
+              "the per-GPU top-k candidates.", file=sys.stderr)
         sys.exit(2)
 
     import torch
