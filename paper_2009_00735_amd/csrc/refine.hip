@@ -96,14 +96,19 @@ __global__ __launch_bounds__(kTile) void k_sf(const float4 *__restrict__ rel, co
                                               const float *__restrict__ quats, const int32_t *__restrict__ phase,
                                               const float *__restrict__ dirs, int n_dir, const int32_t *__restrict__ rep,
                                               const int32_t *__restrict__ mate, const int32_t *__restrict__ n_eval_p,
-                                              int n_tiles,
+                                              int n_tiles, int64_t n_roi,
                                               const float *__restrict__ freqs, const float *__restrict__ targets,
                                               float *__restrict__ partials, float *__restrict__ amp)
 {
     __shared__ float4 xs[kChunk];
     __shared__ float red[kPartial][kTile / 64];
-    const int64_t r = blockIdx.x / n_tiles;
-    const int tile = blockIdx.x - (int)(r * n_tiles);
+    // XCD-aware order: workgroup ids go round-robin to the 8 XCDs; item t =
+    // (b % 8) * (grid / 8) + b / 8 keeps the tiles of one ROI on one XCD, so
+    // its atoms come from HBM into that XCD's L2 once (grid padded to 8)
+    const int64_t t = (int64_t)(blockIdx.x & 7) * (gridDim.x >> 3) + (blockIdx.x >> 3);
+    if (t >= n_roi * n_tiles) return;
+    const int64_t r = t / n_tiles;
+    const int tile = (int)(t - r * n_tiles);
     const int n_eval = *n_eval_p;
     if (tile * kTile >= n_eval) {       // tiles past the evaluation list: nothing to add
         if (MODE != 2 && threadIdx.x < kPartial) partials[((size_t)r * n_tiles + tile) * kPartial + threadIdx.x] = 0.f;
@@ -561,13 +566,16 @@ static ar_status sf_check(ar_context *ctx, const float *rel, const int64_t *offs
     AR_CHECK(n_roi >= 1 && n_dir >= 1 && n_phase >= 1, "sizes must be >= 1");
     AR_CHECK(n_freq >= 1 && n_freq <= sf::kMaxFreq, "n_freq must be in [1, %d]", sf::kMaxFreq);
     const int64_t tiles = (n_dir + sf::kTile - 1) / sf::kTile;
-    AR_CHECK(n_roi * tiles < (int64_t)INT32_MAX, "too many workgroups");
+    AR_CHECK(n_roi * tiles + 7 < (int64_t)INT32_MAX, "too many workgroups");
     return AR_OK;
 }
 
 using SfFn = void (*)(const float4 *, const int64_t *, const float *, const int32_t *, const float *, int,
-                     const int32_t *, const int32_t *, const int32_t *, int, const float *, const float *, float *,
-                     float *);
+                     const int32_t *, const int32_t *, const int32_t *, int, int64_t, const float *, const float *,
+                     float *, float *);
+using SfRemFn = void (*)(const float4 *, const int64_t *, const float *, const int32_t *, const float *, int,
+                        const int32_t *, const int32_t *, const int32_t *, int, const float *, const float *, float *,
+                        float *);
 
 // Device evaluation list for `dirs` in ctx workspace: rep, mate [n_dir], n_eval.
 static ar_status eval_list(ar_context *ctx, const float *dirs, int32_t n_dir, const int32_t **rep,
@@ -600,7 +608,7 @@ template <int MODE> SfFn sf_kernel(int n_freq)
     }
 }
 
-template <int MODE> SfFn sf_rem_kernel(int n_freq)
+template <int MODE> SfRemFn sf_rem_kernel(int n_freq)
 {
     switch (n_freq) {
     case 1: return sf::k_sf_rem<MODE, 1>;
@@ -626,10 +634,11 @@ static ar_status sf_launch(ar_context *ctx, int mode, const float *rel, const in
     const int32_t *base = ctx->r_dirs.as<int32_t>();
     const int32_t *rep = base + n_dir, *mate = base + 2 * n_dir, *n_eval = base + 3 * n_dir;
     const int n_tiles = (n_dir + sf::kTile - 1) / sf::kTile;
-    const unsigned blocks = (unsigned)(n_roi * n_tiles);
+    const unsigned blocks = (unsigned)((n_roi * n_tiles + 7) / 8 * 8);   // k_sf: a multiple of the 8 XCDs
     if (mode == 2) {
         sf_kernel<2>(n_freq)<<<blocks, sf::kTile, 0, s>>>((const float4 *)rel, offsets, quats, phase, dirs, n_dir,
-                                                          rep, mate, n_eval, n_tiles, freqs, targets, nullptr, amp);
+                                                          rep, mate, n_eval, n_tiles, n_roi, freqs, targets, nullptr,
+                                                          amp);
         AR_HIP(hipGetLastError());
         sf_rem_kernel<2>(n_freq)<<<(unsigned)n_roi, sf::kTile, 0, s>>>((const float4 *)rel, offsets, quats, phase,
                                                                        dirs, n_dir, rep, mate, n_eval, n_tiles,
@@ -641,9 +650,9 @@ static ar_status sf_launch(ar_context *ctx, int mode, const float *rel, const in
     float *part = ctx->r_partials.as<float>();
     SfFn fn = mode == 1 ? sf_kernel<1>(n_freq) : sf_kernel<0>(n_freq);
     fn<<<blocks, sf::kTile, 0, s>>>((const float4 *)rel, offsets, quats, phase, dirs, n_dir, rep, mate, n_eval,
-                                    n_tiles, freqs, targets, part, nullptr);
+                                    n_tiles, n_roi, freqs, targets, part, nullptr);
     AR_HIP(hipGetLastError());
-    SfFn fr = mode == 1 ? sf_rem_kernel<1>(n_freq) : sf_rem_kernel<0>(n_freq);
+    SfRemFn fr = mode == 1 ? sf_rem_kernel<1>(n_freq) : sf_rem_kernel<0>(n_freq);
     fr<<<(unsigned)n_roi, sf::kTile, 0, s>>>((const float4 *)rel, offsets, quats, phase, dirs, n_dir, rep, mate,
                                              n_eval, n_tiles, freqs, targets, part, nullptr);
     AR_HIP(hipGetLastError());
