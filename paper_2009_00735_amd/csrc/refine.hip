@@ -85,6 +85,39 @@ __device__ __forceinline__ void sf_direction(const float (&C)[NF], const float (
 
 constexpr int kRemAtoms = 16;   // a last tile with fewer directions runs atom-parallel
 
+__device__ __forceinline__ void swap_acc(float &a, float &b)
+{
+    const float t = a;
+    a = b;
+    b = t;
+}
+
+// One atom's terms for one direction: the phases in turns, their sin and
+// cos, and the C, S, P, Q sums.  (ax, ay, az) = f_kb u, so the dot product
+// is slot 0's phase; slot w's is g_w = f / f_kb times it.
+template <int MODE, int NF>
+__device__ __forceinline__ void sf_term(const float4 x, float ax, float ay, float az, const float (&g)[NF],
+                                        float (&C)[NF], float (&S)[NF], float (&P)[NF][3], float (&Q)[NF][3])
+{
+    const float d = fmaf(az, x.z, fmaf(ay, x.y, ax * x.x));
+#pragma unroll
+    for (int w = 0; w < NF; ++w) {
+        const float t = w == 0 ? d : g[w] * d;   // phase in turns
+        const float sn = __builtin_amdgcn_sinf(t);
+        const float cs = __builtin_amdgcn_cosf(t);
+        C[w] += cs;
+        S[w] += sn;
+        if (MODE == 1) {
+            P[w][0] = fmaf(x.x, sn, P[w][0]);
+            P[w][1] = fmaf(x.y, sn, P[w][1]);
+            P[w][2] = fmaf(x.z, sn, P[w][2]);
+            Q[w][0] = fmaf(x.x, cs, Q[w][0]);
+            Q[w][1] = fmaf(x.y, cs, Q[w][1]);
+            Q[w][2] = fmaf(x.z, cs, Q[w][2]);
+        }
+    }
+}
+
 // MODE 0: score partials; MODE 1: score + gradient partials; MODE 2: amplitudes.
 // NF: number of frequencies (compile-time so the accumulators stay in VGPRs).
 // A last tile with fewer than kRemAtoms directions (e.g. the one direction
@@ -134,6 +167,25 @@ __global__ __launch_bounds__(kTile) void k_sf(const float4 *__restrict__ rel, co
     float f[NF];
 #pragma unroll
     for (int w = 0; w < NF; ++w) f[w] = freqs[p * NF + w];
+    // phases: the loop puts the frequency of largest |f| (index kb) in slot
+    // 0 and forms its phase as one dot product with f_kb u; every other slot
+    // w takes (f / f_kb) times it, one multiply per atom fewer than f (u . x)
+    // per frequency, and |f / f_kb| <= 1 cannot overflow.  Slots 0 and kb
+    // hold frequencies kb and 0; the sums go back to frequency order after
+    // the loop.  All-zero frequencies give zero phases (g = 0, f_kb u = 0).
+    int kb = 0;
+#pragma unroll
+    for (int w = 1; w < NF; ++w)
+        if (fabsf(f[w]) > fabsf(f[kb])) kb = w;
+    const float fb = f[kb];
+    float g[NF];
+#pragma unroll
+    for (int w = 0; w < NF; ++w) {   // uniform over the workgroup: scalar registers
+        const float fw = w == 0 ? fb : (w == kb ? f[0] : f[w]);
+        const float gw = fb != 0.f ? fw / fb : 0.f;
+        g[w] = __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, gw)));
+    }
+    const float ax = fb * ux, ay = fb * uy, az = fb * uz;
     float C[NF], S[NF], P[NF][3], Q[NF][3];
 #pragma unroll
     for (int w = 0; w < NF; ++w) {
@@ -152,25 +204,23 @@ __global__ __launch_bounds__(kTile) void k_sf(const float4 *__restrict__ rel, co
         __syncthreads();
         for (int i = threadIdx.x; i < nc; i += kTile) xs[i] = rel[off0 + c0 + i];
         __syncthreads();
-        const int n_run = wave_busy ? nc : 0;
-        for (int j = 0; j < n_run; ++j) {
-            const float4 x = xs[j];
-            const float s = fmaf(uz, x.z, fmaf(uy, x.y, ux * x.x));
+        const int n_run = __builtin_amdgcn_readfirstlane(wave_busy ? nc : 0);
+        // one atom per iteration: its 2 NF transcendentals issue as one
+        // group ahead of their consumers.  Unrolled by 2 (the compiler's
+        // choice) or 4 the groups double and quadruple, which measured 1 %
+        // and 8 % slower; interleaving each sin/cos with its consumers, 7 %.
+#pragma unroll 1
+        for (int j = 0; j < n_run; ++j) sf_term<MODE, NF>(xs[j], ax, ay, az, g, C, S, P, Q);
+    }
 #pragma unroll
-            for (int w = 0; w < NF; ++w) {
-                const float t = f[w] * s;   // phase in turns
-                const float sn = __builtin_amdgcn_sinf(t);
-                const float cs = __builtin_amdgcn_cosf(t);
-                C[w] += cs;
-                S[w] += sn;
-                if (MODE == 1) {
-                    P[w][0] = fmaf(x.x, sn, P[w][0]);
-                    P[w][1] = fmaf(x.y, sn, P[w][1]);
-                    P[w][2] = fmaf(x.z, sn, P[w][2]);
-                    Q[w][0] = fmaf(x.x, cs, Q[w][0]);
-                    Q[w][1] = fmaf(x.y, cs, Q[w][1]);
-                    Q[w][2] = fmaf(x.z, cs, Q[w][2]);
-                }
+    for (int w = 1; w < NF; ++w) {   // slots back to frequency order
+        if (w == kb) {
+            swap_acc(C[0], C[w]);
+            swap_acc(S[0], S[w]);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                swap_acc(P[0][c], P[w][c]);
+                swap_acc(Q[0][c], Q[w][c]);
             }
         }
     }

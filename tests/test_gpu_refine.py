@@ -195,3 +195,40 @@ def test_unpaired_and_mixed_directions(nat, ctx, orc):
         assert abs(float(score[0]) - j) <= 1e-5 * j
         fd = orc.sf_grad_fd(rel, q64, dirs, F_AL, T.astype(np.float64))
         assert np.linalg.norm(g[0].cpu().numpy() - fd) <= 1e-3 * np.linalg.norm(fd)
+
+
+@pytest.mark.parametrize("freqs", [(8.1892, 4.2767, 6.9838, 4.9383), (4.2767, 0.0, 8.1892, -6.9838),
+                                   (4.9383, 8.1892, 4.2767), (0.0, 0.0, 0.0, 0.0), (-5.0,)])
+def test_frequency_sets(nat, ctx, orc, freqs):
+    """The kernel forms the phase of the largest |f| from the dot product and
+    the others by the ratio f / f_max: any order, zero and negative
+    frequencies, another count, and all-zero frequencies (A = 1, no
+    gradient) match the FP64 oracle; 81 evaluated directions run in the
+    lane-per-direction kernel, 10 unpaired ones in the short-tile kernel."""
+    f = np.array(freqs, np.float64)
+    gen = np.random.default_rng(21)
+    extra = gen.normal(size=(10, 3))
+    extra = (extra / np.linalg.norm(extra, axis=1, keepdims=True)).astype(np.float32)
+    for dirs in (synth.icosphere(2), extra):
+        dirs = np.ascontiguousarray(dirs)
+        p = synth.lattice_in_ball("fcc", 0.405, synth.random_orientations(1, 23)[0], gen.random(3), np.zeros(3), 2.5)
+        rel = orc.roi_gather(p.astype(np.float32), np.zeros(3, np.float32), 2.0)
+        T = gen.random((len(f), len(dirs))).astype(np.float32) * 0.3
+        rel4 = np.zeros((len(rel), 4), np.float32)
+        rel4[:, :3] = rel
+        q = synth.random_orientations(1, 24).astype(np.float32)
+        args = (dev(rel4), dev(np.array([0, len(rel)]), torch.int64), dev(q), dev(np.zeros(1, np.int32), torch.int32),
+                dev(dirs), dev(f[None]))
+        q64 = q[0].astype(np.float64)
+        f32 = f.astype(np.float32).astype(np.float64)      # the frequencies both sides see
+        amp = nat.ar_sf_amplitudes(ctx, *args).cpu().numpy()[0]
+        assert np.max(np.abs(amp - orc.sf_amplitudes(rel, q64, dirs, f32))) <= 1e-5
+        score, g = nat.ar_sf_score_grad(ctx, *args, dev(T[None]))
+        j = orc.sf_score(rel, q64, dirs, f32, T.astype(np.float64))
+        assert abs(float(score[0]) - j) <= 1e-5 * j
+        g = g[0].cpu().numpy()
+        if not f.any():
+            assert np.allclose(amp, 1.0, rtol=0, atol=1e-6) and np.allclose(g, 0.0, rtol=0, atol=1e-6)
+        else:
+            fd = orc.sf_grad_fd(rel, q64, dirs, f32, T.astype(np.float64))
+            assert np.linalg.norm(g - fd) <= 1e-3 * np.linalg.norm(fd)
