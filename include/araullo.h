@@ -435,8 +435,10 @@ ar_status ar_sf_amplitudes(ar_context *ctx, const float *rel, const int64_t *off
  * projected gradient descent on J (ar_sf_score_grad) with a per-ROI
  * backtracking step along the normalised gradient: a trial
  * q' = normalise(q - a g/|g|) is accepted iff J(q') <= J(q) - 1e-4 a |g|,
- * then a grows by 1.5; otherwise a halves and q stays.  Every iteration
- * evaluates J and its gradient once, at the trial points of all ROIs.
+ * then a grows by 1.5; otherwise a halves and q stays.  steps + 1
+ * evaluations at the trial points of all ROIs (the first at the start):
+ * J and its gradient, except the last, which only decides acceptance and
+ * takes J alone.
  *   quats  device float [n_roi][4], in: start, out: refined
  *   a0     starting step (quaternion arc length, e.g. 0.01)
  *   score  device float [n_roi] or NULL, out: final J

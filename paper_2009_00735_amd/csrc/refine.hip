@@ -552,7 +552,10 @@ struct RefineState {
 };
 
 // Evaluations happen at the trial quaternions `trial`.  Step 0 only
-// initialises the state from the first evaluation.
+// initialises the state from the first evaluation.  gt == nullptr: the
+// evaluation took the score alone (the last one, whose gradient would only
+// feed a trial that is never evaluated); an accepted trial then keeps the
+// previous gradient, or zero at step 0.
 __global__ __launch_bounds__(256) void k_refine_update(RefineState *__restrict__ st, float *__restrict__ trial,
                                                        const float *__restrict__ Jt, const float *__restrict__ gt,
                                                        int64_t n_roi, int first, float a0)
@@ -563,7 +566,7 @@ __global__ __launch_bounds__(256) void k_refine_update(RefineState *__restrict__
     if (first) {
         for (int i = 0; i < 4; ++i) {
             s.q[i] = trial[4 * r + i];
-            s.g[i] = gt[4 * r + i];
+            s.g[i] = gt ? gt[4 * r + i] : 0.f;
         }
         s.J = Jt[r];
         s.a = a0;
@@ -572,7 +575,7 @@ __global__ __launch_bounds__(256) void k_refine_update(RefineState *__restrict__
         if (Jt[r] <= s.J - 1e-4f * s.a * gn) {
             for (int i = 0; i < 4; ++i) {
                 s.q[i] = trial[4 * r + i];
-                s.g[i] = gt[4 * r + i];
+                if (gt) s.g[i] = gt[4 * r + i];
             }
             s.J = Jt[r];
             s.a *= 1.5f;
@@ -786,9 +789,12 @@ ar_status ar_refine_orientations(ar_context *ctx, const float *rel, const int64_
         AR_TRY(ar::eval_list(ctx, directions, n_dir, &a, &b, &c, s));
     }
     for (int it = 0; it <= steps; ++it) {
-        AR_TRY(ar::sf_launch(ctx, 1, rel, offsets, n_roi, trial, phase, directions, n_dir, freqs, targets, n_freq, Jt,
-                             gt, nullptr, s, true));
-        ar::sf::k_refine_update<<<nb, 256, 0, s>>>(st, trial, Jt, gt, n_roi, it == 0 ? 1 : 0, a0);
+        // the last evaluation only decides whether its trial is accepted:
+        // score alone (the forward kernel, about half the adjoint's work)
+        const bool last = it == steps;
+        AR_TRY(ar::sf_launch(ctx, last ? 0 : 1, rel, offsets, n_roi, trial, phase, directions, n_dir, freqs, targets,
+                             n_freq, Jt, gt, nullptr, s, true));
+        ar::sf::k_refine_update<<<nb, 256, 0, s>>>(st, trial, Jt, last ? nullptr : gt, n_roi, it == 0 ? 1 : 0, a0);
         AR_HIP(hipGetLastError());
     }
     ar::sf::k_refine_finish<<<nb, 256, 0, s>>>(st, n_roi, quats, score);

@@ -232,3 +232,42 @@ def test_frequency_sets(nat, ctx, orc, freqs):
         else:
             fd = orc.sf_grad_fd(rel, q64, dirs, f32, T.astype(np.float64))
             assert np.linalg.norm(g - fd) <= 1e-3 * np.linalg.norm(fd)
+
+
+def test_refinement_zero_and_one_step(nat, ctx, orc):
+    """The update rule on its first steps, against host arithmetic on the
+    score and gradient entry point.  steps = 0: one score-only evaluation,
+    quaternions unchanged, score J(q0).  steps = 1: one adjoint evaluation at
+    q0 and a score-only one at q1 = normalise(q0 - a0 g/|g|); q1 is kept iff
+    J(q1) <= J(q0) - 1e-4 a0 |g| (a small step that is kept, a large one that
+    is refused)."""
+    dirs, T, rels, offsets, rel4, q0, qt = make_case(orc, 3, 3, seed=13)
+    rel, off, ph, d, f, t = gpu_args(dirs, T, offsets, rel4, 3)
+    q0 = q0.astype(np.float32)
+    J0, g0 = nat.ar_sf_score_grad(ctx, rel, off, dev(q0), ph, d, f, t, grad=True)
+    J0s, _ = nat.ar_sf_score_grad(ctx, rel, off, dev(q0), ph, d, f, t, grad=False)
+    J0, J0s, g0 = J0.cpu().numpy(), J0s.cpu().numpy(), g0.cpu().numpy().astype(np.float64)
+    assert np.allclose(J0s, J0, rtol=1e-6, atol=0)
+
+    q = dev(q0)
+    score = nat.ar_refine_orientations(ctx, rel, off, q, ph, d, f, t, steps=0, a0=0.01).cpu().numpy()
+    assert np.array_equal(q.cpu().numpy(), q0)
+    assert np.array_equal(score, J0s)                     # the same score-only kernels
+
+    for a0, kept in ((0.002, True), (1.5, False)):
+        gn = np.linalg.norm(g0, axis=1, keepdims=True)
+        q1 = q0 - a0 * g0 / gn
+        q1 /= np.linalg.norm(q1, axis=1, keepdims=True)
+        J1, _ = nat.ar_sf_score_grad(ctx, rel, off, dev(q1), ph, d, f, t, grad=False)
+        J1 = J1.cpu().numpy()
+        accept = J1 <= J0 - 1e-4 * a0 * gn[:, 0]
+        assert np.all(accept == kept), (a0, J0, J1)
+        q = dev(q0)
+        score = nat.ar_refine_orientations(ctx, rel, off, q, ph, d, f, t, steps=1, a0=a0).cpu().numpy()
+        qr = q.cpu().numpy()
+        if kept:
+            assert np.allclose(qr, q1, rtol=0, atol=2e-6), (qr, q1)
+            assert np.allclose(score, J1, rtol=1e-5, atol=0)
+        else:
+            assert np.array_equal(qr, q0)
+            assert np.array_equal(score, J0)
