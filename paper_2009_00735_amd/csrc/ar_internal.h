@@ -79,8 +79,10 @@ struct ar_context {
     ar::DeviceBuffer s_rel;
     // one channel's images in the typed-signature entry point
     ar::DeviceBuffer s_typed;
-    // correlation tile: per-wave 32x32 MFMA tiles (wtm x wtn) and K step
+    // correlation tile: per-wave 32x32 MFMA tiles (wtm x wtn) and K step; used
+    // when set by ar_index_set_tile, else chosen per candidate count
     int corr_waves = 8, corr_wtm = 4, corr_wtn = 2, corr_bk = 32;
+    bool corr_tile_set = false;
     // indexing workspace
     ar::DeviceBuffer i_bf16, i_inv, i_cand_idx, i_cand_score, i_merge_idx;
     // sparse indexing workspace

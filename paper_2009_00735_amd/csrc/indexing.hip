@@ -622,7 +622,13 @@ ar_status index_orientations_ex(ar_context *ctx, const float *images, int64_t n_
     AR_CHECK(lib->ctx == ctx, "library belongs to another context");
     AR_HIP(hipSetDevice(ctx->device));
     hipStream_t s = (hipStream_t)stream;
-    const idx::CorrCfg cfg{ctx->corr_waves, ctx->corr_wtm, ctx->corr_wtn, ctx->corr_bk};
+    // Default tile: 256 x 256 (8 waves of 4 x 2 MFMA tiles).  With 32
+    // candidates the per-thread lists no longer fit beside its accumulators
+    // and spill to scratch, so cand = 32 takes 128 x 256 (8 waves of 2 x 2):
+    // 6.8 against 8.4 ms at 2000 x 20000 x 40968, identical results.
+    const idx::CorrCfg cfg = ctx->corr_tile_set ? idx::CorrCfg{ctx->corr_waves, ctx->corr_wtm, ctx->corr_wtn, ctx->corr_bk}
+                             : cand == 32 ? idx::CorrCfg{8, 2, 2, idx::kBK}
+                                          : idx::CorrCfg{8, 4, 2, idx::kBK};
     const int64_t m_pad = idx::round_up(n_roi, idx::kPadM);
     const int m_blocks = (int)(m_pad / cfg.bm());
     const int n_tiles = (int)(lib->n_pad / cfg.bn());
@@ -733,12 +739,17 @@ ar_status index_orientations_ex(ar_context *ctx, const float *images, int64_t n_
 ar_status ar_index_set_tile(ar_context *ctx, int32_t waves, int32_t wtm, int32_t wtn, int32_t bk)
 {
     AR_CHECK(ctx != nullptr, "context is NULL");
+    if (waves == 0 && wtm == 0 && wtn == 0 && bk == 0) {   // back to the default choice per candidate count
+        ctx->corr_tile_set = false;
+        return AR_OK;
+    }
     AR_CHECK(idx::corr_tile_supported(waves, wtm, wtn, bk), "unsupported correlation tile %d waves %dx%dx%d", waves,
              wtm, wtn, bk);
     ctx->corr_waves = waves;
     ctx->corr_wtm = wtm;
     ctx->corr_wtn = wtn;
     ctx->corr_bk = bk;
+    ctx->corr_tile_set = true;
     return AR_OK;
 }
 

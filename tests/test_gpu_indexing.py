@@ -214,19 +214,29 @@ def test_index_invalid_arguments(nat, ctx):
         nat.index_orientations_ex(ctx, dev(S), lib, 4, 20)
 
 
-@pytest.mark.parametrize("tile", [(4, 2, 2, 32), (4, 2, 4, 32), (4, 4, 2, 32), (8, 2, 2, 32), (8, 4, 2, 32)])
+@pytest.mark.parametrize("tile", [(4, 2, 2, 32), (4, 2, 4, 32), (4, 4, 2, 32), (8, 2, 2, 32), (8, 4, 2, 32),
+                                  (0, 0, 0, 0)])
 def test_every_correlation_tile_gives_identical_results(nat, ctx, tile):
     """Each score accumulates K in the same order whatever the workgroup
-    tile, so candidates, indices and FP32 scores are bit-identical."""
+    tile, so candidates, indices and FP32 scores are bit-identical, with 16
+    and with 32 candidates; (0, 0, 0, 0) is the default choice per candidate
+    count."""
     S, L, truth = synth.planted_images(333, 1500, 4, 300, seed=21)
     lib = nat.Library(ctx, dev(L))
-    nat.ar_index_set_tile(ctx, 4, 2, 2, 32)
     try:
-        ref = nat.index_orientations_ex(ctx, dev(S), lib, 16, 16)
-        nat.ar_index_set_tile(ctx, *tile)
-        got = nat.index_orientations_ex(ctx, dev(S), lib, 16, 16)
+        for cand in (16, 32):
+            nat.ar_index_set_tile(ctx, 4, 2, 2, 32)
+            ref = nat.index_orientations_ex(ctx, dev(S), lib, cand, cand)
+            nat.ar_index_set_tile(ctx, *tile)
+            got = nat.index_orientations_ex(ctx, dev(S), lib, cand, cand)
+            for a, b in zip(ref, got):
+                assert torch.equal(a, b)
+            assert np.array_equal(got[0][:, 0].cpu().numpy(), truth)
     finally:
-        nat.ar_index_set_tile(ctx, 8, 4, 2, 32)
-    for a, b in zip(ref, got):
-        assert torch.equal(a, b)
-    assert np.array_equal(got[0][:, 0].cpu().numpy(), truth)
+        nat.ar_index_set_tile(ctx, 0, 0, 0, 0)
+
+
+def test_index_set_tile_rejects_unsupported(nat, ctx):
+    for tile in [(8, 4, 4, 32), (4, 2, 2, 16), (2, 2, 2, 32), (0, 0, 0, 32)]:
+        with pytest.raises(nat.AraulloError):
+            nat.ar_index_set_tile(ctx, *tile)
