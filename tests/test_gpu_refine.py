@@ -198,12 +198,13 @@ def test_unpaired_and_mixed_directions(nat, ctx, orc):
 
 
 @pytest.mark.parametrize("freqs", [(8.1892, 4.2767, 6.9838, 4.9383), (4.2767, 0.0, 8.1892, -6.9838),
-                                   (4.9383, 8.1892, 4.2767), (0.0, 0.0, 0.0, 0.0), (-5.0,)])
+                                   (4.9383, 8.1892, 4.2767), (0.0, 0.0, 0.0, 0.0), (-5.0,),
+                                   (3.0, -7.0, 2.0, 5.0, 1.0, 4.0), (2.0, 3.0, 4.5, 1.0, 0.5, 6.0, 2.5, 7.5)])
 def test_frequency_sets(nat, ctx, orc, freqs):
     """The kernel forms the phase of the largest |f| from the dot product and
     the others by the ratio f / f_max: any order, zero and negative
-    frequencies, another count, and all-zero frequencies (A = 1, no
-    gradient) match the FP64 oracle; 81 evaluated directions run in the
+    frequencies, other counts (1, 3, 6 and the maximum 8), and all-zero
+    frequencies (A = 1, no gradient) match the FP64 oracle; 81 evaluated directions run in the
     lane-per-direction kernel, 10 unpaired ones in the short-tile kernel."""
     f = np.array(freqs, np.float64)
     gen = np.random.default_rng(21)
