@@ -205,12 +205,30 @@ __global__ __launch_bounds__(kTile) void k_sf(const float4 *__restrict__ rel, co
         for (int i = threadIdx.x; i < nc; i += kTile) xs[i] = rel[off0 + c0 + i];
         __syncthreads();
         const int n_run = __builtin_amdgcn_readfirstlane(wave_busy ? nc : 0);
-        // one atom per iteration: its 2 NF transcendentals issue as one
-        // group ahead of their consumers.  Unrolled by 2 (the compiler's
-        // choice) or 4 the groups double and quadruple, which measured 1 %
-        // and 8 % slower; interleaving each sin/cos with its consumers, 7 %.
+        // Two atoms per iteration with the schedule shaped by scheduling
+        // groups (masks: 0x100 LDS read, 0x2 VALU, 0x400 transcendental):
+        // both LDS reads, then per atom the dot product, a sin/cos pair,
+        // the ratio multiplies, the other transcendentals and the 32
+        // accumulations.  Measured against one atom per iteration (the
+        // best unshaped form): 4 % faster.  Shapes that interleave each
+        // sin/cos pair with accumulations, or take four atoms, measured 8 %
+        // and 5 % slower than one atom per iteration.
+        int j = 0;
 #pragma unroll 1
-        for (int j = 0; j < n_run; ++j) sf_term<MODE, NF>(xs[j], ax, ay, az, g, C, S, P, Q);
+        for (; j + 1 < n_run; j += 2) {
+            sf_term<MODE, NF>(xs[j], ax, ay, az, g, C, S, P, Q);
+            sf_term<MODE, NF>(xs[j + 1], ax, ay, az, g, C, S, P, Q);
+            __builtin_amdgcn_sched_group_barrier(0x100, 2, 0);
+#pragma unroll
+            for (int a = 0; a < 2; ++a) {
+                __builtin_amdgcn_sched_group_barrier(0x2, 3, 0);
+                __builtin_amdgcn_sched_group_barrier(0x400, 2, 0);
+                __builtin_amdgcn_sched_group_barrier(0x2, 3, 0);
+                __builtin_amdgcn_sched_group_barrier(0x400, 6, 0);
+                __builtin_amdgcn_sched_group_barrier(0x2, 32, 0);
+            }
+        }
+        if (j < n_run) sf_term<MODE, NF>(xs[j], ax, ay, az, g, C, S, P, Q);
     }
 #pragma unroll
     for (int w = 1; w < NF; ++w) {   // slots back to frequency order
