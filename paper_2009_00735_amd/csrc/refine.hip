@@ -208,11 +208,13 @@ __global__ __launch_bounds__(kTile) void k_sf(const float4 *__restrict__ rel, co
         // Two atoms per iteration with the schedule shaped by scheduling
         // groups (masks: 0x100 LDS read, 0x2 VALU, 0x400 transcendental):
         // both LDS reads, then per atom the dot product, a sin/cos pair,
-        // the ratio multiplies, the other transcendentals and the 32
-        // accumulations.  Measured against one atom per iteration (the
-        // best unshaped form): 4 % faster.  Shapes that interleave each
-        // sin/cos pair with accumulations, or take four atoms, measured 8 %
-        // and 5 % slower than one atom per iteration.
+        // the NF - 1 ratio multiplies, the other transcendentals and the
+        // accumulations (8 NF with the gradient, else 2 NF).  Measured at
+        // NF = 4 with the gradient against one atom per iteration (the best
+        // unshaped form): 4 % faster.  Shapes that interleave each sin/cos
+        // pair with accumulations, or take four atoms, measured 8 % and 5 %
+        // slower than one atom per iteration.
+        constexpr int kAcc = MODE == 1 ? 8 * NF : 2 * NF;
         int j = 0;
 #pragma unroll 1
         for (; j + 1 < n_run; j += 2) {
@@ -223,9 +225,11 @@ __global__ __launch_bounds__(kTile) void k_sf(const float4 *__restrict__ rel, co
             for (int a = 0; a < 2; ++a) {
                 __builtin_amdgcn_sched_group_barrier(0x2, 3, 0);
                 __builtin_amdgcn_sched_group_barrier(0x400, 2, 0);
-                __builtin_amdgcn_sched_group_barrier(0x2, 3, 0);
-                __builtin_amdgcn_sched_group_barrier(0x400, 6, 0);
-                __builtin_amdgcn_sched_group_barrier(0x2, 32, 0);
+                if (NF > 1) {
+                    __builtin_amdgcn_sched_group_barrier(0x2, NF - 1, 0);
+                    __builtin_amdgcn_sched_group_barrier(0x400, 2 * NF - 2, 0);
+                }
+                __builtin_amdgcn_sched_group_barrier(0x2, kAcc, 0);
             }
         }
         if (j < n_run) sf_term<MODE, NF>(xs[j], ax, ay, az, g, C, S, P, Q);
