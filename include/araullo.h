@@ -344,7 +344,7 @@ ar_status ar_fsp_amplitudes(ar_context *ctx, const float *rel, const int64_t *of
                             int32_t L, float k_max, float *amp, void *stream);
 
 /*
- * Adaptive ROI-grid refinement (Sec. 3.4, aluminium bicrystal: a coarse
+ * Adaptive ROI-grid refinement (Sec. 3.5, aluminium bicrystal: a coarse
  * cubic ROI grid, then a local octree-like refinement where the signal is
  * strong; supplement, local grid refinement).  Coarse ROI r has atom count
  * counts[r] = N_r and images img[r][w][v]; its intensity in window w is

@@ -35,7 +35,8 @@
  *      bin b = floor(f L) for a reciprocal spacing f; supplement,
  *      reconstruction parameters: the 1.823-2.230 A interval).
  *  R6  image value = maximum amplitude inside the window (supplement,
- *      reconstruction parameters: "highest amplitude ... in the bin interval").
+ *      reconstruction parameters: the strongest amplitude among the window's
+ *      bins is kept).
  *  R7  normalisation = division by the image maximum over the directions,
  *      all-zero images stay zero (Sec. 2.4 and supplement "Indexing
  *      algorithm": images normalised individually).
@@ -73,12 +74,13 @@
  *      c - L/2) * dk, dk = 2 k_max / L, a, b, c in [0, L) (k in cycles per
  *      length unit, the origin on the grid).  The paper's k in [-2 pi, 2 pi]^3
  *      is read as 2 pi k with |k| <= 1 per Angstrom, i.e. k_max = 10 per nm.
- *  R15 adaptive ROI-grid refinement (Sec. 3.4, aluminium bicrystal;
+ *  R15 adaptive ROI-grid refinement (Sec. 3.5, aluminium bicrystal;
  *      supplement, local grid refinement): the intensity of coarse ROI r in
  *      window w is I[r][w] = max_v img[r][w][v] / N_r (0 for an empty ROI),
- *      the per-atom peak amplitude.  "kappa normalised intensity" is read
- *      against the distribution over all coarse ROIs: r is kept iff for a
- *      selected window I[r][w] >= kappa * max_r' I[r'][w].  Each kept ROI's
+ *      the per-atom peak amplitude.  The kappa threshold on normalised
+ *      intensity is read against the distribution over all coarse ROIs: r
+ *      is kept iff for a selected window I[r][w] >= kappa * max_r' I[r'][w].
+ *      Each kept ROI's
  *      grid cell (edge h, centred on the ROI) is split into s^3 cells
  *      (s = 5 in the main text; the supplement's 0.5 nm and 64x imply 4)
  *      whose centres c + h (2i + 1 - s) / (2s) are the refined ROIs, in
@@ -690,12 +692,15 @@ void orc_fsp_grid(const float *rel, int64_t n_w, int32_t L, double k_max, double
 /* ---------------------------------------------------------------------- */
 /* keep[r] = 1 if ROI r passes the kappa test on a window of window_mask.
  * Returns the number of kept ROIs; refined centres are written for them
- * (cap ROIs at most, parent index of each). */
+ * (cap ROIs at most, parent index of each).  Returns -1 without writing
+ * anything when n_win is outside [1, 32] (the window mask has 32 bits) or
+ * split < 1. */
 int64_t orc_refine_roi_grid(const float *centres, const double *img, const int32_t *counts, int64_t n_roi,
                             int32_t n_win, int32_t n_dir, uint32_t window_mask, double kappa, double h, int32_t split,
                             int32_t *keep, float *out_centres, int32_t *out_parent, int64_t cap)
 {
     double best[32];
+    if (n_win < 1 || n_win > 32 || split < 1) return -1;
     double *I = (double *)malloc(sizeof(double) * (size_t)(n_roi > 0 ? n_roi : 1) * n_win);
     for (int32_t w = 0; w < n_win; ++w) best[w] = 0.0;
     for (int64_t r = 0; r < n_roi; ++r)

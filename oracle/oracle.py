@@ -21,15 +21,26 @@ CFLAGS = ["-O2", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off", "-fno-fast
           "-fopenmp", "-Wall", "-Wno-unknown-pragmas"]
 
 
-def build(verbose: bool = False) -> str:
+# Host sanitizer build of the same source (memory errors and undefined
+# behaviour abort the process).  Loaded instead of LIB when the environment
+# variable ARAULLO_ORACLE_SANITIZED=1 is set; the Python process must then run
+# with the sanitizer runtime preloaded (see tests/test_oracle_sanitized.py).
+LIB_SANITIZED = os.path.join(HERE, "liboracle_sanitized.so")
+SANITIZE_FLAGS = ["-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
+                  "-fno-sanitize-recover=all"]
+
+
+def build(verbose: bool = False, sanitized: bool = False) -> str:
     """Compile the oracle with gcc (always recompiles)."""
-    tmp = LIB + ".tmp"
-    cmd = ["gcc", *CFLAGS, SRC, "-o", tmp, "-lm"]
+    out = LIB_SANITIZED if sanitized else LIB
+    flags = [f for f in CFLAGS if not (sanitized and f == "-O2")] + (SANITIZE_FLAGS if sanitized else [])
+    tmp = out + ".tmp"
+    cmd = ["gcc", *flags, SRC, "-o", tmp, "-lm"]
     if verbose:
         print(" ".join(cmd))
     subprocess.run(cmd, check=True)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, out)
+    return out
 
 
 _lib = None
@@ -44,9 +55,11 @@ c_i32, c_i64, c_f32, c_f64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_float, cty
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
-            build()
-        L = ctypes.CDLL(LIB)
+        sanitized = os.environ.get("ARAULLO_ORACLE_SANITIZED") == "1"
+        path = LIB_SANITIZED if sanitized else LIB
+        if not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(SRC):
+            build(sanitized=sanitized)
+        L = ctypes.CDLL(path)
         L.orc_bin_constants.argtypes = [c_f32, c_i32, ctypes.POINTER(c_f32), ctypes.POINTER(c_f32),
                                         ctypes.POINTER(c_f64)]
         L.orc_window_bins.argtypes = [c_f64, c_i32, c_f64, c_f64, ctypes.POINTER(c_i32), ctypes.POINTER(c_i32)]
@@ -323,15 +336,19 @@ def refine_roi_grid(centres, images, counts, window_mask: int, kappa: float, h: 
     c = _f32(centres).reshape(-1, 3)
     img = _f64(images)
     n_roi, n_win, n_dir = img.shape
-    assert n_win <= 32
+    if float(np.float32(h)) != float(h):
+        # the GPU interface takes h in single precision: callers pass an FP32
+        # number to both sides instead of the oracle rounding it
+        raise ValueError(f"cell edge {h!r} is not a single-precision number")
     cnt = _i32(counts)
     keep = np.zeros(n_roi, np.int32)
     cap = int(n_roi) * split ** 3
     out = np.zeros((max(cap, 1), 3), np.float32)
     par = np.zeros(max(cap, 1), np.int32)
-    # the cell edge is a single-precision parameter of the method's interface
-    n_keep = lib().orc_refine_roi_grid(c, img, cnt, n_roi, n_win, n_dir, window_mask, kappa, float(np.float32(h)),
+    n_keep = lib().orc_refine_roi_grid(c, img, cnt, n_roi, n_win, n_dir, window_mask, kappa, float(h),
                                        split, keep, out, par, cap)
+    if n_keep < 0:
+        raise ValueError(f"n_win {n_win} outside [1, 32] or split {split} < 1")
     n = int(n_keep) * split ** 3
     return keep, out[:n], par[:n]
 

@@ -1,4 +1,4 @@
-// Adaptive ROI-grid refinement (Sec. 3.4, aluminium bicrystal; supplement,
+// Adaptive ROI-grid refinement (Sec. 3.5, aluminium bicrystal; supplement,
 // local grid refinement): scan with a coarse ROI grid, keep the ROIs whose
 // peak intensity in a selected window reaches kappa times the best coarse
 // ROI's, and split each kept ROI's grid cell into s^3 cells whose centres are

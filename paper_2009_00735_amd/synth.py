@@ -589,7 +589,7 @@ def fsp_specimen(n_roi: int = 10000, R: float = 2.0, box: float = 24.0, eta: flo
 
 
 # --------------------------------------------------------------------------
-# coarse ROI grids and a bicrystal (Sec. 3.4: ROIs on a cubic grid over an
+# coarse ROI grids and a bicrystal (Sec. 3.5: ROIs on a cubic grid over an
 # aluminium bicrystal, then local refinement)
 # --------------------------------------------------------------------------
 def roi_grid(lo, hi, h: float) -> np.ndarray:

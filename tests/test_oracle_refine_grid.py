@@ -45,3 +45,16 @@ def test_split_geometry(orc):
         assert np.allclose(np.diff(g[0, :, 0, 1]), h / s, atol=1e-5)      # j along y
         assert np.allclose(np.diff(g[0, 0, :, 2]), h / s, atol=1e-5)      # k along z
         assert np.allclose(g[-1, -1, -1] - g[0, 0, 0], h - h / s, atol=1e-5)
+
+
+def test_invalid_arguments_are_refused(orc):
+    import pytest
+    cen = np.zeros((1, 3), np.float32)
+    with pytest.raises(ValueError):                       # 33 windows: the mask has 32 bits
+        orc.refine_roi_grid(cen, np.ones((1, 33, 4)), [7], 1, 0.75, 2.0, 2)
+    with pytest.raises(ValueError):
+        orc.refine_roi_grid(cen, np.ones((1, 1, 4)), [7], 1, 0.75, 2.0, 0)
+    with pytest.raises(ValueError):                       # not a single-precision number
+        orc.refine_roi_grid(cen, np.ones((1, 1, 4)), [7], 1, 0.75, 0.1, 2)
+    keep, out, _ = orc.refine_roi_grid(cen, np.ones((1, 32, 4)), [7], 1 << 31, 0.75, float(np.float32(0.1)), 2)
+    assert keep.tolist() == [1] and len(out) == 8
