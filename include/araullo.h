@@ -389,6 +389,7 @@ ar_status ar_disorientation_cubic(const double *qa, const double *qb, int64_t n,
  *   reference  device float [n_phase][n_win][n_dir]
  *   directions device float [n_dir][3]
  *   quats      device double [n_lib][4] (w, x, y, z), phase device int32 [n_lib]
+ *              (values in [0, n_phase); a value outside is clamped)
  *   out        device float [n_lib][n_win][n_dir]
  */
 ar_status ar_rotate_reference(ar_context *ctx, const float *reference, int32_t n_phase, int32_t n_win,
@@ -406,12 +407,20 @@ ar_status ar_rotate_reference(ar_context *ctx, const float *reference, int32_t n
  * Terms with |F| < 1e-12 N_w add nothing to the gradient.
  *   rel, offsets  gathered CSR (ar_roi_gather)
  *   quats         device float [n_roi][4]
- *   phase         device int32 [n_roi]
+ *   phase         device int32 [n_roi], values in [0, n_phase) (a value
+ *                 outside is clamped to that range; nothing is read out of
+ *                 bounds)
  *   freqs         device float [n_phase][n_freq]
  *   targets       device float [n_phase][n_freq][n_dir]
  *   score         device float [n_roi], out
  *   grad          device float [n_roi][4] or NULL, out (NULL: forward only)
- * n_freq in [1, 8].  Does not synchronise.
+ * n_freq in [1, 8].  Domain: the phase f_w (u_v . x_j), in turns, goes to
+ * the hardware sine and cosine without range reduction, which are specified
+ * for |phase| <= 256 turns; their argument carries a rounding error of about
+ * |phase| 2^-24 turns, so max|f| max|x| must stay at or below 256 (the
+ * Python binding checks it; at f = 10 nm^-1 and R = 2 nm it is 20).  The
+ * same holds for ar_sf_amplitudes and ar_refine_orientations; the FP64
+ * forward reduces its phases exactly.  Does not synchronise.
  */
 ar_status ar_sf_score_grad(ar_context *ctx, const float *rel, const int64_t *offsets, int64_t n_roi,
                            const float *quats, const int32_t *phase, const float *directions,

@@ -62,8 +62,8 @@ __global__ __launch_bounds__(256) void k_disorientation(const double *__restrict
 __global__ __launch_bounds__(256) void k_rotate_reference(const float *__restrict__ ref, int n_win,
                                                           const float *__restrict__ dirs, int n_dir,
                                                           const double *__restrict__ quats,
-                                                          const int32_t *__restrict__ phase, int64_t n_lib,
-                                                          MeshCells mc, float *__restrict__ out)
+                                                          const int32_t *__restrict__ phase, int n_phase,
+                                                          int64_t n_lib, MeshCells mc, float *__restrict__ out)
 {
     const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t l = gid / n_dir;
@@ -77,7 +77,7 @@ __global__ __launch_bounds__(256) void k_rotate_reference(const float *__restric
     const double rz = M[2] * nx + M[5] * ny + M[8] * nz;
     const int arg = nearest_node(rx, ry, rz, dirs, n_dir, mc);
     if (!valid) return;
-    const int p = phase[l];
+    const int p = min(max(phase[l], 0), n_phase - 1);   // out-of-range phases are clamped
     for (int w = 0; w < n_win; ++w)
         out[((size_t)l * n_win + w) * n_dir + v] = ref[((size_t)p * n_win + w) * n_dir + arg];
 }
@@ -111,7 +111,7 @@ ar_status ar_rotate_reference(ar_context *ctx, const float *reference, int32_t n
     ar::MeshCells mc;
     AR_TRY(ar::build_mesh_cells(ctx, directions, n_dir, (hipStream_t)stream, mc));
     ar::k_rotate_reference<<<(unsigned)((n + 255) / 256), 256, 0, (hipStream_t)stream>>>(
-        reference, n_win, directions, n_dir, quats, phase, n_lib, mc, out);
+        reference, n_win, directions, n_dir, quats, phase, n_phase, n_lib, mc, out);
     AR_HIP(hipGetLastError());
     return AR_OK;
 }

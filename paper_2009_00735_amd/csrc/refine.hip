@@ -127,7 +127,8 @@ __device__ __forceinline__ void sf_term(const float4 x, float ax, float ay, floa
 template <int MODE, int NF>
 __global__ __launch_bounds__(kTile) void k_sf(const float4 *__restrict__ rel, const int64_t *__restrict__ offsets,
                                               const float *__restrict__ quats, const int32_t *__restrict__ phase,
-                                              const float *__restrict__ dirs, int n_dir, const int32_t *__restrict__ rep,
+                                              int n_phase, const float *__restrict__ dirs, int n_dir,
+                                              const int32_t *__restrict__ rep,
                                               const int32_t *__restrict__ mate, const int32_t *__restrict__ n_eval_p,
                                               int n_tiles, int64_t n_roi,
                                               const float *__restrict__ freqs, const float *__restrict__ targets,
@@ -151,7 +152,7 @@ __global__ __launch_bounds__(kTile) void k_sf(const float4 *__restrict__ rel, co
     const bool valid = i_eval < n_eval;
     const int v = valid ? rep[i_eval] : 0;
     const int vm = valid ? mate[i_eval] : -1;
-    const int p = phase[r];
+    const int p = min(max(phase[r], 0), n_phase - 1);   // out-of-range phases are clamped
     float q[4] = {quats[4 * r], quats[4 * r + 1], quats[4 * r + 2], quats[4 * r + 3]};
     float M[9];
     rotation(q, M);
@@ -279,7 +280,7 @@ __global__ __launch_bounds__(kTile) void k_sf(const float4 *__restrict__ rel, co
 template <int MODE, int NF>
 __global__ __launch_bounds__(kTile) void k_sf_rem(const float4 *__restrict__ rel, const int64_t *__restrict__ offsets,
                                                   const float *__restrict__ quats, const int32_t *__restrict__ phase,
-                                                  const float *__restrict__ dirs, int n_dir,
+                                                  int n_phase, const float *__restrict__ dirs, int n_dir,
                                                   const int32_t *__restrict__ rep, const int32_t *__restrict__ mate,
                                                   const int32_t *__restrict__ n_eval_p, int n_tiles,
                                                   const float *__restrict__ freqs, const float *__restrict__ targets,
@@ -290,7 +291,7 @@ __global__ __launch_bounds__(kTile) void k_sf_rem(const float4 *__restrict__ rel
     const int tile = n_eval / kTile;
     const int rem = n_eval - tile * kTile;
     if (rem == 0 || rem >= kRemAtoms) return;
-    const int p = phase[r];
+    const int p = min(max(phase[r], 0), n_phase - 1);   // out-of-range phases are clamped
     float q[4] = {quats[4 * r], quats[4 * r + 1], quats[4 * r + 2], quats[4 * r + 3]};
     float M[9];
     rotation(q, M);
@@ -495,7 +496,7 @@ __global__ __launch_bounds__(256) void k_sf_reduce(const float *__restrict__ par
 // ------------------------------------------------------------ FP64 forward
 __global__ __launch_bounds__(kTile) void k_sf_f64(const float4 *__restrict__ rel, const int64_t *__restrict__ offsets,
                                                   const double *__restrict__ quats, const int32_t *__restrict__ phase,
-                                                  const float *__restrict__ dirs, int n_dir, int n_tiles,
+                                                  int n_phase, const float *__restrict__ dirs, int n_dir, int n_tiles,
                                                   const double *__restrict__ freqs, const double *__restrict__ targets,
                                                   int n_freq, double *__restrict__ partials)
 {
@@ -505,7 +506,7 @@ __global__ __launch_bounds__(kTile) void k_sf_f64(const float4 *__restrict__ rel
     const int tile = blockIdx.x - (int)(r * n_tiles);
     const int v = tile * kTile + threadIdx.x;
     const bool valid = v < n_dir;
-    const int p = phase[r];
+    const int p = min(max(phase[r], 0), n_phase - 1);   // out-of-range phases are clamped
     double q[4] = {quats[4 * r], quats[4 * r + 1], quats[4 * r + 2], quats[4 * r + 3]};
     double M[9];
     rotation(q, M);
@@ -645,10 +646,10 @@ static ar_status sf_check(ar_context *ctx, const float *rel, const int64_t *offs
     return AR_OK;
 }
 
-using SfFn = void (*)(const float4 *, const int64_t *, const float *, const int32_t *, const float *, int,
+using SfFn = void (*)(const float4 *, const int64_t *, const float *, const int32_t *, int, const float *, int,
                      const int32_t *, const int32_t *, const int32_t *, int, int64_t, const float *, const float *,
                      float *, float *);
-using SfRemFn = void (*)(const float4 *, const int64_t *, const float *, const int32_t *, const float *, int,
+using SfRemFn = void (*)(const float4 *, const int64_t *, const float *, const int32_t *, int, const float *, int,
                         const int32_t *, const int32_t *, const int32_t *, int, const float *, const float *, float *,
                         float *);
 
@@ -698,8 +699,9 @@ template <int MODE> SfRemFn sf_rem_kernel(int n_freq)
 }
 
 static ar_status sf_launch(ar_context *ctx, int mode, const float *rel, const int64_t *offsets, int64_t n_roi,
-                           const float *quats, const int32_t *phase, const float *dirs, int32_t n_dir,
-                           const float *freqs, const float *targets, int32_t n_freq, float *score, float *grad,
+                           const float *quats, const int32_t *phase, int32_t n_phase, const float *dirs,
+                           int32_t n_dir, const float *freqs, const float *targets, int32_t n_freq, float *score,
+                           float *grad,
                            float *amp, hipStream_t s, bool have_list = false)
 {
     if (!have_list) {
@@ -711,12 +713,12 @@ static ar_status sf_launch(ar_context *ctx, int mode, const float *rel, const in
     const int n_tiles = (n_dir + sf::kTile - 1) / sf::kTile;
     const unsigned blocks = (unsigned)((n_roi * n_tiles + 7) / 8 * 8);   // k_sf: a multiple of the 8 XCDs
     if (mode == 2) {
-        sf_kernel<2>(n_freq)<<<blocks, sf::kTile, 0, s>>>((const float4 *)rel, offsets, quats, phase, dirs, n_dir,
+        sf_kernel<2>(n_freq)<<<blocks, sf::kTile, 0, s>>>((const float4 *)rel, offsets, quats, phase, n_phase, dirs, n_dir,
                                                           rep, mate, n_eval, n_tiles, n_roi, freqs, targets, nullptr,
                                                           amp);
         AR_HIP(hipGetLastError());
         sf_rem_kernel<2>(n_freq)<<<(unsigned)n_roi, sf::kTile, 0, s>>>((const float4 *)rel, offsets, quats, phase,
-                                                                       dirs, n_dir, rep, mate, n_eval, n_tiles,
+                                                                       n_phase, dirs, n_dir, rep, mate, n_eval, n_tiles,
                                                                        freqs, targets, nullptr, amp);
         AR_HIP(hipGetLastError());
         return AR_OK;
@@ -724,11 +726,11 @@ static ar_status sf_launch(ar_context *ctx, int mode, const float *rel, const in
     AR_TRY(ctx->r_partials.reserve(sizeof(float) * (size_t)n_roi * n_tiles * sf::kPartial));
     float *part = ctx->r_partials.as<float>();
     SfFn fn = mode == 1 ? sf_kernel<1>(n_freq) : sf_kernel<0>(n_freq);
-    fn<<<blocks, sf::kTile, 0, s>>>((const float4 *)rel, offsets, quats, phase, dirs, n_dir, rep, mate, n_eval,
+    fn<<<blocks, sf::kTile, 0, s>>>((const float4 *)rel, offsets, quats, phase, n_phase, dirs, n_dir, rep, mate, n_eval,
                                     n_tiles, n_roi, freqs, targets, part, nullptr);
     AR_HIP(hipGetLastError());
     SfRemFn fr = mode == 1 ? sf_rem_kernel<1>(n_freq) : sf_rem_kernel<0>(n_freq);
-    fr<<<(unsigned)n_roi, sf::kTile, 0, s>>>((const float4 *)rel, offsets, quats, phase, dirs, n_dir, rep, mate,
+    fr<<<(unsigned)n_roi, sf::kTile, 0, s>>>((const float4 *)rel, offsets, quats, phase, n_phase, dirs, n_dir, rep, mate,
                                              n_eval, n_tiles, freqs, targets, part, nullptr);
     AR_HIP(hipGetLastError());
     sf::k_sf_reduce<<<(unsigned)((n_roi + 255) / 256), 256, 0, s>>>(part, n_tiles, n_roi, quats, score,
@@ -749,7 +751,7 @@ ar_status ar_sf_score_grad(ar_context *ctx, const float *rel, const int64_t *off
     AR_TRY(ar::sf_check(ctx, rel, offsets, n_roi, quats, phase, directions, n_dir, freqs, n_phase, n_freq));
     AR_CHECK(targets && score, "targets/score must not be NULL");
     AR_HIP(hipSetDevice(ctx->device));
-    return ar::sf_launch(ctx, grad ? 1 : 0, rel, offsets, n_roi, quats, phase, directions, n_dir, freqs, targets,
+    return ar::sf_launch(ctx, grad ? 1 : 0, rel, offsets, n_roi, quats, phase, n_phase, directions, n_dir, freqs, targets,
                          n_freq, score, grad, nullptr, (hipStream_t)stream);
 }
 
@@ -760,7 +762,7 @@ ar_status ar_sf_amplitudes(ar_context *ctx, const float *rel, const int64_t *off
     AR_TRY(ar::sf_check(ctx, rel, offsets, n_roi, quats, phase, directions, n_dir, freqs, n_phase, n_freq));
     AR_CHECK(amp != nullptr, "amp is NULL");
     AR_HIP(hipSetDevice(ctx->device));
-    return ar::sf_launch(ctx, 2, rel, offsets, n_roi, quats, phase, directions, n_dir, freqs, nullptr, n_freq, nullptr,
+    return ar::sf_launch(ctx, 2, rel, offsets, n_roi, quats, phase, n_phase, directions, n_dir, freqs, nullptr, n_freq, nullptr,
                          nullptr, amp, (hipStream_t)stream);
 }
 
@@ -777,7 +779,7 @@ ar_status ar_sf_score_f64(ar_context *ctx, const float *rel, const int64_t *offs
     AR_TRY(ctx->r_partials.reserve(sizeof(double) * (size_t)n_roi * n_tiles));
     double *part = ctx->r_partials.as<double>();
     ar::sf::k_sf_f64<<<(unsigned)(n_roi * n_tiles), ar::sf::kTile, 0, s>>>(
-        (const float4 *)rel, offsets, quats, phase, directions, n_dir, n_tiles, freqs, targets, n_freq, part);
+        (const float4 *)rel, offsets, quats, phase, n_phase, directions, n_dir, n_tiles, freqs, targets, n_freq, part);
     AR_HIP(hipGetLastError());
     ar::sf::k_sf_reduce_f64<<<(unsigned)((n_roi + 255) / 256), 256, 0, s>>>(part, n_tiles, n_roi, score);
     AR_HIP(hipGetLastError());
@@ -814,7 +816,7 @@ ar_status ar_refine_orientations(ar_context *ctx, const float *rel, const int64_
         // the last evaluation only decides whether its trial is accepted:
         // score alone (the forward kernel, about half the adjoint's work)
         const bool last = it == steps;
-        AR_TRY(ar::sf_launch(ctx, last ? 0 : 1, rel, offsets, n_roi, trial, phase, directions, n_dir, freqs, targets,
+        AR_TRY(ar::sf_launch(ctx, last ? 0 : 1, rel, offsets, n_roi, trial, phase, n_phase, directions, n_dir, freqs, targets,
                              n_freq, Jt, gt, nullptr, s, true));
         ar::sf::k_refine_update<<<nb, 256, 0, s>>>(st, trial, Jt, last ? nullptr : gt, n_roi, it == 0 ? 1 : 0, a0);
         AR_HIP(hipGetLastError());

@@ -106,6 +106,29 @@ def _dev(t: torch.Tensor, dtype, device, name: str) -> int:
     return t.data_ptr()
 
 
+def _shape(t: torch.Tensor, shape, name: str) -> None:
+    """Raise ValueError unless t has the given shape (None matches any size)."""
+    ok = t.dim() == len(shape) and all(want is None or got == want for got, want in zip(t.shape, shape))
+    if not ok:
+        want = "[" + "][".join("*" if x is None else str(x) for x in shape) + "]"
+        raise ValueError(f"{name} must have shape {want}, got {list(t.shape)}")
+
+
+# v_sin_f32 / v_cos_f32 take the phase in turns and are specified for
+# |t| <= 256; the structure-factor kernels form t = f (u . x) without range
+# reduction, so every call checks max|f| * max|x| against that bound.
+SF_MAX_TURNS = 256.0
+
+
+def _sf_domain(rel: torch.Tensor, freqs: torch.Tensor) -> None:
+    if rel.numel() == 0:
+        return
+    turns = float(freqs.detach().abs().max()) * float(torch.linalg.vector_norm(rel[:, :3], dim=1).max())
+    if not turns <= SF_MAX_TURNS:
+        raise ValueError(f"max|f| * max|x| = {turns:.4g} turns exceeds the {SF_MAX_TURNS:g}-turn domain of the "
+                         "hardware sine and cosine")
+
+
 class Context:
     """ar_context on one GPU."""
 
@@ -155,6 +178,8 @@ def ar_roi_gather(ctx: Context, positions: torch.Tensor, centres: torch.Tensor, 
     With types (int32 [n_atoms]) only atoms whose type bit is set in
     type_mask are gathered (ar_roi_gather_typed)."""
     d = ctx.device
+    _shape(positions, (None, 3), "positions")
+    _shape(centres, (None, 3), "centres")
     n_roi = centres.shape[0]
     total = i64()
     pp = _dev(positions, torch.float32, d, "positions") if positions.numel() else None
@@ -165,6 +190,7 @@ def ar_roi_gather(ctx: Context, positions: torch.Tensor, centres: torch.Tensor, 
             _call("ar_roi_gather", ctx.handle, pp, positions.shape[0], cp, n_roi, radius, offp, relp, cap,
                   ctypes.byref(total), s)
     else:
+        _shape(types, (positions.shape[0],), "types")
         tp = _dev(types, torch.int32, d, "types") if types.numel() else None
 
         def gather(offp, relp, cap):
@@ -172,6 +198,8 @@ def ar_roi_gather(ctx: Context, positions: torch.Tensor, centres: torch.Tensor, 
                   relp, cap, ctypes.byref(total), s)
     if out is not None:
         offsets, rel = out
+        _shape(offsets, (n_roi + 1,), "offsets")
+        _shape(rel, (None, 4), "rel")
         _dev(offsets, torch.int64, d, "offsets")
         _dev(rel, torch.float32, d, "rel")
         gather(offsets.data_ptr(), rel.data_ptr(), rel.shape[0])
@@ -187,6 +215,9 @@ def araullo_signatures(ctx: Context, positions: torch.Tensor, centres: torch.Ten
                        directions: torch.Tensor, nbins: int, windows, counts: bool = True):
     """-> images float32 [n_roi][n_win][n_dir] (and int32 counts [n_roi])."""
     d = ctx.device
+    _shape(positions, (None, 3), "positions")
+    _shape(centres, (None, 3), "centres")
+    _shape(directions, (None, 3), "directions")
     w = _host_windows(windows)
     n_roi, n_dir, n_win = centres.shape[0], directions.shape[0], w.shape[0]
     images = torch.empty((n_roi, n_win, n_dir), dtype=torch.float32, device=d)
@@ -204,6 +235,10 @@ def araullo_signatures_typed(ctx: Context, positions: torch.Tensor, types: torch
     """-> images float32 [n_roi][n_ch][n_win][n_dir] (and int32 counts [n_roi][n_ch]):
     one signature channel per atom-type mask."""
     d = ctx.device
+    _shape(positions, (None, 3), "positions")
+    _shape(types, (positions.shape[0],), "types")
+    _shape(centres, (None, 3), "centres")
+    _shape(directions, (None, 3), "directions")
     w = _host_windows(windows)
     n_roi, n_dir, n_win, n_ch = centres.shape[0], directions.shape[0], w.shape[0], len(type_masks)
     masks = (ctypes.c_uint64 * n_ch)(*[int(m) for m in type_masks])
@@ -222,6 +257,9 @@ def araullo_sdm(ctx: Context, positions: torch.Tensor, centres: torch.Tensor, ra
                 directions: torch.Tensor, nbins: int):
     """-> (hist int32 [n_roi][n_dir][nbins], amp float32 [n_roi][n_dir][nbins/2+1])."""
     d = ctx.device
+    _shape(positions, (None, 3), "positions")
+    _shape(centres, (None, 3), "centres")
+    _shape(directions, (None, 3), "directions")
     n_roi, n_dir = centres.shape[0], directions.shape[0]
     hist = torch.empty((n_roi, n_dir, nbins), dtype=torch.int32, device=d)
     amp = torch.empty((n_roi, n_dir, nbins // 2 + 1), dtype=torch.float32, device=d)
@@ -235,8 +273,12 @@ def araullo_signatures_csr(ctx: Context, rel: torch.Tensor, offsets: torch.Tenso
                            directions: torch.Tensor, nbins: int, windows, out: Optional[torch.Tensor] = None):
     d = ctx.device
     w = _host_windows(windows)
+    _shape(rel, (None, 4), "rel")
+    _shape(offsets, (None,), "offsets")
+    _shape(directions, (None, 3), "directions")
     n_roi, n_dir, n_win = offsets.shape[0] - 1, directions.shape[0], w.shape[0]
     images = out if out is not None else torch.empty((n_roi, n_win, n_dir), dtype=torch.float32, device=d)
+    _shape(images, (n_roi, n_win, n_dir), "out")
     relp = rel if rel.numel() else torch.zeros((1, 4), dtype=torch.float32, device=d)
     _call("araullo_signatures_csr", ctx.handle, _dev(relp, torch.float32, d, "rel"),
           _dev(offsets, torch.int64, d, "offsets"), n_roi, radius, _dev(directions, torch.float32, d, "directions"),
@@ -256,6 +298,10 @@ class SignaturePlan:
 
     def _args(self, rel, offsets, directions, images):
         d = self.ctx.device
+        _shape(rel, (None, 4), "rel")
+        _shape(offsets, (None,), "offsets")
+        _shape(directions, (self.n_dir, 3), "directions")
+        _shape(images, (offsets.shape[0] - 1, self.n_win, self.n_dir), "images")
         relp = rel if rel.numel() else torch.zeros((1, 4), dtype=torch.float32, device=d)
         return (_dev(relp, torch.float32, d, "rel"), _dev(offsets, torch.int64, d, "offsets"), offsets.shape[0] - 1,
                 _dev(directions, torch.float32, d, "directions"), _dev(images, torch.float32, d, "images"))
@@ -310,6 +356,7 @@ class Library:
 
     def __init__(self, ctx: Context, ref_images: torch.Tensor):
         self.ctx = ctx
+        _shape(ref_images, (None, None, None), "ref_images")
         n_lib, n_win, n_dir = ref_images.shape
         self.ref = ref_images
         self.n_lib, self.n_win, self.n_dir = n_lib, n_win, n_dir
@@ -338,6 +385,7 @@ def ar_index_set_tile(ctx: Context, waves: int, wtm: int, wtn: int, bk: int) -> 
 def index_orientations(ctx: Context, images: torch.Tensor, library: Library, k: int = 16):
     """-> (top_idx int32 [n_roi][k], top_score float32 [n_roi][k])."""
     d = ctx.device
+    _shape(images, (None, library.n_win, library.n_dir), "images")
     n_roi = images.shape[0]
     idx = torch.empty((n_roi, k), dtype=torch.int32, device=d)
     sc = torch.empty((n_roi, k), dtype=torch.float32, device=d)
@@ -349,6 +397,7 @@ def index_orientations(ctx: Context, images: torch.Tensor, library: Library, k: 
 def index_orientations_ex(ctx: Context, images: torch.Tensor, library: Library, k: int, cand: int):
     """-> (top_idx, top_score, cand_idx int32 [n_roi][cand])."""
     d = ctx.device
+    _shape(images, (None, library.n_win, library.n_dir), "images")
     n_roi = images.shape[0]
     idx = torch.empty((n_roi, k), dtype=torch.int32, device=d)
     sc = torch.empty((n_roi, k), dtype=torch.float32, device=d)
@@ -368,7 +417,9 @@ class SparseLUT:
                  phase_count: Sequence[int], n_hat: int):
         self.ctx = ctx
         d = ctx.device
+        _shape(reference, (None, None, None), "reference")
         n_phase, n_win, n_dir = reference.shape
+        _shape(directions, (n_dir, 3), "directions")
         if len(phase_count) != n_phase:
             raise ValueError("phase_count needs one entry per phase")
         counts = (i64 * n_phase)(*[int(c) for c in phase_count])
@@ -414,6 +465,7 @@ class SparseLUT:
 def index_orientations_sparse(ctx: Context, images: torch.Tensor, lut: SparseLUT, k: int = 16):
     """-> (top_idx int32 [n_roi][k], top_score float32 [n_roi][k]): sparse Eq. S1."""
     d = ctx.device
+    _shape(images, (None, lut.n_win, lut.n_dir), "images")
     n_roi = images.shape[0]
     idx = torch.empty((n_roi, k), dtype=torch.int32, device=d)
     sc = torch.empty((n_roi, k), dtype=torch.float32, device=d)
@@ -426,9 +478,12 @@ def ar_fsp_amplitudes(ctx: Context, rel: torch.Tensor, offsets: torch.Tensor, L:
                       out: Optional[torch.Tensor] = None) -> torch.Tensor:
     """-> amplitudes float32 [n_roi][L][L][L] of Eq. (2) on the cubic grid."""
     d = ctx.device
+    _shape(rel, (None, 4), "rel")
+    _shape(offsets, (None,), "offsets")
     n_roi = offsets.shape[0] - 1
     if out is None:
         out = torch.empty((n_roi, L, L, L), dtype=torch.float32, device=d)
+    _shape(out, (n_roi, L, L, L), "out")
     _call("ar_fsp_amplitudes", ctx.handle, _dev(rel, torch.float32, d, "rel"), _dev(offsets, torch.int64, d, "offsets"),
           n_roi, L, k_max, _dev(out, torch.float32, d, "out"), _stream(d))
     return out
@@ -439,7 +494,10 @@ def ar_refine_roi_grid(ctx: Context, centres: torch.Tensor, images: torch.Tensor
     """-> (refined centres float32 [n][3], parent int32 [n]) of the coarse ROIs
     that pass the kappa test (see include/araullo.h)."""
     d = ctx.device
+    _shape(images, (None, None, None), "images")
     n_roi, n_win, n_dir = images.shape
+    _shape(centres, (n_roi, 3), "centres")
+    _shape(counts, (n_roi,), "counts")
     cap = n_roi * split ** 3
     out = torch.empty((max(cap, 1), 3), dtype=torch.float32, device=d)
     par = torch.empty(max(cap, 1), dtype=torch.int32, device=d)
@@ -453,6 +511,8 @@ def ar_refine_roi_grid(ctx: Context, centres: torch.Tensor, images: torch.Tensor
 def ar_disorientation_cubic(qa: torch.Tensor, qb: torch.Tensor) -> torch.Tensor:
     d = qa.device
     n = qa.shape[0]
+    _shape(qa, (n, 4), "qa")
+    _shape(qb, (n, 4), "qb")
     out = torch.empty(n, dtype=torch.float64, device=d)
     _call("ar_disorientation_cubic", _dev(qa, torch.float64, d, "qa"), _dev(qb, torch.float64, d, "qb"), n,
           out.data_ptr(), _stream(d))
@@ -462,18 +522,39 @@ def ar_disorientation_cubic(qa: torch.Tensor, qb: torch.Tensor) -> torch.Tensor:
 def ar_rotate_reference(ctx: Context, reference: torch.Tensor, directions: torch.Tensor, quats: torch.Tensor,
                         phase: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
     d = ctx.device
+    _shape(reference, (None, None, None), "reference")
     n_phase, n_win, n_dir = reference.shape
     n_lib = quats.shape[0]
+    _shape(directions, (n_dir, 3), "directions")
+    _shape(quats, (n_lib, 4), "quats")
+    _shape(phase, (n_lib,), "phase")
     o = out if out is not None else torch.empty((n_lib, n_win, n_dir), dtype=torch.float32, device=d)
+    _shape(o, (n_lib, n_win, n_dir), "out")
     _call("ar_rotate_reference", ctx.handle, _dev(reference, torch.float32, d, "reference"), n_phase, n_win,
           _dev(directions, torch.float32, d, "directions"), n_dir, _dev(quats, torch.float64, d, "quats"),
           _dev(phase, torch.int32, d, "phase"), n_lib, _dev(o, torch.float32, d, "out"), _stream(d))
     return o
 
 
+def _sf_shapes(rel, offsets, quats, phase, directions, freqs, targets=None) -> None:
+    """Shape checks shared by the structure-factor calls: the kernels index
+    quats[4 r + i], phase[r], freqs[p][w] and targets[p][w][v] directly."""
+    _shape(rel, (None, 4), "rel")
+    _shape(offsets, (None,), "offsets")
+    n_roi = offsets.shape[0] - 1
+    _shape(quats, (n_roi, 4), "quats")
+    _shape(phase, (n_roi,), "phase")
+    _shape(directions, (None, 3), "directions")
+    _shape(freqs, (None, None), "freqs")
+    if targets is not None:
+        _shape(targets, (freqs.shape[0], freqs.shape[1], directions.shape[0]), "targets")
+    _sf_domain(rel, freqs)
+
+
 def ar_sf_score_grad(ctx: Context, rel, offsets, quats, phase, directions, freqs, targets, grad: bool = True):
     """-> (score float32 [n_roi], grad float32 [n_roi][4] or None)."""
     d = ctx.device
+    _sf_shapes(rel, offsets, quats, phase, directions, freqs, targets)
     n_roi = offsets.shape[0] - 1
     n_phase, n_freq = freqs.shape
     score = torch.empty(n_roi, dtype=torch.float32, device=d)
@@ -489,6 +570,7 @@ def ar_sf_score_grad(ctx: Context, rel, offsets, quats, phase, directions, freqs
 
 def ar_sf_score_f64(ctx: Context, rel, offsets, quats, phase, directions, freqs, targets) -> torch.Tensor:
     d = ctx.device
+    _sf_shapes(rel, offsets, quats, phase, directions, freqs, targets)
     n_roi = offsets.shape[0] - 1
     n_phase, n_freq = freqs.shape
     score = torch.empty(n_roi, dtype=torch.float64, device=d)
@@ -502,6 +584,7 @@ def ar_sf_score_f64(ctx: Context, rel, offsets, quats, phase, directions, freqs,
 
 def ar_sf_amplitudes(ctx: Context, rel, offsets, quats, phase, directions, freqs) -> torch.Tensor:
     d = ctx.device
+    _sf_shapes(rel, offsets, quats, phase, directions, freqs)
     n_roi = offsets.shape[0] - 1
     n_phase, n_freq = freqs.shape
     amp = torch.empty((n_roi, n_freq, directions.shape[0]), dtype=torch.float32, device=d)
@@ -517,6 +600,7 @@ def ar_refine_orientations(ctx: Context, rel, offsets, quats, phase, directions,
                            a0: float = 1e-3):
     """Refines quats in place; -> final score float32 [n_roi]."""
     d = ctx.device
+    _sf_shapes(rel, offsets, quats, phase, directions, freqs, targets)
     n_roi = offsets.shape[0] - 1
     n_phase, n_freq = freqs.shape
     score = torch.empty(n_roi, dtype=torch.float32, device=d)

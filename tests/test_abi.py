@@ -67,3 +67,58 @@ def test_null_context_is_rejected():
     st = native._L.araullo_signatures(None, None, 0, None, 1, 2.0, None, 1, 1024, None, 1, None, None, None)
     assert st == -1
     assert b"NULL" in native._L.ar_last_error()
+
+
+class _HostCtx:
+    """Stand-in context: the binding's shape checks run before any device
+    pointer is taken, so they can be exercised on the CPU."""
+    device = "cpu"
+    handle = None
+
+
+def test_binding_rejects_mismatched_shapes():
+    import torch
+    from paper_2009_00735_amd import native
+    c = _HostCtx()
+    rel = torch.zeros((10, 4))
+    off = torch.tensor([0, 4, 10])
+    dirs = torch.zeros((12, 3))
+    freqs = torch.ones((1, 4))
+    targets = torch.zeros((1, 4, 12))
+    good = dict(rel=rel, offsets=off, quats=torch.zeros((2, 4)), phase=torch.zeros(2, dtype=torch.int32),
+                directions=dirs, freqs=freqs, targets=targets)
+    for key, bad in (("quats", torch.zeros((1, 4))), ("quats", torch.zeros((2, 3))), ("phase", torch.zeros(3)),
+                     ("directions", torch.zeros((12, 4))), ("targets", torch.zeros((1, 4, 11))),
+                     ("targets", torch.zeros((2, 4, 12))), ("rel", torch.zeros((10, 3)))):
+        args = dict(good, **{key: bad})
+        with pytest.raises(ValueError, match=key if key != "rel" else "rel"):
+            native.ar_sf_score_grad(c, **args)
+        with pytest.raises(ValueError):
+            native.ar_refine_orientations(c, **args)
+    with pytest.raises(ValueError, match="quats"):
+        native.ar_rotate_reference(c, torch.zeros((1, 4, 12)), dirs, torch.zeros((5, 3)), torch.zeros(5))
+    with pytest.raises(ValueError, match="phase"):
+        native.ar_rotate_reference(c, torch.zeros((1, 4, 12)), dirs, torch.zeros((5, 4)), torch.zeros(4))
+
+    class _Lib:
+        n_win, n_dir = 4, 12
+    with pytest.raises(ValueError, match="images"):
+        native.index_orientations(c, torch.zeros((3, 4, 11)), _Lib(), 4)
+    with pytest.raises(ValueError, match="counts"):
+        native.ar_refine_roi_grid(c, torch.zeros((3, 3)), torch.zeros((3, 4, 12)), torch.zeros(2), 1, 0.75, 1.0)
+
+
+def test_binding_rejects_phases_beyond_the_sine_domain():
+    """max|f| max|x| above 256 turns leaves the domain of the hardware sine
+    and cosine, so the structure-factor calls refuse it."""
+    import torch
+    from paper_2009_00735_amd import native
+    c = _HostCtx()
+    rel = torch.zeros((10, 4))
+    rel[3, :3] = torch.tensor([30.0, 0.0, 0.0])
+    args = dict(rel=rel, offsets=torch.tensor([0, 10]), quats=torch.zeros((1, 4)),
+                phase=torch.zeros(1, dtype=torch.int32), directions=torch.zeros((12, 3)),
+                targets=torch.zeros((1, 4, 12)))
+    with pytest.raises(ValueError, match="turns"):
+        native.ar_sf_score_grad(c, freqs=torch.full((1, 4), 9.0), **args)
+    native._sf_domain(rel, torch.full((1, 4), 8.5))   # 255 turns: inside

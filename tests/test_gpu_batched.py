@@ -6,6 +6,7 @@ import pytest
 import torch
 
 from paper_2009_00735_amd import synth
+from parity_bars import assert_images
 
 pytestmark = pytest.mark.gpu
 
@@ -83,7 +84,7 @@ def test_plan_sampled_oracle_parity(nat, ctx, orc, cone):
     got = img[torch.as_tensor(pick).cuda()][:, :, torch.as_tensor(dsel).cuda()].cpu().numpy().astype(np.float64)
     assert np.array_equal(counts[pick], rcnt)
     for i in range(len(pick)):
-        assert np.abs(got[i] - ref[i]).max() <= 1e-5 * rcnt[i]
+        assert_images(got[i], ref[i], rcnt[i], f"ROI {pick[i]}")
 
 
 def test_plan_argument_checks(nat, ctx, cone):

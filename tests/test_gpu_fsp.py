@@ -50,11 +50,18 @@ def test_fsp_grid_matches_oracle(nat, ctx, orc, L):
 
 
 def test_fsp_argument_checks(nat, ctx):
+    """The C entry point rejects bad grids before touching `amp` (called
+    directly, with a buffer smaller than the grid asked for); the binding
+    rejects an output of the wrong shape."""
     rel, off = csr([np.zeros((3, 3), np.float32)])
+    rel_d, off_d = dev(rel), dev(off, torch.int64)
+    out = torch.empty((1, 32, 32, 32), device="cuda")
+    s = torch.cuda.current_stream().cuda_stream
     for L, km in [(16, 10.0), (48, 10.0), (1024, 10.0), (64, 0.0), (64, float("nan"))]:
-        with pytest.raises(nat.AraulloError):
-            nat.ar_fsp_amplitudes(ctx, dev(rel), dev(off, torch.int64), L, km,
-                                  out=torch.empty((1, 32, 32, 32), device="cuda"))
+        st = nat._L.ar_fsp_amplitudes(ctx.handle, rel_d.data_ptr(), off_d.data_ptr(), 1, L, km, out.data_ptr(), s)
+        assert st == -1, (L, km)
+    with pytest.raises(ValueError, match="out"):
+        nat.ar_fsp_amplitudes(ctx, rel_d, off_d, 64, 10.0, out=out)
 
 
 def test_fsp_benchmark_size_sampled(nat, ctx, orc):

@@ -11,7 +11,7 @@ the per-phase structure-factor score.
 Parity at these sizes, every oracle input computed by the oracle itself or
 drawn from seeded generators (never taken from the GPU path):
   * signatures of sampled polycrystal ROIs and of the reference crystals, on
-    sampled directions (1e-5 N_w);
+    sampled directions (per value, relative 1e-5 with a floor of 1e-6 N_w);
   * rotated library rows of sampled orientations, level-5 mesh (exact);
   * indexing at the two-phase shape (20000 ROIs x 100000 references x
     40968 nodes) on seeded images generated on the device by torch: on 8
@@ -28,6 +28,7 @@ import pytest
 import torch
 
 from paper_2009_00735_amd import synth
+from parity_bars import assert_images
 
 pytestmark = pytest.mark.gpu
 
@@ -101,13 +102,13 @@ def test_polycrystal_signatures_and_references_sampled(nat, ctx, orc, world):
     ref, cnt = orc.signatures(world["pos"], centres[sel], R, world["dirs"][dsel], NB, wn)
     assert np.array_equal(cnt, counts[sel])
     for i in range(len(sel)):
-        assert np.abs(S[i] - ref[i]).max() <= 1e-5 * cnt[i]
+        assert_images(S[i], ref[i], cnt[i], f"ROI {sel[i]}")
     for ph in (0, 1):
         rpos, roffs = world["ref_in"][ph]
         oref, ocnt = orc.signatures(rpos, roffs, R, world["dirs"][dsel], NB, wn)
         g = world["ref_imgs"][ph][:, :, torch.as_tensor(dsel).cuda()].cpu().numpy()
         for i in range(len(roffs)):
-            assert np.abs(g[i] - oref[i]).max() <= 1e-5 * ocnt[i]
+            assert_images(g[i], oref[i], ocnt[i], f"phase {ph} reference ROI {i}")
 
 
 def test_two_phase_rotated_rows_sampled(nat, ctx, orc, world):
