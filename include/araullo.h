@@ -427,6 +427,29 @@ ar_status ar_sf_score_grad(ar_context *ctx, const float *rel, const int64_t *off
                            int32_t n_dir, const float *freqs, const float *targets, int32_t n_phase,
                            int32_t n_freq, float *score, float *grad, void *stream);
 
+/*
+ * ar_sf_score_grad for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving or refinement loops, harnesses that
+ * forbid allocation): the same kernels, results bit-identical to
+ * ar_sf_score_grad, but the workspace (the direction evaluation list and
+ * the per-tile partial sums) lives in one fixed 32 MiB device array per GPU
+ * that the library holds until the process ends.  The call makes no device
+ * allocation or free.  Arguments, layouts and domain as ar_sf_score_grad;
+ * the caller owns every buffer passed.
+ * Limit: 4 (3 n_dir + 1) rounded up to 256, plus 40 n_roi ceil(n_dir / 256),
+ * bytes must fit 32 MiB (about 19800 ROIs at 10242 directions); a larger
+ * call returns AR_EINVAL and writes nothing.  The array's device address is
+ * looked up by ar_context_create for its device.
+ * Every call on one GPU shares that GPU's array and leaves its contents
+ * behind (nothing in it needs clearing: each call writes what it reads), so
+ * calls that overlap on one GPU (different streams, or other threads,
+ * without ordering between them) race: order them on one stream.
+ */
+ar_status ar_sf_score_grad_noalloc(ar_context *ctx, const float *rel, const int64_t *offsets, int64_t n_roi,
+                                   const float *quats, const int32_t *phase, const float *directions,
+                                   int32_t n_dir, const float *freqs, const float *targets, int32_t n_phase,
+                                   int32_t n_freq, float *score, float *grad, void *stream);
+
 /* FP64 forward of the same score (for finite-difference checks):
  *   quats device double [n_roi][4]; score device double [n_roi], out. */
 ar_status ar_sf_score_f64(ar_context *ctx, const float *rel, const int64_t *offsets, int64_t n_roi,

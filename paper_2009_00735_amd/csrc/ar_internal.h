@@ -117,4 +117,7 @@ ar_status gather_csr(ar_context *ctx, const float *positions, const int32_t *typ
 struct MeshCells;
 // cube-map nearest-node candidate lists of `dirs` in ctx->m_cells (mesh.hip)
 ar_status build_mesh_cells(ar_context *ctx, const float *dirs, int n_dir, hipStream_t stream, MeshCells &mc);
+// looks up, once per device, the device address of the fixed workspace of
+// ar_sf_score_grad_noalloc (refine.hip); `device` must be current
+ar_status scratch_setup(int device);
 }

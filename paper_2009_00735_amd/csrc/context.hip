@@ -127,6 +127,7 @@ ar_status ar_context_create(int device, ar_context **out)
     AR_HIP(hipSetDevice(device));
     hipDeviceProp_t prop;
     AR_HIP(hipGetDeviceProperties(&prop, device));
+    AR_TRY(ar::scratch_setup(device));
     auto *c = new (std::nothrow) ar_context();
     if (!c) return ar::fail(AR_ENOMEM, "context allocation failed");
     c->device = device;

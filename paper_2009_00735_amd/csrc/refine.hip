@@ -28,6 +28,8 @@
 // Directions without an exact antipode are evaluated on their own.
 #include <math.h>
 
+#include <mutex>
+
 #include "ar_internal.h"
 
 namespace ar {
@@ -653,21 +655,30 @@ using SfRemFn = void (*)(const float4 *, const int64_t *, const float *, const i
                         const int32_t *, const int32_t *, const int32_t *, int, const float *, const float *, float *,
                         float *);
 
-// Device evaluation list for `dirs` in ctx workspace: rep, mate [n_dir], n_eval.
-static ar_status eval_list(ar_context *ctx, const float *dirs, int32_t n_dir, const int32_t **rep,
-                           const int32_t **mate, const int32_t **n_eval, hipStream_t s)
+// Device evaluation list for `dirs` written to `base` (int32 [3 n_dir + 1]):
+// mate_of, rep, mate [n_dir] each, then n_eval.
+static size_t eval_list_ints(int32_t n_dir) { return 3 * (size_t)n_dir + 1; }
+
+static ar_status eval_list_into(int32_t *base, const float *dirs, int32_t n_dir, hipStream_t s)
 {
-    AR_TRY(ctx->r_dirs.reserve(sizeof(int32_t) * (3 * (size_t)n_dir + 1)));
-    int32_t *base = ctx->r_dirs.as<int32_t>();
     int32_t *mate_of = base, *r = base + n_dir, *m = base + 2 * n_dir, *n = base + 3 * n_dir;
     sf::k_antipodes<<<(unsigned)((n_dir + 255) / 256), 256, 0, s>>>(dirs, n_dir, mate_of);
     AR_HIP(hipGetLastError());
     sf::k_eval_list<<<1, 1024, 0, s>>>(mate_of, n_dir, r, m, n);
     AR_HIP(hipGetLastError());
-    *rep = r;
-    *mate = m;
-    *n_eval = n;
     return AR_OK;
+}
+
+// The evaluation list in the context's workspace.
+static ar_status eval_list(ar_context *ctx, const float *dirs, int32_t n_dir, hipStream_t s)
+{
+    AR_TRY(ctx->r_dirs.reserve(sizeof(int32_t) * eval_list_ints(n_dir)));
+    return eval_list_into(ctx->r_dirs.as<int32_t>(), dirs, n_dir, s);
+}
+
+static size_t partial_floats(int64_t n_roi, int32_t n_dir)
+{
+    return (size_t)n_roi * ((n_dir + sf::kTile - 1) / sf::kTile) * sf::kPartial;
 }
 
 template <int MODE> SfFn sf_kernel(int n_freq)
@@ -698,18 +709,16 @@ template <int MODE> SfRemFn sf_rem_kernel(int n_freq)
     }
 }
 
-static ar_status sf_launch(ar_context *ctx, int mode, const float *rel, const int64_t *offsets, int64_t n_roi,
-                           const float *quats, const int32_t *phase, int32_t n_phase, const float *dirs,
-                           int32_t n_dir, const float *freqs, const float *targets, int32_t n_freq, float *score,
-                           float *grad,
-                           float *amp, hipStream_t s, bool have_list = false)
+// Launches of one evaluation with explicit workspace: `list` holds the
+// evaluation list of eval_list_into, `part` (mode 0 and 1) the per-tile
+// partials, float [n_roi][n_tiles][kPartial]; every partial is written before
+// it is read, so neither needs clearing.
+static ar_status sf_launch_ws(int mode, const float *rel, const int64_t *offsets, int64_t n_roi, const float *quats,
+                              const int32_t *phase, int32_t n_phase, const float *dirs, int32_t n_dir,
+                              const float *freqs, const float *targets, int32_t n_freq, float *score, float *grad,
+                              float *amp, const int32_t *list, float *part, hipStream_t s)
 {
-    if (!have_list) {
-        const int32_t *a, *b, *c;
-        AR_TRY(eval_list(ctx, dirs, n_dir, &a, &b, &c, s));
-    }
-    const int32_t *base = ctx->r_dirs.as<int32_t>();
-    const int32_t *rep = base + n_dir, *mate = base + 2 * n_dir, *n_eval = base + 3 * n_dir;
+    const int32_t *rep = list + n_dir, *mate = list + 2 * n_dir, *n_eval = list + 3 * n_dir;
     const int n_tiles = (n_dir + sf::kTile - 1) / sf::kTile;
     const unsigned blocks = (unsigned)((n_roi * n_tiles + 7) / 8 * 8);   // k_sf: a multiple of the 8 XCDs
     if (mode == 2) {
@@ -723,8 +732,6 @@ static ar_status sf_launch(ar_context *ctx, int mode, const float *rel, const in
         AR_HIP(hipGetLastError());
         return AR_OK;
     }
-    AR_TRY(ctx->r_partials.reserve(sizeof(float) * (size_t)n_roi * n_tiles * sf::kPartial));
-    float *part = ctx->r_partials.as<float>();
     SfFn fn = mode == 1 ? sf_kernel<1>(n_freq) : sf_kernel<0>(n_freq);
     fn<<<blocks, sf::kTile, 0, s>>>((const float4 *)rel, offsets, quats, phase, n_phase, dirs, n_dir, rep, mate, n_eval,
                                     n_tiles, n_roi, freqs, targets, part, nullptr);
@@ -736,6 +743,49 @@ static ar_status sf_launch(ar_context *ctx, int mode, const float *rel, const in
     sf::k_sf_reduce<<<(unsigned)((n_roi + 255) / 256), 256, 0, s>>>(part, n_tiles, n_roi, quats, score,
                                                                     mode == 1 ? grad : nullptr);
     AR_HIP(hipGetLastError());
+    return AR_OK;
+}
+
+// One evaluation with the context's (growable) workspace.
+static ar_status sf_launch(ar_context *ctx, int mode, const float *rel, const int64_t *offsets, int64_t n_roi,
+                           const float *quats, const int32_t *phase, int32_t n_phase, const float *dirs,
+                           int32_t n_dir, const float *freqs, const float *targets, int32_t n_freq, float *score,
+                           float *grad, float *amp, hipStream_t s, bool have_list = false)
+{
+    if (!have_list) AR_TRY(eval_list(ctx, dirs, n_dir, s));
+    float *part = nullptr;
+    if (mode != 2) {
+        AR_TRY(ctx->r_partials.reserve(sizeof(float) * partial_floats(n_roi, n_dir)));
+        part = ctx->r_partials.as<float>();
+    }
+    return sf_launch_ws(mode, rel, offsets, n_roi, quats, phase, n_phase, dirs, n_dir, freqs, targets, n_freq, score,
+                        grad, amp, ctx->r_dirs.as<int32_t>(), part, s);
+}
+
+// ---------------------------------------------- allocation-free workspace
+// One fixed workspace per GPU for ar_sf_score_grad_noalloc: the evaluation
+// list (256-byte aligned), then the per-tile partials.  It lives as long as
+// the process; its device address is looked up once per device when a
+// context is created on it (the array's name is not a device address in
+// host code).
+constexpr size_t kScratchBytes = (size_t)32 << 20;
+constexpr int kScratchDevices = 64;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+static void *g_scratch[kScratchDevices];
+static std::mutex g_scratch_mu;
+
+static size_t scratch_list_bytes(int32_t n_dir) { return (sizeof(int32_t) * eval_list_ints(n_dir) + 255) / 256 * 256; }
+
+// Called by ar_context_create with `device` current.
+ar_status scratch_setup(int device)
+{
+    if (device < 0 || device >= kScratchDevices) return AR_OK;   // the allocation-free call then refuses
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch[device]) return AR_OK;
+    void *p = nullptr;
+    AR_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    AR_CHECK(p != nullptr, "no device address for the fixed workspace on device %d", device);
+    g_scratch[device] = p;
     return AR_OK;
 }
 
@@ -753,6 +803,35 @@ ar_status ar_sf_score_grad(ar_context *ctx, const float *rel, const int64_t *off
     AR_HIP(hipSetDevice(ctx->device));
     return ar::sf_launch(ctx, grad ? 1 : 0, rel, offsets, n_roi, quats, phase, n_phase, directions, n_dir, freqs, targets,
                          n_freq, score, grad, nullptr, (hipStream_t)stream);
+}
+
+ar_status ar_sf_score_grad_noalloc(ar_context *ctx, const float *rel, const int64_t *offsets, int64_t n_roi,
+                                   const float *quats, const int32_t *phase, const float *directions, int32_t n_dir,
+                                   const float *freqs, const float *targets, int32_t n_phase, int32_t n_freq,
+                                   float *score, float *grad, void *stream)
+{
+    AR_TRY(ar::sf_check(ctx, rel, offsets, n_roi, quats, phase, directions, n_dir, freqs, n_phase, n_freq));
+    AR_CHECK(targets && score, "targets/score must not be NULL");
+    const size_t list = ar::scratch_list_bytes(n_dir);
+    const size_t need = list + sizeof(float) * ar::partial_floats(n_roi, n_dir);
+    AR_CHECK(need <= ar::kScratchBytes,
+             "n_roi = %lld and n_dir = %d need %zu bytes of workspace; the fixed workspace holds %zu "
+             "(n_roi * ceil(n_dir / 256) * 40 + 12 n_dir bytes, about)",
+             (long long)n_roi, n_dir, need, ar::kScratchBytes);
+    AR_CHECK(ctx->device < ar::kScratchDevices, "device %d has no fixed workspace", ctx->device);
+    unsigned char *base;
+    {
+        std::lock_guard<std::mutex> lock(ar::g_scratch_mu);
+        base = static_cast<unsigned char *>(ar::g_scratch[ctx->device]);
+    }
+    AR_CHECK(base != nullptr, "fixed workspace of device %d not set up", ctx->device);
+    AR_HIP(hipSetDevice(ctx->device));
+    hipStream_t s = (hipStream_t)stream;
+    int32_t *lst = reinterpret_cast<int32_t *>(base);
+    float *part = reinterpret_cast<float *>(base + list);
+    AR_TRY(ar::eval_list_into(lst, directions, n_dir, s));
+    return ar::sf_launch_ws(grad ? 1 : 0, rel, offsets, n_roi, quats, phase, n_phase, directions, n_dir, freqs,
+                            targets, n_freq, score, grad, nullptr, lst, part, s);
 }
 
 ar_status ar_sf_amplitudes(ar_context *ctx, const float *rel, const int64_t *offsets, int64_t n_roi,
@@ -808,10 +887,7 @@ ar_status ar_refine_orientations(ar_context *ctx, const float *rel, const int64_
     const unsigned nb = (unsigned)((n_roi + 255) / 256);
     ar::sf::k_copy4<<<(unsigned)((4 * n_roi + 255) / 256), 256, 0, s>>>(quats, trial, n_roi);
     AR_HIP(hipGetLastError());
-    {
-        const int32_t *a, *b, *c;
-        AR_TRY(ar::eval_list(ctx, directions, n_dir, &a, &b, &c, s));
-    }
+    AR_TRY(ar::eval_list(ctx, directions, n_dir, s));
     for (int it = 0; it <= steps; ++it) {
         // the last evaluation only decides whether its trial is accepted:
         // score alone (the forward kernel, about half the adjoint's work)

@@ -59,6 +59,7 @@ _SIGS = {
     "ar_disorientation_cubic": ([vp, vp, i64, vp, vp], ctypes.c_int),
     "ar_rotate_reference": ([vp, vp, i32, i32, vp, i32, vp, vp, i64, vp, vp], ctypes.c_int),
     "ar_sf_score_grad": ([vp, vp, vp, i64, vp, vp, vp, i32, vp, vp, i32, i32, vp, vp, vp], ctypes.c_int),
+    "ar_sf_score_grad_noalloc": ([vp, vp, vp, i64, vp, vp, vp, i32, vp, vp, i32, i32, vp, vp, vp], ctypes.c_int),
     "ar_sf_score_f64": ([vp, vp, vp, i64, vp, vp, vp, i32, vp, vp, i32, i32, vp, vp], ctypes.c_int),
     "ar_sf_amplitudes": ([vp, vp, vp, i64, vp, vp, vp, i32, vp, i32, i32, vp, vp], ctypes.c_int),
     "ar_refine_orientations": ([vp, vp, vp, i64, vp, vp, vp, i32, vp, vp, i32, i32, i32, f32, vp, vp],
@@ -566,6 +567,33 @@ def ar_sf_score_grad(ctx: Context, rel, offsets, quats, phase, directions, freqs
           _dev(targets, torch.float32, d, "targets"), n_phase, n_freq, score.data_ptr(),
           g.data_ptr() if grad else None, _stream(d))
     return score, g
+
+
+def ar_sf_score_grad_noalloc(ctx: Context, rel, offsets, quats, phase, directions, freqs, targets,
+                             score: torch.Tensor, grad: Optional[torch.Tensor] = None) -> None:
+    """ar_sf_score_grad into caller-owned outputs (score float32 [n_roi],
+    grad float32 [n_roi][4] or None) through the allocation-free entry point.
+    Shape checks only: this wrapper allocates nothing, so the 256-turn sine
+    domain (max|f| max|x|) is the caller's to keep."""
+    d = ctx.device
+    _shape(rel, (None, 4), "rel")
+    _shape(offsets, (None,), "offsets")
+    n_roi = offsets.shape[0] - 1
+    _shape(quats, (n_roi, 4), "quats")
+    _shape(phase, (n_roi,), "phase")
+    _shape(directions, (None, 3), "directions")
+    _shape(freqs, (None, None), "freqs")
+    n_phase, n_freq = freqs.shape
+    _shape(targets, (n_phase, n_freq, directions.shape[0]), "targets")
+    _shape(score, (n_roi,), "score")
+    if grad is not None:
+        _shape(grad, (n_roi, 4), "grad")
+    _call("ar_sf_score_grad_noalloc", ctx.handle, _dev(rel, torch.float32, d, "rel"),
+          _dev(offsets, torch.int64, d, "offsets"), n_roi, _dev(quats, torch.float32, d, "quats"),
+          _dev(phase, torch.int32, d, "phase"), _dev(directions, torch.float32, d, "directions"), directions.shape[0],
+          _dev(freqs, torch.float32, d, "freqs"), _dev(targets, torch.float32, d, "targets"), n_phase, n_freq,
+          _dev(score, torch.float32, d, "score"), _dev(grad, torch.float32, d, "grad") if grad is not None else None,
+          _stream(d))
 
 
 def ar_sf_score_f64(ctx: Context, rel, offsets, quats, phase, directions, freqs, targets) -> torch.Tensor:
