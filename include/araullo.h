@@ -231,6 +231,30 @@ ar_status ar_signature_plan_run(ar_plan *plan, const float *rel, const int64_t *
  */
 ar_status ar_library_create(ar_context *ctx, const float *ref_images, int64_t n_lib,
                             int32_t n_win, int32_t n_dir, void *stream, ar_library **out);
+/*
+ * As ar_library_create, and the library also keeps the orientation and the
+ * phase of every entry (Sec. 2.4 and the supplement's indexing paragraph:
+ * each reference image is the phase's reference rotated into one test
+ * orientation), so that indexing results can be reported as orientations:
+ *   quats      device double [n_lib][4] (w, x, y, z), copied
+ *   phase      device int32 [n_lib], copied
+ * Entry l of ref_images must be the reference of phase[l] rotated by
+ * quats[l] (e.g. from ar_rotate_reference with the same arrays).
+ */
+ar_status ar_library_prepare(ar_context *ctx, const float *ref_images, int64_t n_lib, int32_t n_win,
+                             int32_t n_dir, const double *quats, const int32_t *phase, void *stream,
+                             ar_library **out);
+/*
+ * Orientation and phase of library entries, e.g. of the top_idx of an
+ * indexing call: quats[i] = quaternion of entry idx[i], phase[i] = its
+ * phase; an index of -1 (no candidate) or out of range gives a NaN
+ * quaternion and phase -1.
+ *   idx    device int32 [n];  quats device double [n][4] or NULL, out;
+ *   phase  device int32 [n] or NULL, out
+ * AR_EINVAL for a library made by ar_library_create.  Does not synchronise.
+ */
+ar_status ar_library_lookup(const ar_library *lib, const int32_t *idx, int64_t n, double *quats,
+                            int32_t *phase, void *stream);
 ar_status ar_library_destroy(ar_library *lib);
 
 /*
@@ -240,10 +264,13 @@ ar_status ar_library_destroy(ar_library *lib);
  *   Delta(r,l) = sum_{w,v} (S_r[w][v]/max_v S_r[w] - L_l[w][v]/max_v L_l[w])^2.
  * Candidates come from a BF16-input / FP32-accumulate MFMA correlation
  * (score = |L_l|^2 - 2 <S_r, L_l>) keeping the best `cand` (16 for
- * k <= 16, else 32) per ROI, which are then rescored in FP32 from the FP32
- * images; the output is sorted ascending by (FP32 Delta, library index).
+ * k <= 16, 32 for k <= 32, else 64) per ROI, which are then rescored in
+ * FP32 from the FP32 images; the output is sorted ascending by (FP32 Delta,
+ * library index).  The paper keeps many near-best solutions per ROI (Sec.
+ * 3.2); k up to 64 returns that many.  Entries past the library's size
+ * (k > n_lib) hold index -1 and Delta +inf.
  *   images    device float [n_roi][n_win][n_dir] (raw signatures)
- *   k         1 .. 32 outputs per ROI
+ *   k         1 .. 64 outputs per ROI
  *   top_idx   device int32 [n_roi][k], out
  *   top_score device float [n_roi][k], out: FP32 Delta
  * Does not synchronise.
@@ -252,9 +279,9 @@ ar_status index_orientations(ar_context *ctx, const float *images, int64_t n_roi
                              const ar_library *lib, int32_t k, int32_t *top_idx, float *top_score,
                              void *stream);
 
-/* As index_orientations with an explicit candidate count `cand` (16 or 32,
- * k <= cand; index_orientations uses 16 for k <= 16, else 32), optionally
- * returning the BF16-stage candidates before rescoring.
+/* As index_orientations with an explicit candidate count `cand` (16, 32 or
+ * 64, k <= cand; index_orientations uses the smallest that holds k),
+ * optionally returning the BF16-stage candidates before rescoring.
  *   cand_idx  device int32 [n_roi][cand] or NULL, out */
 ar_status index_orientations_ex(ar_context *ctx, const float *images, int64_t n_roi,
                                 const ar_library *lib, int32_t k, int32_t cand, int32_t *top_idx,
@@ -265,9 +292,10 @@ ar_status index_orientations_ex(ar_context *ctx, const float *images, int64_t n_
  * 32x32 (workgroup tile 64 wtm x 32 wtn (waves/2)); K advances bk = 32 per
  * step.  Supported (waves, wtm, wtn, bk): (4,2,2,32) (4,2,4,32) (4,4,2,32)
  * (8,2,2,32) (8,4,2,32).  (0,0,0,0) returns to the default choice: (8,4,2,32),
- * a 256 x 256 tile, for 16 candidates and (8,2,2,32), 128 x 256, for 32 (whose
- * candidate lists would spill beside the larger tile's accumulators).  Results
- * do not depend on the tile: every score accumulates K in the same order.
+ * a 256 x 256 tile, for 16 candidates and (8,2,2,32), 128 x 256, for 32 and
+ * 64 (whose candidate lists would spill beside the larger tile's
+ * accumulators).  Results do not depend on the tile: every score accumulates
+ * K in the same order.
  * Returns AR_EINVAL for an unsupported tile. */
 ar_status ar_index_set_tile(ar_context *ctx, int32_t waves, int32_t wtm, int32_t wtn, int32_t bk);
 

@@ -107,6 +107,9 @@ struct ar_library {
     ar::DeviceBuffer bf16;        // [n_pad][Kp] bf16, normalised
     ar::DeviceBuffer norm2;       // [n_pad] float, |bf16 row|^2 (pad rows: +inf)
     ar::DeviceBuffer inv_max;     // [n_lib][n_win] float, 1/max (0 for a zero image)
+    ar::DeviceBuffer quats;       // [n_lib][4] double (w, x, y, z), if prepared with orientations
+    ar::DeviceBuffer phase;       // [n_lib] int32, if prepared with orientations
+    bool has_orientations = false;
 };
 
 namespace ar {

@@ -121,8 +121,10 @@ __global__ __launch_bounds__(256) void k_row_norm2(const uint16_t *__restrict__ 
 // step, whose stage is then refilled.
 // grid.x = m_blocks * n_seg; the launch covers library rows from col0.
 // out_s/out_i: [M_pad][list_stride][CAND]; this launch writes lists
-// list_base .. list_base + n_seg * TPR - 1 of each row, where TPR =
-// THREADS / BM threads share a row in the epilogue.
+// list_base .. list_base + n_seg * LPR - 1 of each row: with CAND 16 or 32,
+// LPR = TPR = THREADS / BM threads share a row in the epilogue, each with its
+// own list in registers; with CAND = 64 each wave owns RPW = BM / WAVES whole
+// rows, one wave-wide list per row and segment (LPR = 1).
 constexpr int kBK = 32;        // bf16 per K step
 constexpr int kStages = 4;     // LDS ring depth
 
@@ -134,6 +136,7 @@ template <int WGM, int WGN, int WTM, int WTN> struct CorrShape {
     static constexpr int A_BLK = BM / 16, B_BLK = BN / 16;     // 1-KB blocks per stage
     static constexpr int BLK_PER_WAVE = (A_BLK + B_BLK) / WAVES;
     static constexpr int TPR = THREADS / BM;                   // epilogue threads per row
+    static constexpr int RPW = BM / WAVES;                     // rows per wave (64-entry wave lists)
     static_assert((A_BLK + B_BLK) % WAVES == 0, "stage blocks must split evenly over the waves");
     static constexpr size_t lds()
     {
@@ -214,6 +217,9 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_corr_topk(const uint16_t *__
     constexpr int BM = S::BM, BN = S::BN, TPR = S::TPR, NB = S::BLK_PER_WAVE;
     static_assert(TPR >= 1 && S::THREADS % BM == 0, "tile too small for the workgroup");
     static_assert((BN / WGN) % 64 == 0, "each wave must own whole 64-column epilogue passes");
+    static_assert(CAND == 16 || CAND == 32 || CAND == 64, "candidate lists of 16, 32 or 64");
+    constexpr bool WAVE_LIST = CAND == 64;
+    constexpr int RPW = S::RPW;
     extern __shared__ __align__(16) unsigned char smem[];
     float *Cs = reinterpret_cast<float *>(smem);                       // [BM][65], aliases the stages
 
@@ -250,8 +256,15 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_corr_topk(const uint16_t *__
     // epilogue ownership: thread -> (row, part of each 64-column pass)
     const int e_row = tid % BM;
     const int e_part = tid / BM;
-    TopList<CAND> top;
+    TopList<WAVE_LIST ? 1 : CAND> top;
     top.init();
+    float wl_s[WAVE_LIST ? RPW : 1];   // 64-entry lists: rows wave + WAVES * j, entry `lane`
+    int wl_i[WAVE_LIST ? RPW : 1];
+#pragma unroll
+    for (int j = 0; j < (WAVE_LIST ? RPW : 1); ++j) {
+        wl_s[j] = INFINITY;
+        wl_i[j] = 0x7fffffff;
+    }
 
     const int KT = (int)(Kp / kBK);
     for (int nt = t0; nt < t1; ++nt) {
@@ -312,7 +325,12 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_corr_topk(const uint16_t *__
                     }
             }
             __syncthreads();
-            {
+            if constexpr (WAVE_LIST) {
+                const int col = (int)(n0 + h * 64) + lane;
+#pragma unroll
+                for (int j = 0; j < RPW; ++j)
+                    wave_merge64(wl_s[j], wl_i[j], Cs[(wave + S::WAVES * j) * 65 + lane], col, lane);
+            } else {
                 constexpr int W = 64 / TPR;
                 const float *crow = Cs + e_row * 65 + e_part * W;
                 const int base = (int)(n0 + h * 64 + e_part * W);
@@ -322,13 +340,25 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_corr_topk(const uint16_t *__
             __syncthreads();
         }
     }
-    const size_t o = (((size_t)(m0 + e_row)) * list_stride + list_base + seg * TPR + e_part) * CAND;
+    if constexpr (WAVE_LIST) {
 #pragma unroll
-    for (int j = 0; j < CAND; ++j) {
-        out_s[o + j] = top.s[j];
-        out_i[o + j] = top.i[j];
+        for (int j = 0; j < RPW; ++j) {
+            const size_t o = (((size_t)(m0 + wave + S::WAVES * j)) * list_stride + list_base + seg) * CAND + lane;
+            out_s[o] = wl_s[j];
+            out_i[o] = wl_i[j];
+        }
+    } else {
+        const size_t o = (((size_t)(m0 + e_row)) * list_stride + list_base + seg * TPR + e_part) * CAND;
+#pragma unroll
+        for (int j = 0; j < CAND; ++j) {
+            out_s[o + j] = top.s[j];
+            out_i[o + j] = top.i[j];
+        }
     }
 }
+
+// Epilogue lists per row and segment of a tile configuration.
+constexpr int lists_per_row(int cand, int threads, int bm) { return cand == 64 ? 1 : threads / bm; }
 
 // ------------------------------------------------------------ merge
 // One wave per row: the CAND smallest (score, index) over n_lists lists.
@@ -349,6 +379,23 @@ __global__ __launch_bounds__(256) void k_merge(const float *__restrict__ in_s, c
     wave_select<CAND>(t, [&](int j, float, int bi) {
         if (lane == 0) cand_idx[(size_t)row * CAND + j] = bi;
     });
+}
+
+// One wave per row, 64 candidates: the lists are read 64 entries at a time
+// and merged into one wave-wide list.
+__global__ __launch_bounds__(256) void k_merge64(const float *__restrict__ in_s, const int32_t *__restrict__ in_i,
+                                                 int n_lists, int64_t n_rows, int32_t *__restrict__ cand_idx)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (row >= n_rows) return;
+    const int n = n_lists * 64;
+    const float *s = in_s + (size_t)row * n;
+    const int32_t *ix = in_i + (size_t)row * n;
+    float ls = INFINITY;
+    int li = 0x7fffffff;
+    for (int e = 0; e < n; e += 64) wave_merge64(ls, li, s[e + lane], ix[e + lane], lane);
+    cand_idx[(size_t)row * 64 + lane] = li;
 }
 
 // ------------------------------------------------------------ FP32 rescore
@@ -465,6 +512,21 @@ ar_status launch_rescore(ar_context *ctx, const float *images, const ar_library 
     return AR_OK;
 }
 
+// Orientation and phase of library entries idx[i] (-1 or out of range: NaN
+// quaternion, phase -1).
+__global__ __launch_bounds__(256) void k_library_lookup(const double *__restrict__ lq, const int32_t *__restrict__ lp,
+                                                        int64_t n_lib, const int32_t *__restrict__ idx, int64_t n,
+                                                        double *__restrict__ quats, int32_t *__restrict__ phase)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int32_t l = idx[i];
+    const bool ok = l >= 0 && l < n_lib;
+    if (quats)
+        for (int c = 0; c < 4; ++c) quats[4 * i + c] = ok ? lq[4 * (int64_t)l + c] : __builtin_nan("");
+    if (phase) phase[i] = ok ? lp[l] : -1;
+}
+
 template <int CAND>
 __global__ void k_copy_cand(const int32_t *__restrict__ cand, int64_t n_rows, int32_t *__restrict__ out)
 {
@@ -554,6 +616,33 @@ ar_status normalise_cast(const float *img, int64_t n, int64_t n_pad, int n_win, 
     return AR_OK;
 }
 
+// Correlation (main and optional tail launch), merge, FP32 rescore and the
+// optional copy of the BF16-stage candidates, for CAND candidates per row.
+template <int CAND>
+ar_status run_index(ar_context *ctx, const CorrCfg &cfg, const CorrCfg &tail_cfg, bool split, const CorrLaunch &main_l,
+                    const CorrLaunch &tail_l, int n_lists, const float *images, const ar_library *lib, int64_t n_roi,
+                    int k, int32_t *top_idx, float *top_score, int32_t *cand_idx, hipStream_t s)
+{
+    const uint16_t *A = ctx->i_bf16.as<uint16_t>();
+    float *cs = ctx->i_cand_score.as<float>();
+    int32_t *ci = ctx->i_cand_idx.as<int32_t>();
+    int32_t *merged = ctx->i_merge_idx.as<int32_t>();
+    AR_TRY(launch_corr<CAND>(ctx, cfg, A, lib, main_l, cs, ci, s));
+    if (split) AR_TRY(launch_corr<CAND>(ctx, tail_cfg, A, lib, tail_l, cs, ci, s));
+    if constexpr (CAND == 64)
+        k_merge64<<<(unsigned)((n_roi + 3) / 4), 256, 0, s>>>(cs, ci, n_lists, n_roi, merged);
+    else
+        k_merge<CAND><<<(unsigned)((n_roi + 3) / 4), 256, 0, s>>>(cs, ci, n_lists, n_roi, merged);
+    AR_HIP(hipGetLastError());
+    AR_TRY(launch_rescore<CAND>(ctx, images, lib, n_roi, k, top_idx, top_score, s));
+    if (cand_idx) {
+        const int64_t n = n_roi * CAND;
+        k_copy_cand<CAND><<<(unsigned)((n + 255) / 256), 256, 0, s>>>(merged, n_roi, cand_idx);
+        AR_HIP(hipGetLastError());
+    }
+    return AR_OK;
+}
+
 }  // namespace idx
 }  // namespace ar
 
@@ -602,6 +691,49 @@ ar_status ar_library_create(ar_context *ctx, const float *ref_images, int64_t n_
     return AR_OK;
 }
 
+ar_status ar_library_prepare(ar_context *ctx, const float *ref_images, int64_t n_lib, int32_t n_win, int32_t n_dir,
+                             const double *quats, const int32_t *phase, void *stream, ar_library **out)
+{
+    AR_CHECK(out != nullptr, "out is NULL");
+    *out = nullptr;
+    AR_CHECK(quats && phase, "quats/phase must not be NULL (ar_library_create takes images alone)");
+    ar_library *lib = nullptr;
+    AR_TRY(ar_library_create(ctx, ref_images, n_lib, n_win, n_dir, stream, &lib));
+    ar_status st = lib->quats.reserve(sizeof(double) * 4 * (size_t)n_lib);
+    if (st == AR_OK) st = lib->phase.reserve(sizeof(int32_t) * (size_t)n_lib);
+    hipStream_t s = (hipStream_t)stream;
+    if (st == AR_OK) {
+        hipError_t e = hipMemcpyAsync(lib->quats.ptr, quats, sizeof(double) * 4 * (size_t)n_lib,
+                                      hipMemcpyDeviceToDevice, s);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(lib->phase.ptr, phase, sizeof(int32_t) * (size_t)n_lib, hipMemcpyDeviceToDevice, s);
+        if (e != hipSuccess) st = fail(AR_EDEVICE, "copying the orientations: %s", hipGetErrorString(e));
+    }
+    if (st != AR_OK) {
+        ar_library_destroy(lib);
+        return st;
+    }
+    lib->has_orientations = true;
+    *out = lib;
+    return AR_OK;
+}
+
+ar_status ar_library_lookup(const ar_library *lib, const int32_t *idx, int64_t n, double *quats, int32_t *phase,
+                            void *stream)
+{
+    AR_CHECK(lib != nullptr, "library is NULL");
+    AR_CHECK(lib->has_orientations, "library was created without orientations (use ar_library_prepare)");
+    AR_CHECK(n >= 0, "n must be >= 0");
+    if (n == 0) return AR_OK;
+    AR_CHECK(idx != nullptr && (quats || phase), "idx is NULL or no output given");
+    AR_CHECK((n + 255) / 256 < (int64_t)INT32_MAX, "too many entries");
+    AR_HIP(hipSetDevice(lib->ctx->device));
+    idx::k_library_lookup<<<(unsigned)((n + 255) / 256), 256, 0, (hipStream_t)stream>>>(
+        lib->quats.as<double>(), lib->phase.as<int32_t>(), lib->n_lib, idx, n, quats, phase);
+    AR_HIP(hipGetLastError());
+    return AR_OK;
+}
+
 ar_status ar_library_destroy(ar_library *lib)
 {
     if (!lib) return AR_OK;
@@ -617,7 +749,7 @@ ar_status index_orientations_ex(ar_context *ctx, const float *images, int64_t n_
     AR_CHECK(ctx && lib, "ctx/library is NULL");
     AR_CHECK(images && top_idx && top_score, "images/top_idx/top_score must not be NULL");
     AR_CHECK(n_roi >= 1 && n_roi < (int64_t)INT32_MAX - idx::kPadM, "n_roi out of range");
-    AR_CHECK(cand == 16 || cand == 32, "cand must be 16 or 32, got %d", cand);
+    AR_CHECK(cand == 16 || cand == 32 || cand == 64, "cand must be 16, 32 or 64, got %d", cand);
     AR_CHECK(k >= 1 && k <= cand, "k must be in [1, cand = %d], got %d", cand, k);
     AR_CHECK(lib->ctx == ctx, "library belongs to another context");
     AR_HIP(hipSetDevice(ctx->device));
@@ -625,9 +757,11 @@ ar_status index_orientations_ex(ar_context *ctx, const float *images, int64_t n_
     // Default tile: 256 x 256 (8 waves of 4 x 2 MFMA tiles).  With 32
     // candidates the per-thread lists no longer fit beside its accumulators
     // and spill to scratch, so cand = 32 takes 128 x 256 (8 waves of 2 x 2):
-    // 6.8 against 8.4 ms at 2000 x 20000 x 40968, identical results.
+    // 6.8 against 8.4 ms at 2000 x 20000 x 40968, identical results.  With 64
+    // the lists are wave-wide, two registers per row a wave owns: 128 x 256
+    // keeps that at 16 rows per wave.
     const idx::CorrCfg cfg = ctx->corr_tile_set ? idx::CorrCfg{ctx->corr_waves, ctx->corr_wtm, ctx->corr_wtn, ctx->corr_bk}
-                             : cand == 32 ? idx::CorrCfg{8, 2, 2, idx::kBK}
+                             : cand >= 32 ? idx::CorrCfg{8, 2, 2, idx::kBK}
                                           : idx::CorrCfg{8, 4, 2, idx::kBK};
     const int64_t m_pad = idx::round_up(n_roi, idx::kPadM);
     const int m_blocks = (int)(m_pad / cfg.bm());
@@ -686,12 +820,12 @@ ar_status index_orientations_ex(ar_context *ctx, const float *images, int64_t n_
                 split = true;
                 main_l = idx::CorrLaunch{m_blocks, main_cols, 1, main_cols, 0, 0, 0};
                 tail_l = idx::CorrLaunch{m_blocks, tail_tiles, 1, tail_tiles, (int64_t)main_cols * cfg.bn(), 0,
-                                         main_cols * (cfg.threads() / cfg.bm())};
+                                         main_cols * idx::lists_per_row(cand, cfg.threads(), cfg.bm())};
             }
         }
     }
-    const int n_lists = main_l.n_seg * (cfg.threads() / cfg.bm()) +
-                        (split ? tail_l.n_seg * (tail_cfg.threads() / tail_cfg.bm()) : 0);
+    const int n_lists = main_l.n_seg * idx::lists_per_row(cand, cfg.threads(), cfg.bm()) +
+                        (split ? tail_l.n_seg * idx::lists_per_row(cand, tail_cfg.threads(), tail_cfg.bm()) : 0);
     main_l.list_stride = tail_l.list_stride = n_lists;
 
     AR_TRY(ctx->i_bf16.reserve(sizeof(uint16_t) * (size_t)m_pad * lib->Kp));
@@ -702,36 +836,13 @@ ar_status index_orientations_ex(ar_context *ctx, const float *images, int64_t n_
 
     AR_TRY(idx::normalise_cast(images, n_roi, m_pad, lib->n_win, lib->n_dir, lib->Kp, ctx->i_inv.as<float>(),
                                ctx->i_bf16.as<uint16_t>(), s));
-    if (cand == 16) {
-        AR_TRY(idx::launch_corr<16>(ctx, cfg, ctx->i_bf16.as<uint16_t>(), lib, main_l, ctx->i_cand_score.as<float>(),
-                                    ctx->i_cand_idx.as<int32_t>(), s));
-        if (split)
-            AR_TRY(idx::launch_corr<16>(ctx, tail_cfg, ctx->i_bf16.as<uint16_t>(), lib, tail_l,
-                                        ctx->i_cand_score.as<float>(), ctx->i_cand_idx.as<int32_t>(), s));
-        idx::k_merge<16><<<(unsigned)((n_roi + 3) / 4), 256, 0, s>>>(
-            ctx->i_cand_score.as<float>(), ctx->i_cand_idx.as<int32_t>(), n_lists, n_roi, ctx->i_merge_idx.as<int32_t>());
-        AR_HIP(hipGetLastError());
-        AR_TRY(idx::launch_rescore<16>(ctx, images, lib, n_roi, k, top_idx, top_score, s));
-    } else {
-        AR_TRY(idx::launch_corr<32>(ctx, cfg, ctx->i_bf16.as<uint16_t>(), lib, main_l, ctx->i_cand_score.as<float>(),
-                                    ctx->i_cand_idx.as<int32_t>(), s));
-        if (split)
-            AR_TRY(idx::launch_corr<32>(ctx, tail_cfg, ctx->i_bf16.as<uint16_t>(), lib, tail_l,
-                                        ctx->i_cand_score.as<float>(), ctx->i_cand_idx.as<int32_t>(), s));
-        idx::k_merge<32><<<(unsigned)((n_roi + 3) / 4), 256, 0, s>>>(
-            ctx->i_cand_score.as<float>(), ctx->i_cand_idx.as<int32_t>(), n_lists, n_roi, ctx->i_merge_idx.as<int32_t>());
-        AR_HIP(hipGetLastError());
-        AR_TRY(idx::launch_rescore<32>(ctx, images, lib, n_roi, k, top_idx, top_score, s));
-    }
-    if (cand_idx) {
-        const int64_t n = n_roi * cand;
-        if (cand == 16)
-            idx::k_copy_cand<16><<<(unsigned)((n + 255) / 256), 256, 0, s>>>(ctx->i_merge_idx.as<int32_t>(), n_roi,
-                                                                             cand_idx);
-        else
-            idx::k_copy_cand<32><<<(unsigned)((n + 255) / 256), 256, 0, s>>>(ctx->i_merge_idx.as<int32_t>(), n_roi,
-                                                                             cand_idx);
-        AR_HIP(hipGetLastError());
+    switch (cand) {
+    case 16: AR_TRY(idx::run_index<16>(ctx, cfg, tail_cfg, split, main_l, tail_l, n_lists, images, lib, n_roi, k, top_idx,
+                                       top_score, cand_idx, s)); break;
+    case 32: AR_TRY(idx::run_index<32>(ctx, cfg, tail_cfg, split, main_l, tail_l, n_lists, images, lib, n_roi, k, top_idx,
+                                       top_score, cand_idx, s)); break;
+    default: AR_TRY(idx::run_index<64>(ctx, cfg, tail_cfg, split, main_l, tail_l, n_lists, images, lib, n_roi, k, top_idx,
+                                       top_score, cand_idx, s)); break;
     }
     return AR_OK;
 }
@@ -756,7 +867,7 @@ ar_status ar_index_set_tile(ar_context *ctx, int32_t waves, int32_t wtm, int32_t
 ar_status index_orientations(ar_context *ctx, const float *images, int64_t n_roi, const ar_library *lib, int32_t k,
                              int32_t *top_idx, float *top_score, void *stream)
 {
-    const int cand = k <= 16 ? 16 : 32;
+    const int cand = k <= 16 ? 16 : k <= 32 ? 32 : 64;
     return index_orientations_ex(ctx, images, n_roi, lib, k, cand, top_idx, top_score, nullptr, stream);
 }
 

@@ -45,6 +45,8 @@ _SIGS = {
     "ar_signature_plan_run": ([vp, vp, vp, i64, f32, vp, vp, vp, i32, vp], ctypes.c_int),
     "ar_library_create": ([vp, vp, i64, i32, i32, vp, P(vp)], ctypes.c_int),
     "ar_library_destroy": ([vp], ctypes.c_int),
+    "ar_library_prepare": ([vp, vp, i64, i32, i32, vp, vp, vp, P(vp)], ctypes.c_int),
+    "ar_library_lookup": ([vp, vp, i64, vp, vp, vp], ctypes.c_int),
     "index_orientations": ([vp, vp, i64, vp, i32, vp, vp, vp], ctypes.c_int),
     "ar_index_set_tile": ([vp, i32, i32, i32, i32], ctypes.c_int),
     "ar_sparse_lut_create": ([vp, vp, i32, i32, vp, i32, vp, P(i64), i32, vp, P(vp)], ctypes.c_int),
@@ -353,18 +355,41 @@ class SignaturePlan:
 
 
 class Library:
-    """ar_library: normalised BF16 reference images + norms (keeps ref alive)."""
+    """ar_library: normalised BF16 reference images + norms (keeps ref alive).
+    With quats (float64 [n_lib][4]) and phase (int32 [n_lib]) it is made by
+    ar_library_prepare and can map indexing results to orientations."""
 
-    def __init__(self, ctx: Context, ref_images: torch.Tensor):
+    def __init__(self, ctx: Context, ref_images: torch.Tensor, quats: Optional[torch.Tensor] = None,
+                 phase: Optional[torch.Tensor] = None):
         self.ctx = ctx
         _shape(ref_images, (None, None, None), "ref_images")
         n_lib, n_win, n_dir = ref_images.shape
         self.ref = ref_images
         self.n_lib, self.n_win, self.n_dir = n_lib, n_win, n_dir
+        d = ctx.device
         h = vp()
-        _call("ar_library_create", ctx.handle, _dev(ref_images, torch.float32, ctx.device, "ref_images"), n_lib,
-              n_win, n_dir, _stream(ctx.device), ctypes.byref(h))
+        if (quats is None) != (phase is None):
+            raise ValueError("give both quats and phase, or neither")
+        if quats is None:
+            _call("ar_library_create", ctx.handle, _dev(ref_images, torch.float32, d, "ref_images"), n_lib,
+                  n_win, n_dir, _stream(d), ctypes.byref(h))
+        else:
+            _shape(quats, (n_lib, 4), "quats")
+            _shape(phase, (n_lib,), "phase")
+            _call("ar_library_prepare", ctx.handle, _dev(ref_images, torch.float32, d, "ref_images"), n_lib, n_win,
+                  n_dir, _dev(quats, torch.float64, d, "quats"), _dev(phase, torch.int32, d, "phase"), _stream(d),
+                  ctypes.byref(h))
         self.handle = h
+
+    def lookup(self, idx: torch.Tensor):
+        """-> (quats float64 [*idx.shape][4], phase int32 [*idx.shape]) of the
+        entries idx (int32; -1 gives NaN and phase -1)."""
+        d = self.ctx.device
+        q = torch.empty((*idx.shape, 4), dtype=torch.float64, device=d)
+        ph = torch.empty(idx.shape, dtype=torch.int32, device=d)
+        _call("ar_library_lookup", self.handle, _dev(idx, torch.int32, d, "idx"), idx.numel(), q.data_ptr(),
+              ph.data_ptr(), _stream(d))
+        return q, ph
 
     def close(self):
         if getattr(self, "handle", None) and self.handle.value:

@@ -515,6 +515,30 @@ def planted_images(n_roi: int, n_lib: int, n_win: int, n_dir: int, seed: int, no
     return S, L, truth
 
 
+def ranked_images(n_roi: int, n_lib: int, n_win: int, n_dir: int, n_ranked: int, seed: int):
+    """Seeded image sets with a planted ranking per ROI (inputs for checking
+    long candidate lists): ROI r is a random non-negative image B_r; n_ranked
+    library rows (distinct per ROI, at random positions) are B_r * (1 - e_j
+    |n_r|) with e_j = 0.01 * 1.04^j and one noise pattern n_r per ROI that is
+    zero at every window's largest node, so that each row keeps B_r's window
+    maxima and its squared distance to B_r after per-window normalisation is
+    e_j^2 times a constant of ROI r: rank j.  The other rows are random.
+    Returns (S float32 [n_roi][n_win][n_dir], L float32 [n_lib][n_win][n_dir],
+    ranked int64 [n_roi][n_ranked], the planted rows nearest first)."""
+    if n_roi * n_ranked > n_lib:
+        raise ValueError("n_roi * n_ranked must not exceed n_lib")
+    gen = np.random.Generator(np.random.PCG64(np.random.SeedSequence([SEED_ROOT, 778, seed])))
+    L = gen.random((n_lib, n_win, n_dir), dtype=np.float32) ** 2
+    S = 0.05 + gen.random((n_roi, n_win, n_dir), dtype=np.float32) ** 2
+    rows = gen.permutation(n_lib)[:n_roi * n_ranked].reshape(n_roi, n_ranked)
+    eps = 0.01 * 1.04 ** np.arange(n_ranked)
+    for r in range(n_roi):
+        n = np.abs(gen.standard_normal((n_win, n_dir))).clip(0.0, 3.0)
+        n[np.arange(n_win), np.argmax(S[r], axis=1)] = 0.0
+        L[rows[r]] = (S[r][None] * (1.0 - eps[:, None, None] * 0.3 * n[None])).astype(np.float32)
+    return S.astype(np.float32), L, rows.astype(np.int64)
+
+
 # --------------------------------------------------------------------------
 # signature-like spherical images (indexing inputs without running the
 # signature path): peaks at the crystal directions of each window's

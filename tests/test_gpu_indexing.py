@@ -209,22 +209,26 @@ def test_index_invalid_arguments(nat, ctx):
     with pytest.raises(nat.AraulloError):
         nat.index_orientations(ctx, dev(S), lib, 0)
     with pytest.raises(nat.AraulloError):
-        nat.index_orientations(ctx, dev(S), lib, 33)
+        nat.index_orientations(ctx, dev(S), lib, 65)
     with pytest.raises(nat.AraulloError):
         nat.index_orientations_ex(ctx, dev(S), lib, 4, 20)
+    with pytest.raises(nat.AraulloError):
+        nat.index_orientations_ex(ctx, dev(S), lib, 33, 32)
+    with pytest.raises(nat.AraulloError, match="without orientations"):
+        lib.lookup(torch.zeros(3, dtype=torch.int32, device="cuda"))
 
 
 @pytest.mark.parametrize("tile", [(4, 2, 2, 32), (4, 2, 4, 32), (4, 4, 2, 32), (8, 2, 2, 32), (8, 4, 2, 32),
                                   (0, 0, 0, 0)])
 def test_every_correlation_tile_gives_identical_results(nat, ctx, tile):
     """Each score accumulates K in the same order whatever the workgroup
-    tile, so candidates, indices and FP32 scores are bit-identical, with 16
-    and with 32 candidates; (0, 0, 0, 0) is the default choice per candidate
+    tile, so candidates, indices and FP32 scores are bit-identical, with 16,
+    32 and 64 candidates; (0, 0, 0, 0) is the default choice per candidate
     count."""
     S, L, truth = synth.planted_images(333, 1500, 4, 300, seed=21)
     lib = nat.Library(ctx, dev(L))
     try:
-        for cand in (16, 32):
+        for cand in (16, 32, 64):
             nat.ar_index_set_tile(ctx, 4, 2, 2, 32)
             ref = nat.index_orientations_ex(ctx, dev(S), lib, cand, cand)
             nat.ar_index_set_tile(ctx, *tile)
@@ -240,3 +244,58 @@ def test_index_set_tile_rejects_unsupported(nat, ctx):
     for tile in [(8, 4, 4, 32), (4, 2, 2, 16), (2, 2, 2, 32), (0, 0, 0, 32)]:
         with pytest.raises(nat.AraulloError):
             nat.ar_index_set_tile(ctx, *tile)
+
+
+@pytest.mark.parametrize("k", [64, 40, 33, 17])
+def test_index_long_lists_planted_ranking(nat, ctx, orc, k):
+    """k above 32 (the paper keeps many near-best solutions per ROI, Sec.
+    3.2): 40 ROIs, each with 64 planted library rows at increasing distance
+    (ratio 1.08 between neighbours) among 5003 rows, 4 x 642 nodes.  The
+    oracle's FP64 top-64 is the planted ranking (checked first); the GPU
+    returns exactly the planted first k, its 64 BF16-stage candidates are the
+    planted set, and every score is within 1e-5 of FP64."""
+    S, L, ranked = synth.ranked_images(40, 5003, 4, 642, 64, seed=5)
+    oidx, _ = orc.index_topk(orc.normalise(S), orc.normalise(L), 64)
+    assert np.array_equal(oidx, ranked)
+    lib = nat.Library(ctx, dev(L))
+    gidx, gsc = nat.index_orientations(ctx, dev(S), lib, k)
+    gidx = gidx.cpu().numpy()
+    assert np.array_equal(gidx, ranked[:, :k])
+    check_topk(orc, S, L, gidx, gsc.cpu().numpy(), k, {})
+    _, _, gcand = nat.index_orientations_ex(ctx, dev(S), lib, k, 64)
+    gcand = gcand.cpu().numpy()
+    assert all(set(gcand[r]) == set(ranked[r]) for r in range(len(S)))
+
+
+def test_index_k64_beyond_the_library(nat, ctx, orc):
+    """k = 64 against a 40-entry library: the 40 entries in the oracle's
+    order, then index -1 and Delta +inf."""
+    S, L, truth = synth.planted_images(7, 40, 4, 300, seed=9)
+    lib = nat.Library(ctx, dev(L))
+    gidx, gsc = nat.index_orientations(ctx, dev(S), lib, 64)
+    gidx, gsc = gidx.cpu().numpy(), gsc.cpu().numpy()
+    oidx, _ = orc.index_topk(orc.normalise(S), orc.normalise(L), 40)
+    assert np.array_equal(gidx[:, :40], oidx)
+    assert np.all(gidx[:, 40:] == -1) and np.all(np.isinf(gsc[:, 40:]))
+    check_topk(orc, S, L, gidx[:, :40], gsc[:, :40], 40, {})
+
+
+def test_library_with_orientations_reports_them(nat, ctx, orc):
+    """A library prepared with orientations and phases maps indexing results
+    back to them; -1 gives a NaN quaternion and phase -1."""
+    s = synth.single_roi()
+    w = orc.windows_for(s.radius, s.nbins, s.spacings)
+    R0, q, L = reference_library(orc, s.radius, s.nbins, s.directions, w, 300, 1)
+    ph = (np.arange(300) % 2).astype(np.int32)
+    lib = nat.Library(ctx, dev(L), dev(q, torch.float64), dev(ph, torch.int32))
+    img, _ = orc.signatures(s.positions, s.centres, s.radius, s.directions, s.nbins, w)
+    gidx, _ = nat.index_orientations(ctx, dev(img.astype(np.float32)), lib, 64)
+    plain = nat.Library(ctx, dev(L))
+    pidx, _ = nat.index_orientations(ctx, dev(img.astype(np.float32)), plain, 64)
+    assert torch.equal(gidx, pidx)
+    probe = torch.cat([gidx.reshape(-1), torch.tensor([-1, 300, 299], dtype=torch.int32, device="cuda")])
+    gq, gph = lib.lookup(probe)
+    gq, gph, probe = gq.cpu().numpy(), gph.cpu().numpy(), probe.cpu().numpy()
+    ok = (probe >= 0) & (probe < 300)
+    assert np.array_equal(gq[ok], q[probe[ok]]) and np.array_equal(gph[ok], ph[probe[ok]])
+    assert np.all(np.isnan(gq[~ok])) and np.all(gph[~ok] == -1)
