@@ -50,3 +50,15 @@ def test_more_than_one_gpu_is_refused(n):
                        text=True, timeout=300)
     assert r.returncode != 0
     assert "one GPU" in (r.stdout + r.stderr)
+
+
+def test_structure_factor_accounting():
+    """Arithmetic per term: phase 1, C and S 2, the shared dot product
+    5 / n_freq, the adjoint's P and Q 12; sine and cosine are not flops.
+    Antipodal pairs of the icosphere share one evaluation."""
+    import bench
+    from paper_2009_00735_amd import synth
+    assert bench.sf_flop_per_term(4, True) == 16.25
+    assert bench.sf_flop_per_term(4, False) == 4.25
+    assert bench.evaluated_directions(synth.icosphere(3)) == 321
+    assert bench.evaluated_directions(synth.icosphere(5)) == 5121
