@@ -57,7 +57,8 @@ constexpr int kMaxWindows = 16;
 struct WindowSet {
     int n;
     int kmin, kmax;          // union of all windows
-    int rows;                // 1: n <= 4, kmax - kmin < 64 and every window at most 16 bins wide
+    int rows;                // 1: n <= 4, kmax - kmin < 64 and every window at most 16 bins wide;
+                             // 2: the same within 32 bins (two lanes per bin in the last FFT stage)
     int lo[kMaxWindows];
     int hi[kMaxWindows];
 };

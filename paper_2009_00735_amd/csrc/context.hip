@@ -87,6 +87,7 @@ ar_status make_windows(const int32_t *windows, int32_t n_win, int32_t nbins, Win
     ws->rows = n_win <= 4 && ws->kmax - ws->kmin < 64;
     for (int w = 0; w < n_win; ++w)
         if (ws->hi[w] - ws->lo[w] >= 16) ws->rows = 0;
+    if (ws->rows && ws->kmax - ws->kmin < 32) ws->rows = 2;   // two lanes per bin in the last FFT stage
     return AR_OK;
 }
 

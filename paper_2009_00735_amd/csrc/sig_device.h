@@ -268,6 +268,26 @@ __device__ __forceinline__ float bin_amplitude(const float2 *buf, int mm1, int m
     return 0.5f * sqrtf(fmaf(x2.x, x2.x, x2.y * x2.y));
 }
 
+// The same |X_k| with the two R-term sums on two lanes: lane l < 32 sums
+// Z_k, lane l + 32 sums Z_(NC-k) (its twiddles conjugated, base mmx = that
+// lane's last_base), and the partial results are exchanged across the
+// half-wavefronts.  Valid in lanes 0..31, for windows spanning at most 32
+// bins: half the multiply-adds and LDS reads of bin_amplitude.
+template <int NC>
+__device__ __forceinline__ float bin_amplitude_split(const float2 *buf, int mmx, const float2 *ftw, float2 wk)
+{
+    constexpr int NS = FftPlan<NC>::NS_LAST;
+    constexpr int R = FftPlan<NC>::R_LAST;
+    float2 a = buf[last_index<NS>(mmx, 0)];
+#pragma unroll
+    for (int t = 1; t < R; ++t) a = cmac(a, buf[last_index<NS>(mmx, t)], ftw[t - 1]);
+    const float2 b = make_float2(__shfl_xor(a.x, 32), __shfl_xor(a.y, 32));
+    const float2 e2 = make_float2(a.x + b.x, a.y - b.y);
+    const float2 o2 = make_float2(a.y + b.y, b.x - a.x);
+    const float2 x2 = cmac(e2, o2, wk);
+    return 0.5f * sqrtf(fmaf(x2.x, x2.x, x2.y * x2.y));
+}
+
 // |X_k| of the real input from the full packed transform Z (length NC,
 // swizzled): X_k = E_k + exp(-2 pi i k / NB) O_k, 0 <= k <= NC.
 template <int NC>

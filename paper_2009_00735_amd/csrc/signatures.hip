@@ -53,6 +53,7 @@ template <int LOGNB> struct LaneConsts {
     float2 ftw[R_LAST - 1];   // w^(t k), w = exp(-2 pi i / NC), k = this lane's bin
     float2 wk;                // exp(-2 pi i k / NB)
     int mm1, mm2;             // last-stage base indices of k and NC - k
+    int mmx;                  // split last stage: this lane's base (mm1 below lane 32, mm2 above)
     int rd;                   // row reduction: scratch slot read by this lane
 
     __device__ __forceinline__ void load_bin(const float2 *__restrict__ Wg, int kk)
@@ -65,11 +66,24 @@ template <int LOGNB> struct LaneConsts {
         wk = Wg[kk];
     }
 
+    // split last stage (windows within 32 bins): lane l and l + 32 share
+    // bin k = kmin + l; the upper lane sums Z_(NC-k) with conjugate twiddles
+    __device__ __forceinline__ void load_split(const float2 *__restrict__ Wg, int kk, bool upper)
+    {
+        load_bin(Wg, kk);
+        mmx = upper ? mm2 : mm1;
+        if (upper) {
+#pragma unroll
+            for (int t = 1; t < R_LAST; ++t) ftw[t - 1].y = -ftw[t - 1].y;
+        }
+    }
+
     __device__ __forceinline__ void load(const float2 *__restrict__ Wg, const WindowSet &ws, int lane)
     {
         if constexpr (FftPlan<NC>::NS_LAST > 8) tw8.load(Wg, lane);
         if constexpr (FftPlan<NC>::NS_LAST > 64) tw64.load(Wg, lane);
-        load_bin(Wg, min(ws.kmin + lane, ws.kmax));
+        if (ws.rows == 2) load_split(Wg, min(ws.kmin + (lane & 31), ws.kmax), lane >= 32);
+        else load_bin(Wg, min(ws.kmin + lane, ws.kmax));
         // row w = lane / 16 reads window w, bin lo_w + min(lane % 16, width - 1)
         rd = 0;
         const int w = lane >> 4, i = lane & 15;
@@ -155,7 +169,8 @@ __device__ __forceinline__ void finish_direction(float *A, LaneConsts<LOGNB> &lc
     fft_head<NB, NC, 1, true>(Z, lc.tw8, lc.tw64, lane);
     wave_lds_sync();
     if (ws.rows) {
-        scratch[lane] = bin_amplitude<NC>(Z, lc.mm1, lc.mm2, lc.ftw, lc.wk);
+        scratch[lane] = ws.rows == 2 ? bin_amplitude_split<NC>(Z, lc.mmx, lc.ftw, lc.wk)
+                                     : bin_amplitude<NC>(Z, lc.mm1, lc.mm2, lc.ftw, lc.wk);
         wave_lds_sync();
         const float m = row_max16(scratch[lc.rd]);
         const int w = lane >> 4;
