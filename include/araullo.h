@@ -60,10 +60,10 @@ ar_status ar_context_destroy(ar_context *ctx);
 
 /*
  * Window of DFT indices for a lattice-spacing interval [d_min, d_max]
- * (supplement, reconstruction parameters: the signature takes the highest
- * amplitude in the bin interval of a spacing range; Fig. 2 caption: spacing
- * d sits at index L/d with L = 2R + 2dR the histogram span and
- * dR = R / (nbins/2 - 1) the bin width of Eq. (1)).
+ * (supplement, reconstruction parameters: an image value is the window
+ * maximum of the amplitude spectrum over the bins of a spacing range;
+ * Fig. 2 caption: spacing d sits at index L/d with L = 2R + 2dR the
+ * histogram span and dR = R / (nbins/2 - 1) the bin width of Eq. (1)).
  * Result: k_lo = ceil(L/d_max), k_hi = floor(L/d_min), evaluated in FP64.
  * Host call.  AR_EINVAL unless nbins is a power of two in [256, 4096],
  * radius > 0, 0 < d_min <= d_max and 1 <= k_lo <= k_hi <= nbins/2.
