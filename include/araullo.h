@@ -291,7 +291,7 @@ ar_status index_orientations_ex(ar_context *ctx, const float *images, int64_t n_
  * wavefronts (4 as a 2x2 grid, 8 as 2x4), each owning wtm x wtn MFMA tiles of
  * 32x32 (workgroup tile 64 wtm x 32 wtn (waves/2)); K advances bk = 32 per
  * step.  Supported (waves, wtm, wtn, bk): (4,2,2,32) (4,2,4,32) (4,4,2,32)
- * (8,2,2,32) (8,4,2,32).  (0,0,0,0) returns to the default choice: (8,4,2,32),
+ * (4,4,4,32) (8,2,2,32) (8,4,2,32).  (0,0,0,0) returns to the default choice: (8,4,2,32),
  * a 256 x 256 tile, for 16 candidates and (8,2,2,32), 128 x 256, for 32 and
  * 64 (whose candidate lists would spill beside the larger tile's
  * accumulators).  Results do not depend on the tile: every score accumulates

@@ -209,9 +209,9 @@ __device__ __forceinline__ void fill_stage(unsigned char *smem, const uint16_t *
 template <int WGM, int WGN, int WTM, int WTN, int CAND>
 __global__ __launch_bounds__(64 * WGM * WGN) void k_corr_topk(const uint16_t *__restrict__ A, const uint16_t *__restrict__ B,
                                                         const float *__restrict__ norm2, int64_t Kp, int m_blocks,
-                                                        int n_tiles, int tiles_per_seg, int n_seg, int64_t col0,
-                                                        int list_stride, int list_base, float *__restrict__ out_s,
-                                                        int32_t *__restrict__ out_i)
+                                                        int n_tiles, int tiles_per_seg, int n_seg, int gm, int gs,
+                                                        int64_t col0, int list_stride, int list_base,
+                                                        float *__restrict__ out_s, int32_t *__restrict__ out_i)
 {
     using S = CorrShape<WGM, WGN, WTM, WTN>;
     constexpr int BM = S::BM, BN = S::BN, TPR = S::TPR, NB = S::BLK_PER_WAVE;
@@ -227,18 +227,27 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_corr_topk(const uint16_t *__
     const int lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int wm = wave % WGM, wn = wave / WGM;
-    // XCD-aware ordering: workgroup ids are dealt round-robin to the 8 XCDs;
-    // map them so that each XCD walks a contiguous range of (m_block, seg)
-    // (segment-major), i.e. its resident workgroups share library segments.
-    const int T = m_blocks * n_seg;
-    int b;
+    // XCD-aware ordering: workgroup ids are dealt round-robin to the 8 XCDs,
+    // and each XCD takes a contiguous range u of an order of the (m_block,
+    // seg) pairs that walks blocks of gm row blocks x gs segments: the
+    // workgroups resident on one XCD at a time (about gm x gs) then stream
+    // gm panels of ROI images and gs library segments through its L2
+    // instead of one panel per workgroup.
+    int mb, seg;
     {
+        const int T = m_blocks * n_seg;
         const int x = blockIdx.x & 7, j = blockIdx.x >> 3;
         const int q = T >> 3, r = T & 7;
-        b = x * q + min(x, r) + j;
+        const int u = x * q + min(x, r) + j;
+        const int full = m_blocks / gm;                   // block rows of gm row blocks
+        const int sm = min(u / (gm * n_seg), full);       // block row of u (the last may be short)
+        const int rows = sm < full ? gm : m_blocks - full * gm;
+        const int rem = u - sm * gm * n_seg;
+        const int ss = rem / (rows * gs);                 // block column (the last may be narrow)
+        const int l = rem - ss * rows * gs;
+        mb = sm * gm + l % rows;
+        seg = ss * gs + l / rows;
     }
-    const int mb = b % m_blocks;
-    const int seg = b / m_blocks;
     const int64_t m0 = (int64_t)mb * BM;
     const int t0 = seg * tiles_per_seg;
     const int t1 = min(t0 + tiles_per_seg, n_tiles);
@@ -555,7 +564,16 @@ struct CorrLaunch {
     int m_blocks, n_tiles, tiles_per_seg, n_seg;
     int64_t col0;
     int list_stride, list_base;
+    int gm = 1, gs = 1;   // XCD blocking: row blocks x segments walked together (set by launch_corr_t)
 };
+
+// Blocking of the (row block, segment) pairs for the workgroups resident on
+// one XCD at a time (`resident`): gs segments (at most 8) by gm row blocks.
+void xcd_blocking(int m_blocks, int n_seg, int resident, int &gm, int &gs)
+{
+    gs = std::max(1, std::min(n_seg, 8));
+    gm = std::max(1, std::min(m_blocks, resident / gs));
+}
 
 template <int WGM, int WGN, int WTM, int WTN, int CAND>
 ar_status launch_corr_t(ar_context *ctx, const uint16_t *A, const ar_library *lib, const CorrLaunch &L,
@@ -569,15 +587,18 @@ ar_status launch_corr_t(ar_context *ctx, const uint16_t *A, const ar_library *li
     if (lds > 65536)   // on every launch: the attribute belongs to the current device
         AR_HIP(hipFuncSetAttribute((const void *)k_corr_topk<WGM, WGN, WTM, WTN, CAND>,
                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    const int per_cu = std::max(1, std::min((int)(ctx->lds_per_block / lds), 8 / S::WAVES));
+    int gm, gs;
+    xcd_blocking(m_blocks, n_seg, per_cu * ctx->cu_count / 8, gm, gs);
     k_corr_topk<WGM, WGN, WTM, WTN, CAND><<<blocks, S::THREADS, lds, s>>>(
-        A, lib->bf16.as<uint16_t>(), lib->norm2.as<float>(), lib->Kp, m_blocks, n_tiles, tiles_per_seg, n_seg, L.col0,
-        L.list_stride, L.list_base, out_s, out_i);
+        A, lib->bf16.as<uint16_t>(), lib->norm2.as<float>(), lib->Kp, m_blocks, n_tiles, tiles_per_seg, n_seg, gm, gs,
+        L.col0, L.list_stride, L.list_base, out_s, out_i);
     AR_HIP(hipGetLastError());
     return AR_OK;
 }
 
 // (waves, wtm, wtn): 2x2 or 2x4 wave grids, K step 32
-#define AR_CORR_TILES(X) X(4, 2, 2) X(4, 2, 4) X(4, 4, 2) X(8, 2, 2) X(8, 4, 2)
+#define AR_CORR_TILES(X) X(4, 2, 2) X(4, 2, 4) X(4, 4, 2) X(4, 4, 4) X(8, 2, 2) X(8, 4, 2)
 
 bool corr_tile_supported(int waves, int wtm, int wtn, int bk)
 {

@@ -1,6 +1,7 @@
 """Single-stage workloads for profiling one kernel family under rocprofv3.
 
     python -m paper_2009_00735_amd.profile_workloads indexing [--reps 5]
+    python -m paper_2009_00735_amd.profile_workloads indexing_two_phase [--reps 2]
     python -m paper_2009_00735_amd.profile_workloads signatures [--reps 5]
     python -m paper_2009_00735_amd.profile_workloads sparse [--reps 5]
     python -m paper_2009_00735_amd.profile_workloads fsp [--reps 5]
@@ -8,6 +9,10 @@
 `indexing`: the config-2 indexing shape (2000 ROI images x 20000 references,
 4 x 10242 nodes) on seeded random non-negative images generated on the
 device; calls `index_orientations(k = 16)` `reps` times.
+
+`indexing_two_phase`: the two-phase indexing shape (20000 ROI images x
+100000 references, 4 x 10242 nodes), seeded random non-negative images
+generated on the device; `index_orientations(k = 16)` `reps` times.
 
 `signatures`: config 2 (2000 ROIs of about 1000 atoms, 10242 directions,
 1024 bins): one ROI query, then the autotuned persistent signature plan
@@ -55,6 +60,15 @@ def indexing(reps: int) -> None:
     _timed("index_orientations", lambda: nat.index_orientations(ctx, S, lib, 16), reps)
 
 
+def indexing_two_phase(reps: int) -> None:
+    ctx = nat.Context(0)
+    gen = torch.Generator(device="cuda").manual_seed(6)
+    L = torch.rand((100000, 4, 10242), device="cuda", generator=gen) ** 2
+    S = torch.rand((20000, 4, 10242), device="cuda", generator=gen) ** 2
+    lib = nat.Library(ctx, L)
+    _timed("index_orientations", lambda: nat.index_orientations(ctx, S, lib, 16), reps)
+
+
 def signatures(reps: int) -> None:
     ctx = nat.Context(0)
     s = synth.single_grain_box()
@@ -95,10 +109,11 @@ def fsp(reps: int) -> None:
 
 def main() -> None:
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
-    ap.add_argument("workload", choices=["indexing", "signatures", "sparse", "fsp"])
+    ap.add_argument("workload", choices=["indexing", "indexing_two_phase", "signatures", "sparse", "fsp"])
     ap.add_argument("--reps", type=int, default=5)
     a = ap.parse_args()
-    {"indexing": indexing, "signatures": signatures, "sparse": sparse, "fsp": fsp}[a.workload](a.reps)
+    {"indexing": indexing, "indexing_two_phase": indexing_two_phase, "signatures": signatures, "sparse": sparse,
+     "fsp": fsp}[a.workload](a.reps)
 
 
 if __name__ == "__main__":

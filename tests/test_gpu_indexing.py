@@ -218,8 +218,8 @@ def test_index_invalid_arguments(nat, ctx):
         lib.lookup(torch.zeros(3, dtype=torch.int32, device="cuda"))
 
 
-@pytest.mark.parametrize("tile", [(4, 2, 2, 32), (4, 2, 4, 32), (4, 4, 2, 32), (8, 2, 2, 32), (8, 4, 2, 32),
-                                  (0, 0, 0, 0)])
+@pytest.mark.parametrize("tile", [(4, 2, 2, 32), (4, 2, 4, 32), (4, 4, 2, 32), (4, 4, 4, 32), (8, 2, 2, 32),
+                                  (8, 4, 2, 32), (0, 0, 0, 0)])
 def test_every_correlation_tile_gives_identical_results(nat, ctx, tile):
     """Each score accumulates K in the same order whatever the workgroup
     tile, so candidates, indices and FP32 scores are bit-identical, with 16,
