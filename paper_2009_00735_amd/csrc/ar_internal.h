@@ -74,8 +74,7 @@ struct ar_context {
     int cu_count = 0;
     int lds_per_block = 0;
     // gather workspace
-    ar::DeviceBuffer g_keys, g_vals, g_keys2, g_vals2, g_cell_start, g_sorted, g_counts, g_temp,
-        g_bbox, g_offsets;
+    ar::DeviceBuffer g_keys, g_vals, g_counts32, g_cell_start, g_sorted, g_counts, g_temp, g_bbox, g_offsets;
     // gathered CSR used by the position-taking signature entry points
     ar::DeviceBuffer s_rel;
     // one channel's images in the typed-signature entry point

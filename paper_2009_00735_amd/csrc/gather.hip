@@ -3,16 +3,21 @@
 // model: one neighbour query per ROI before the projections).
 //
 // GPU design: a uniform cell grid (cell edge R/2) over the box spanned by the
-// ROI centres +- R; atoms are bucketed by a stable radix sort on the cell id
-// (so the order inside a cell is the input order), each ROI is served by one
-// wavefront that walks the rows of cells overlapping its ball (+-1 cell of
-// slack against FP32 rounding of the cell index).  Rows of cells are
-// contiguous in the sorted array, so each row is one coalesced range.
+// ROI centres +- R; atoms are bucketed by cell with a counting sort (per-cell
+// counts by atomics, an exclusive scan for the cell starts, an atomic
+// scatter, then each cell's atoms put back in input order, so the result is
+// the stable sort by cell id), each ROI is served by one wavefront that walks
+// the rows of cells overlapping its ball (+-1 cell of slack against FP32
+// rounding of the cell index).  Rows of cells are contiguous in the sorted
+// array, so each row is one coalesced range.
 // Membership is decided exactly as the paper's single-precision test:
 // fmaf(dz,dz,fmaf(dy,dy,dx*dx)) <= (float)(R*R).
-#include <hipcub/hipcub.hpp>
+#include <math.h>
+
+#include <algorithm>
 
 #include "ar_internal.h"
+#include "scan_device.h"
 
 namespace ar {
 namespace {
@@ -51,8 +56,16 @@ __global__ __launch_bounds__(1024) void k_centre_bbox(const float *__restrict__ 
 
 __device__ __forceinline__ int cell_coord(float p, float o, float inv_h) { return (int)floorf((p - o) * inv_h); }
 
+__global__ __launch_bounds__(256) void k_fill_i32(int32_t *__restrict__ a, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        a[i] = 0;
+}
+
+// Cell id of every atom (ncells for atoms outside the grid) and the count of
+// every cell.
 __global__ __launch_bounds__(256) void k_cell_keys(const float *__restrict__ pos, int64_t n, Grid g,
-                                                   uint32_t *__restrict__ keys, int32_t *__restrict__ vals)
+                                                   uint32_t *__restrict__ keys, int32_t *__restrict__ counts)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -61,20 +74,41 @@ __global__ __launch_bounds__(256) void k_cell_keys(const float *__restrict__ pos
     int cy = cell_coord(pos[3 * i + 1], g.oy, g.inv_h);
     int cz = cell_coord(pos[3 * i + 2], g.oz, g.inv_h);
     bool in = cx >= 0 && cx < g.nx && cy >= 0 && cy < g.ny && cz >= 0 && cz < g.nz;
-    keys[i] = in ? (uint32_t)(cx + g.nx * (cy + g.ny * cz)) : ncells;
-    vals[i] = (int32_t)i;
+    const uint32_t key = in ? (uint32_t)(cx + g.nx * (cy + g.ny * cz)) : ncells;
+    keys[i] = key;
+    if (in) atomicAdd(&counts[key], 1);
 }
 
-// cell_start[c] = first sorted index whose key >= c, for c in [0, ncells].
-__global__ __launch_bounds__(256) void k_cell_bounds(const uint32_t *__restrict__ keys, int64_t n,
-                                                     uint32_t ncells, int32_t *__restrict__ cell_start)
+// Each atom inside the grid to a slot of its cell (slots in arrival order,
+// fixed afterwards by k_cell_order); cursor starts at zero.
+__global__ __launch_bounds__(256) void k_cell_scatter(const uint32_t *__restrict__ keys, int64_t n, uint32_t ncells,
+                                                      const int32_t *__restrict__ cell_start,
+                                                      int32_t *__restrict__ cursor, int32_t *__restrict__ idx)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i > n) return;
-    int64_t prev = i == 0 ? -1 : (int64_t)keys[i - 1];
-    int64_t cur = i == n ? (int64_t)ncells : (int64_t)keys[i];
-    if (cur > (int64_t)ncells) cur = ncells;
-    for (int64_t c = prev + 1; c <= cur; ++c) cell_start[c] = (int32_t)i;
+    if (i >= n) return;
+    const uint32_t key = keys[i];
+    if (key >= ncells) return;
+    idx[cell_start[key] + atomicAdd(&cursor[key], 1)] = (int32_t)i;
+}
+
+// One thread per cell: its atoms back into input order (insertion sort of
+// the atom indices; cells hold tens of atoms at the R/2 cell edge).
+__global__ __launch_bounds__(256) void k_cell_order(const int32_t *__restrict__ cell_start, uint32_t ncells,
+                                                    int32_t *__restrict__ idx)
+{
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= (int64_t)ncells) return;
+    const int a0 = cell_start[c], a1 = cell_start[c + 1];
+    for (int a = a0 + 1; a < a1; ++a) {
+        const int32_t v = idx[a];
+        int b = a - 1;
+        while (b >= a0 && idx[b] > v) {
+            idx[b + 1] = idx[b];
+            --b;
+        }
+        idx[b + 1] = v;
+    }
 }
 
 // Sorted positions; the 4th component carries the atom type's bits (0 when
@@ -185,40 +219,39 @@ ar_status gather_csr(ar_context *ctx, const float *positions, const int32_t *typ
     g.ny = (int)(floor(ext[1] / h) + 1.0);
     g.nz = (int)(floor(ext[2] / h) + 1.0);
     const uint32_t ncells = (uint32_t)g.nx * g.ny * g.nz;
-    int end_bit = 1;
-    while (end_bit < 32 && ((uint64_t)1 << end_bit) <= ncells) ++end_bit;
 
+    // counting sort of the atoms by cell: counts, cell starts (exclusive
+    // scan), scatter, per-cell input order
     const int64_t n = n_atoms;
     AR_TRY(ctx->g_keys.reserve(sizeof(uint32_t) * (n + 1)));
-    AR_TRY(ctx->g_keys2.reserve(sizeof(uint32_t) * (n + 1)));
     AR_TRY(ctx->g_vals.reserve(sizeof(int32_t) * (n + 1)));
-    AR_TRY(ctx->g_vals2.reserve(sizeof(int32_t) * (n + 1)));
+    AR_TRY(ctx->g_counts32.reserve(sizeof(int32_t) * ((size_t)ncells + 1)));
     AR_TRY(ctx->g_cell_start.reserve(sizeof(int32_t) * ((size_t)ncells + 1)));
     AR_TRY(ctx->g_sorted.reserve(sizeof(float4) * (n + 1)));
-
-    size_t sort_bytes = 0, scan_bytes = 0;
-    AR_HIP(hipcub::DeviceRadixSort::SortPairs(nullptr, sort_bytes, (uint32_t *)nullptr, (uint32_t *)nullptr,
-                                              (int32_t *)nullptr, (int32_t *)nullptr, (int)n, 0, end_bit, stream));
-    AR_HIP(hipcub::DeviceScan::InclusiveSum(nullptr, scan_bytes, (int64_t *)nullptr, (int64_t *)nullptr,
-                                            (int)n_roi, stream));
-    AR_TRY(ctx->g_temp.reserve(sort_bytes > scan_bytes ? sort_bytes : scan_bytes));
-
-    if (n > 0) {
-        k_cell_keys<<<(unsigned)((n + 255) / 256), 256, 0, stream>>>(positions, n, g, ctx->g_keys.as<uint32_t>(),
-                                                                    ctx->g_vals.as<int32_t>());
-        AR_HIP(hipGetLastError());
-        size_t tb = ctx->g_temp.bytes;
-        AR_HIP(hipcub::DeviceRadixSort::SortPairs(ctx->g_temp.ptr, tb, ctx->g_keys.as<uint32_t>(),
-                                                  ctx->g_keys2.as<uint32_t>(), ctx->g_vals.as<int32_t>(),
-                                                  ctx->g_vals2.as<int32_t>(), (int)n, 0, end_bit, stream));
-    }
-    k_cell_bounds<<<(unsigned)((n + 1 + 255) / 256), 256, 0, stream>>>(ctx->g_keys2.as<uint32_t>(), n, ncells,
-                                                                      ctx->g_cell_start.as<int32_t>());
+    AR_TRY(ctx->g_temp.reserve(std::max(sizeof(int32_t) * scan::tiles(ncells), sizeof(int64_t) * scan::tiles(n_roi)) +
+                               16));
+    int32_t *counts = ctx->g_counts32.as<int32_t>();
+    int32_t *cell_start = ctx->g_cell_start.as<int32_t>();
+    const unsigned fill_blocks = (unsigned)std::min<int64_t>(((int64_t)ncells + 255) / 256, 4096);
+    k_fill_i32<<<fill_blocks, 256, 0, stream>>>(counts, ncells);
     AR_HIP(hipGetLastError());
     if (n > 0) {
-        k_sorted_pos<<<(unsigned)((n + 255) / 256), 256, 0, stream>>>(positions, types, ctx->g_vals2.as<int32_t>(),
-                                                                     ctx->g_cell_start.as<int32_t>(), ncells,
-                                                                     ctx->g_sorted.as<float4>());
+        k_cell_keys<<<(unsigned)((n + 255) / 256), 256, 0, stream>>>(positions, n, g, ctx->g_keys.as<uint32_t>(),
+                                                                    counts);
+        AR_HIP(hipGetLastError());
+    }
+    AR_TRY((scan::exclusive_scan<int32_t, int32_t>(counts, ncells, cell_start, ctx->g_temp.as<int32_t>(), stream)));
+    if (n > 0) {
+        k_fill_i32<<<fill_blocks, 256, 0, stream>>>(counts, ncells);
+        AR_HIP(hipGetLastError());
+        k_cell_scatter<<<(unsigned)((n + 255) / 256), 256, 0, stream>>>(ctx->g_keys.as<uint32_t>(), n, ncells,
+                                                                       cell_start, counts, ctx->g_vals.as<int32_t>());
+        AR_HIP(hipGetLastError());
+        k_cell_order<<<(unsigned)(((int64_t)ncells + 255) / 256), 256, 0, stream>>>(cell_start, ncells,
+                                                                                     ctx->g_vals.as<int32_t>());
+        AR_HIP(hipGetLastError());
+        k_sorted_pos<<<(unsigned)((n + 255) / 256), 256, 0, stream>>>(positions, types, ctx->g_vals.as<int32_t>(),
+                                                                     cell_start, ncells, ctx->g_sorted.as<float4>());
         AR_HIP(hipGetLastError());
     }
     const float R2 = (float)((double)radius * (double)radius);
@@ -228,11 +261,8 @@ ar_status gather_csr(ar_context *ctx, const float *positions, const int32_t *typ
                                                    centres, n_roi, radius, R2, type_mask, ctx->g_counts.as<int64_t>(),
                                                    offsets, nullptr);
     AR_HIP(hipGetLastError());
-    {
-        size_t tb = ctx->g_temp.bytes;
-        AR_HIP(hipcub::DeviceScan::InclusiveSum(ctx->g_temp.ptr, tb, ctx->g_counts.as<int64_t>(), offsets + 1,
-                                                (int)n_roi, stream));
-    }
+    AR_TRY((scan::exclusive_scan<int64_t, int64_t>(ctx->g_counts.as<int64_t>(), n_roi, offsets,
+                                                   ctx->g_temp.as<int64_t>(), stream)));
     int64_t tot = 0;
     AR_HIP(hipMemcpyAsync(&tot, offsets + n_roi, sizeof(int64_t), hipMemcpyDeviceToHost, stream));
     AR_HIP(hipStreamSynchronize(stream));

@@ -9,13 +9,15 @@
 //                    directions, divided by the atom count (FP32).
 //   2. k_best        per window, the maximum over all ROIs.
 //   3. k_keep        flag[r] = any selected window with I >= kappa * best.
-//   4. hipCUB exclusive scan of the flags (one host read of the total).
+//   4. exclusive scan of the flags (scan_device.h; one host read of the
+//                    total).
 //   5. k_emit        s^3 centres per kept ROI, in the order (kept ROI, x, y,
 //                    z); each offset h (2i + 1 - s) / (2s) is evaluated in
 //                    FP64 on the host, rounded to FP32 and added in FP32.
-#include <hipcub/hipcub.hpp>
+#include <math.h>
 
 #include "ar_internal.h"
+#include "scan_device.h"
 
 namespace ar {
 namespace roigrid {
@@ -121,10 +123,7 @@ extern "C" ar_status ar_refine_roi_grid(ar_context *ctx, const float *centres, c
     AR_TRY(best.reserve(sizeof(float) * n_win));
     AR_TRY(flag.reserve(sizeof(int32_t) * n_roi));
     AR_TRY(pos.reserve(sizeof(int64_t) * (n_roi + 1)));
-    size_t tb = 0;
-    AR_HIP(hipcub::DeviceScan::ExclusiveSum(nullptr, tb, (const int32_t *)nullptr, (int64_t *)nullptr, (int)n_roi + 1,
-                                            s));
-    AR_TRY(temp.reserve(tb));
+    AR_TRY(temp.reserve(sizeof(int64_t) * ar::scan::tiles(n_roi) + 16));
 
     k_intensity<<<(unsigned)n_roi, 256, 0, s>>>(images, counts, n_win, n_dir, I.as<float>());
     AR_HIP(hipGetLastError());
@@ -133,15 +132,14 @@ extern "C" ar_status ar_refine_roi_grid(ar_context *ctx, const float *centres, c
     k_keep<<<(unsigned)((n_roi + 255) / 256), 256, 0, s>>>(I.as<float>(), best.as<float>(), n_roi, n_win, window_mask,
                                                            kappa, flag.as<int32_t>());
     AR_HIP(hipGetLastError());
-    // exclusive scan over n_roi flags (the scan reads n_roi values)
-    AR_HIP(hipcub::DeviceScan::ExclusiveSum(temp.ptr, tb, flag.as<int32_t>(), pos.as<int64_t>(), (int)n_roi, s));
-    int64_t last_pos = 0;
-    int32_t last_flag = 0;
-    AR_HIP(hipMemcpyAsync(&last_pos, pos.as<int64_t>() + (n_roi - 1), sizeof(int64_t), hipMemcpyDeviceToHost, s));
-    AR_HIP(hipMemcpyAsync(&last_flag, flag.as<int32_t>() + (n_roi - 1), sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    // exclusive scan of the n_roi flags: pos[r] = kept ROIs before r, pos[n_roi] = kept ROIs
+    AR_TRY((ar::scan::exclusive_scan<int32_t, int64_t>(flag.as<int32_t>(), n_roi, pos.as<int64_t>(),
+                                                       temp.as<int64_t>(), s)));
+    int64_t kept = 0;
+    AR_HIP(hipMemcpyAsync(&kept, pos.as<int64_t>() + n_roi, sizeof(int64_t), hipMemcpyDeviceToHost, s));
     AR_HIP(hipStreamSynchronize(s));
     const int64_t s3 = (int64_t)split * split * split;
-    const int64_t total = (last_pos + last_flag) * s3;
+    const int64_t total = kept * s3;
     *n_out = total;
     AR_CHECK(cap >= total, "out capacity %lld is smaller than the %lld refined ROIs", (long long)cap,
              (long long)total);
