@@ -460,14 +460,14 @@ def config_legs(nat, synth, torch, dev, ctx, peaks, args):
     ms = event_ms(torch, index, reps)
     top = res["idx"][:, 0].contiguous()
     tq, tph = lib.lookup(top)
-    tq, tph = tq.cpu().numpy(), tph.cpu().numpy()
-    gq, gph = s3.grain_q[dom], s3.grain_phase[dom]
+    dis = nat.ar_disorientation_cubic(tq, torch.from_numpy(s3.grain_q[dom]).to(dev)).cpu().numpy()
+    tph = tph.cpu().numpy()
     good = share >= 0.9
-    phase_ok = tph == gph
-    dis = orc.disorientation_cubic(tq, gq)
+    phase_ok = tph == s3.grain_phase[dom]
     m = good & phase_ok
-    # FP64 oracle over the whole library for sampled ROIs: the top-1 must be
-    # the oracle's or a tie; its time is the CPU baseline (host copies excluded)
+    # CPU baseline of this leg: the FP64 oracle over the whole library for
+    # sampled ROIs (host copies excluded from its time); its result also
+    # tells whether the GPU top-1 is the oracle's or a tie
     n_chk = 4
     chk = np.sort(np.random.default_rng(41).choice(len(centres), n_chk, replace=False))
     t_o = 0.0
@@ -544,8 +544,9 @@ def config_legs(nat, synth, torch, dev, ctx, peaks, args):
     terms = float(countsr.sum()) * evaluated_directions(s3.directions) * len(F_AL)
     flop = terms * (args.refine_steps * sf_flop_per_term(4, True) + sf_flop_per_term(4, False))
     ok = ph0.cpu().numpy() == rpht
-    d0 = orc.disorientation_cubic(q0.double().cpu().numpy(), rqt)[ok]
-    d1 = orc.disorientation_cubic(q.double().cpu().numpy(), rqt)[ok]
+    rqt_d = torch.from_numpy(rqt).to(dev)
+    d0 = nat.ar_disorientation_cubic(q0.double().contiguous(), rqt_d).cpu().numpy()[ok]
+    d1 = nat.ar_disorientation_cubic(q.double().contiguous(), rqt_d).cpu().numpy()[ok]
     # oracle: FP64 finite-difference refinement, one iteration per ROI, one ROI per thread
     import concurrent.futures as cf
     n_o = threads
