@@ -83,3 +83,28 @@ def test_edge_cases(nat, ctx, orc, scan):
                                    scan["img"].shape[2], 0b11, 0.75, 2.0, 5, buf.data_ptr(), None, 1,
                                    ctypes.byref(n), nat._stream(ctx.device))
     assert st != 0 and n.value > 1 and n.value % 125 == 0
+
+
+def test_many_coarse_rois_multi_tile_scan(nat, ctx, orc):
+    """10007 coarse ROIs (the flag scan spans three 4096-entry tiles) with
+    seeded images and counts (a tenth of them empty): kept set, refined
+    centres and parents against the oracle, bit for bit away from the
+    threshold."""
+    gen = np.random.default_rng(91)
+    n = 10007
+    cen = (gen.random((n, 3)) * 40.0).astype(np.float32)
+    img = (gen.random((n, 2, 12)) ** 4 * 50.0).astype(np.float32)
+    cnt = gen.integers(1, 200, n).astype(np.int32)
+    cnt[gen.random(n) < 0.1] = 0
+    out, par = nat.ar_refine_roi_grid(ctx, dev(cen), dev(img), dev(cnt, torch.int32), 0b11, 0.3, 1.5, 2)
+    out, par = out.cpu().numpy(), par.cpu().numpy()
+    okeep, oout, opar = orc.refine_roi_grid(cen, img, cnt, 0b11, 0.3, 1.5, 2)
+    I = img.astype(np.float64).max(axis=2) / np.maximum(cnt, 1)[:, None]
+    I[cnt == 0] = 0.0
+    best = I.max(axis=0)
+    near = np.zeros(n, bool)
+    for w in range(2):
+        near |= np.abs(I[:, w] - 0.3 * best[w]) <= 1e-5 * best[w]
+    assert not near.any(), "seeded values should stay away from the threshold"
+    assert 100 < okeep.sum() < n - 100
+    assert np.array_equal(par, opar) and np.array_equal(out, oout)
