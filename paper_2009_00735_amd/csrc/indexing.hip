@@ -156,15 +156,18 @@ template <int N> __device__ __forceinline__ void wait_vmcnt()
     asm volatile("s_waitcnt vmcnt(%0)" ::"n"(N) : "memory");
 }
 
-// Wait until at most `later` steps' fills (NB instructions each) of this
-// wave are outstanding, later in [0, MAXL].
-template <int NB, int MAXL> __device__ __forceinline__ void wait_fills(int later)
+// Instruction order of one K step after its fragment reads: the NF fill
+// instructions spread evenly between the NM MFMAs (a run of MFMAs, then one
+// fill, NF times).  A wave whose fills all sit in one run stalls at their
+// issue while its SIMD's matrix core runs dry; spread out, each fill issues
+// behind MFMAs already queued.
+template <int I, int NF, int NM> __device__ __forceinline__ void fill_schedule()
 {
-    if constexpr (MAXL == 0) {
-        wait_vmcnt<0>();
-    } else {
-        if (later == MAXL) wait_vmcnt<MAXL * NB>();
-        else wait_fills<NB, MAXL - 1>(later);
+    if constexpr (I < NF) {
+        constexpr int m = NM * (I + 1) / NF - NM * I / NF;
+        if constexpr (m > 0) __builtin_amdgcn_sched_group_barrier(0x008, m, 0);   // MFMA
+        __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);                          // VMEM read
+        fill_schedule<I + 1, NF, NM>();
     }
 }
 
@@ -299,16 +302,17 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_corr_topk(const uint16_t *__
                 for (int r = 0; r < 16; ++r) acc[a][c][r] = 0.0f;
 
         __syncthreads();   // the previous tile's epilogue read Cs, which aliases the stages
+        // Every step issues exactly NB fills per wave, so the wait below is a
+        // constant: steps past the end reload step KT - 1 into the stage the
+        // previous step read (no later step reads it), and a K shorter than
+        // the ring fills the spare stages with step KT - 1 as well.
 #pragma unroll
-        for (int p = 0; p < kStages - 1; ++p)
-            if (p < KT) fill_stage<S>(smem, A, B, m0, n0, Kp, wave, lane_off, p, p);
+        for (int p = 0; p < kStages - 1; ++p) fill_stage<S>(smem, A, B, m0, n0, Kp, wave, lane_off, min(p, KT - 1), p);
         for (int kt = 0; kt < KT; ++kt) {
             // this wave's fills of step kt have landed once at most the fills
-            // of the later steps in flight remain outstanding
-            wait_fills<NB, kStages - 2>(min(kStages - 2, KT - 1 - kt));
-            barrier_only();
-            if (kt + kStages - 1 < KT)
-                fill_stage<S>(smem, A, B, m0, n0, Kp, wave, lane_off, kt + kStages - 1, (kt + kStages - 1) % kStages);
+            // of the kStages - 2 later steps in flight remain outstanding
+            wait_vmcnt<(kStages - 2) * NB>();
+            barrier_only();   // every wave's fills of step kt have landed; step kt - 1's stage is free
             const unsigned char *st = smem + (size_t)(kt % kStages) * S::STAGE;
             const unsigned char *a_rows = st + (wm * (BM / WGM)) * 64;
             const unsigned char *b_rows = st + S::A_BYTES + (wn * (BN / WGN)) * 64;
@@ -317,7 +321,12 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_corr_topk(const uint16_t *__
             read_frags<WTM, WTN>(a_rows, b_rows, r_off1, fa1, fb1);
             mfma_frags<WTM, WTN>(fa0, fb0, acc);
             mfma_frags<WTM, WTN>(fa1, fb1, acc);
+            fill_stage<S>(smem, A, B, m0, n0, Kp, wave, lane_off, min(kt + kStages - 1, KT - 1),
+                          (kt + kStages - 1) % kStages);
+            __builtin_amdgcn_sched_group_barrier(0x100, 2 * (WTM + WTN), 0);   // the fragment reads first
+            fill_schedule<0, NB, 2 * WTM * WTN>();
         }
+        wait_vmcnt<0>();   // the fills past the end land before Cs reuses the stages
         __syncthreads();
         // epilogue in 64-column passes: the waves owning the columns write their
         // scores |L|^2 - 2<S,L> to LDS, then every thread scans its share of a row
