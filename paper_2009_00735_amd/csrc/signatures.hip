@@ -93,10 +93,22 @@ template <int LOGNB> struct LaneConsts {
 };
 
 // Stage atoms [first, first + n) of a ROI into LDS (all threads of the
-// workgroup; the caller synchronises).
+// workgroup; the caller synchronises).  With q = n / 64, the first 64 q
+// atoms are stored transposed, atom l q + a at slot a * 64 + l (a < q,
+// l < 64), so the 64 lanes binning one slot group take atoms q apart in the
+// ROI's order.  That order is cell-sorted: neighbours in it are neighbours
+// in space, whose projections crowd into the same histogram bins and banks,
+// and the LDS atomics of one instruction then serialise.  The remaining
+// n - 64 q atoms (fewer than 64) keep their order at slots 64 q .. n - 1.
+// The histogram is a sum of integer counts, the same in any order.
 __device__ __forceinline__ void stage_atoms(float4 *xs, const float4 *__restrict__ rel, int64_t first, int n)
 {
-    for (int i = threadIdx.x; i < n; i += blockDim.x) xs[i] = rel[first + i];
+    const int q = n / kWave;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        const int l = q > 0 ? i / q : 0;
+        const int slot = i < q * kWave ? (i - l * q) * kWave + l : i;
+        xs[slot] = rel[first + i];
+    }
 }
 
 // Eq. (1) histogram of n staged atoms (slot a * 64 + lane), added into the
