@@ -227,6 +227,8 @@ ar_status ar_signature_plan_run(ar_plan *plan, const float *rel, const int64_t *
  * per-(entry, window) reciprocal maxima for the FP32 rescoring.
  *   ref_images device float [n_lib][n_win][n_dir]; must stay valid and
  *              unchanged while the library exists (FP32 rescoring reads it)
+ *   n_win * n_dir at most 4194240 (a 256-row panel of BF16 rows stays
+ *              below 2 GiB); larger gives AR_EINVAL
  * The library owns its BF16 copy; destroy frees it.
  */
 ar_status ar_library_create(ar_context *ctx, const float *ref_images, int64_t n_lib,

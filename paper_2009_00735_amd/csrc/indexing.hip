@@ -204,20 +204,30 @@ __device__ __forceinline__ void read_frags(const unsigned char *a_rows, const un
     for (int c = 0; c < WTN; ++c) fb[c] = *reinterpret_cast<const bf16x8 *>(b_rows + c * 32 * 64 + off);
 }
 
+// Buffer resource over a row panel of a BF16 matrix (raw addressing, no
+// range clamp inside the panel): the fills address it with a per-lane
+// 32-bit offset and a wave-uniform one, no 64-bit address arithmetic.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t panel_rsrc(const uint16_t *base)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<uint16_t *>(base), (short)0, 0x7fffffff, 0x00020000);
+}
+
 // Fill stage `stage` with K step `step`: this wave's NB blocks (block
-// wave + j * WAVES; A blocks first, then B), 16 rows each.
+// wave + j * WAVES; A blocks first, then B), 16 rows each, from the row
+// panels rA (A rows m0 ..) and rB (B rows n0 ..).  Lane i loads row i / 4
+// of its block at byte offset voff (row and swizzled chunk); the block row
+// and the step go in the uniform offset.
 template <class S>
-__device__ __forceinline__ void fill_stage(unsigned char *smem, const uint16_t *__restrict__ A,
-                                           const uint16_t *__restrict__ B, int64_t m0, int64_t n0, int64_t Kp, int wave,
-                                           int64_t lane_off, int step, int stage)
+__device__ __forceinline__ void fill_stage(unsigned char *smem, __amdgpu_buffer_rsrc_t rA, __amdgpu_buffer_rsrc_t rB,
+                                           int row_bytes, int wave, int voff, int step, int stage)
 {
     unsigned char *st = smem + (size_t)stage * S::STAGE;
 #pragma unroll
     for (int j = 0; j < S::BLK_PER_WAVE; ++j) {
         const int blk = wave + j * S::WAVES;
-        const uint16_t *base = blk < S::A_BLK ? A + (m0 + 16 * (int64_t)blk) * Kp
-                                              : B + (n0 + 16 * (int64_t)(blk - S::A_BLK)) * Kp;
-        __builtin_amdgcn_global_load_lds(base + lane_off + (int64_t)step * kBK, (lds_void *)(st + blk * 1024), 16, 0, 0);
+        const bool in_a = blk < S::A_BLK;
+        const int soff = (in_a ? blk : blk - S::A_BLK) * 16 * row_bytes + step * (kBK * 2);
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(in_a ? rA : rB, (lds_void *)(st + blk * 1024), 16, voff, soff, 0, 0);
     }
 }
 
@@ -270,7 +280,9 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_corr_topk(const uint16_t *__
     // fill side: wave-block j of a stage is block wave + j * WAVES (A blocks
     // first, then B); lane i loads row 16 * blk + i / 4, logical chunk
     // (i % 4) ^ ((i / 16) % 4), and lands at byte 16 i of the block
-    const int64_t lane_off = (int64_t)(lane >> 2) * Kp + 8 * ((lane & 3) ^ ((lane >> 4) & 3));
+    const int row_bytes = (int)(Kp * 2);
+    const int voff = (lane >> 2) * row_bytes + 16 * ((lane & 3) ^ ((lane >> 4) & 3));
+    const __amdgpu_buffer_rsrc_t rA = panel_rsrc(A + m0 * Kp);
     // read side: fragment row (lane % 32) of every 32-row group, chunk
     // 2 * slice + lane / 32 stored at chunk ^ ((lane >> 2) & 3)
     const int r_x = (lane >> 2) & 3;
@@ -293,6 +305,7 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_corr_topk(const uint16_t *__
     const int KT = (int)(Kp / kBK);
     for (int nt = t0; nt < t1; ++nt) {
         const int64_t n0 = col0 + (int64_t)nt * BN;
+        const __amdgpu_buffer_rsrc_t rB = panel_rsrc(B + n0 * Kp);
         f32x16 acc[WTM][WTN];
 #pragma unroll
         for (int a = 0; a < WTM; ++a)
@@ -307,7 +320,7 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_corr_topk(const uint16_t *__
         // previous step read (no later step reads it), and a K shorter than
         // the ring fills the spare stages with step KT - 1 as well.
 #pragma unroll
-        for (int p = 0; p < kStages - 1; ++p) fill_stage<S>(smem, A, B, m0, n0, Kp, wave, lane_off, min(p, KT - 1), p);
+        for (int p = 0; p < kStages - 1; ++p) fill_stage<S>(smem, rA, rB, row_bytes, wave, voff, min(p, KT - 1), p);
         for (int kt = 0; kt < KT; ++kt) {
             // this wave's fills of step kt have landed once at most the fills
             // of the kStages - 2 later steps in flight remain outstanding
@@ -321,7 +334,7 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_corr_topk(const uint16_t *__
             read_frags<WTM, WTN>(a_rows, b_rows, r_off1, fa1, fb1);
             mfma_frags<WTM, WTN>(fa0, fb0, acc);
             mfma_frags<WTM, WTN>(fa1, fb1, acc);
-            fill_stage<S>(smem, A, B, m0, n0, Kp, wave, lane_off, min(kt + kStages - 1, KT - 1),
+            fill_stage<S>(smem, rA, rB, row_bytes, wave, voff, min(kt + kStages - 1, KT - 1),
                           (kt + kStages - 1) % kStages);
             __builtin_amdgcn_sched_group_barrier(0x100, 2 * (WTM + WTN), 0);   // the fragment reads first
             fill_schedule<0, NB, 2 * WTM * WTN>();
@@ -698,6 +711,9 @@ ar_status ar_library_create(ar_context *ctx, const float *ref_images, int64_t n_
     AR_CHECK(ref_images != nullptr, "ref_images is NULL");
     AR_CHECK(n_lib >= 1 && n_lib < (int64_t)INT32_MAX - idx::kPadN, "n_lib out of range");
     AR_CHECK(n_win >= 1 && n_dir >= 1, "n_win and n_dir must be >= 1");
+    // the correlation addresses a 256-row panel of BF16 rows with 32-bit byte offsets
+    AR_CHECK(idx::round_up((int64_t)n_win * n_dir, idx::kPadK) * 2 * 256 < (int64_t)INT32_MAX,
+             "n_win * n_dir = %lld too large (at most %d)", (long long)n_win * n_dir, (int)(INT32_MAX / 512) & ~63);
     AR_HIP(hipSetDevice(ctx->device));
     hipStream_t s = (hipStream_t)stream;
     auto *lib = new (std::nothrow) ar_library();
