@@ -218,6 +218,20 @@ def test_index_invalid_arguments(nat, ctx):
         lib.lookup(torch.zeros(3, dtype=torch.int32, device="cuda"))
 
 
+def test_library_rejects_rows_beyond_the_panel_offsets(nat, ctx):
+    """The correlation addresses 256-row panels of BF16 rows with 32-bit
+    byte offsets, so n_win * n_dir above 4194240 is refused before any device
+    memory is touched (the image pointer is a stand-in and never read)."""
+    import ctypes
+    out = ctypes.c_void_p()
+    s = torch.cuda.current_stream().cuda_stream
+    fake = ctypes.c_void_p(256)
+    for n_win, n_dir in ((4, 1048561), (1, 4194241), (64, 65536)):   # 4 x 1048560 would be the largest accepted
+        st = nat._L.ar_library_create(ctx.handle, fake, 1, n_win, n_dir, s, ctypes.byref(out))
+        assert st == -1 and not out.value, (n_win, n_dir, st)
+        assert b"too large" in nat._L.ar_last_error()
+
+
 @pytest.mark.parametrize("tile", [(4, 2, 2, 32), (4, 2, 4, 32), (4, 4, 2, 32), (4, 4, 4, 32), (8, 2, 2, 32),
                                   (8, 4, 2, 32), (0, 0, 0, 0)])
 def test_every_correlation_tile_gives_identical_results(nat, ctx, tile):
