@@ -16,7 +16,7 @@
  *    returns an error has written nothing.  Errors: AR_EINVAL (bad argument),
  *    AR_ENOMEM (a workspace allocation failed), AR_EDEVICE (a HIP runtime
  *    error, including an earlier asynchronous fault), AR_EUNSUPPORTED.
- *    ar_last_error() returns a thread-local message for the last failure.
+ *    ar_last_error(ctx) returns a thread-local message for the last failure.
  *  - No exceptions cross this boundary.
  *  - Work is queued on `stream` (a hipStream_t passed as void*; NULL is the
  *    null stream).  Calls that must know a data-dependent size on the host
@@ -45,8 +45,10 @@ typedef struct ar_library ar_library;
 typedef struct ar_plan ar_plan;
 typedef struct ar_sparse_lut ar_sparse_lut;
 
-/* Message of the last failed call on this thread ("" if none). */
-const char *ar_last_error(void);
+/* Message of the last failed call on this thread ("" if none).  The
+ * message is kept per thread, not per context: ctx may be NULL, and any
+ * context (or none) gives the same message. */
+const char *ar_last_error(const ar_context *ctx);
 
 /* Version string of the library build. */
 const char *ar_version(void);

@@ -114,7 +114,7 @@ ar_status ar_context::twiddle_table(int nbins, const float2 **out)
 
 extern "C" {
 
-const char *ar_last_error(void) { return ar::g_error; }
+const char *ar_last_error(const ar_context *) { return ar::g_error; }
 
 const char *ar_version(void) { return "araullo-gfx950 0.1"; }
 

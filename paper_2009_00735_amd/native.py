@@ -25,7 +25,7 @@ vp, i32, i64, f32, f64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes
 P = ctypes.POINTER
 
 _SIGS = {
-    "ar_last_error": ([], ctypes.c_char_p),
+    "ar_last_error": ([vp], ctypes.c_char_p),
     "ar_version": ([], ctypes.c_char_p),
     "ar_context_create": ([ctypes.c_int, P(vp)], ctypes.c_int),
     "ar_context_destroy": ([vp], ctypes.c_int),
@@ -78,7 +78,7 @@ EXPORTED = tuple(_SIGS)
 
 class AraulloError(RuntimeError):
     def __init__(self, fn: str, status: int):
-        msg = _L.ar_last_error().decode(errors="replace")
+        msg = _L.ar_last_error(None).decode(errors="replace")
         super().__init__(f"{fn} returned {status}: {msg}")
         self.status = status
 

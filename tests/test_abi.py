@@ -66,7 +66,7 @@ def test_null_context_is_rejected():
     from paper_2009_00735_amd import native
     st = native._L.araullo_signatures(None, None, 0, None, 1, 2.0, None, 1, 1024, None, 1, None, None, None)
     assert st == -1
-    assert b"NULL" in native._L.ar_last_error()
+    assert b"NULL" in native._L.ar_last_error(None)
 
 
 class _HostCtx:

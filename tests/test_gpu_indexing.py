@@ -229,7 +229,7 @@ def test_library_rejects_rows_beyond_the_panel_offsets(nat, ctx):
     for n_win, n_dir in ((4, 1048561), (1, 4194241), (64, 65536)):   # 4 x 1048560 would be the largest accepted
         st = nat._L.ar_library_create(ctx.handle, fake, 1, n_win, n_dir, s, ctypes.byref(out))
         assert st == -1 and not out.value, (n_win, n_dir, st)
-        assert b"too large" in nat._L.ar_last_error()
+        assert b"too large" in nat._L.ar_last_error(ctx.handle)
 
 
 @pytest.mark.parametrize("tile", [(4, 2, 2, 32), (4, 2, 4, 32), (4, 4, 2, 32), (4, 4, 4, 32), (8, 2, 2, 32),
