@@ -70,7 +70,20 @@ __global__ __launch_bounds__(256) void k_normalise_cast(const float *__restrict_
     const float inv = mx > 0.0f ? 1.0f / mx : 0.0f;
     if (threadIdx.x == 0) inv_max[(size_t)row * n_win + w] = inv;
     uint16_t *dst = out + (size_t)row * Kp + (size_t)w * n_dir;
-    for (int v = threadIdx.x; v < n_dir; v += blockDim.x) dst[v] = f32_to_bf16_rne(src[v] * inv);
+    if ((n_dir & 1) == 0 && (reinterpret_cast<uintptr_t>(img) & 7) == 0) {
+        // even n_dir (every geodesic mesh: 10 * 4^k + 2 nodes) and an 8-byte
+        // aligned image array: the window's source floats and destination bf16
+        // start 8- and 4-byte aligned,
+        // so convert pairs with one 8-byte load and one 4-byte store per lane
+        const float2 *s2 = reinterpret_cast<const float2 *>(src);
+        uint32_t *d2 = reinterpret_cast<uint32_t *>(dst);
+        for (int v = threadIdx.x; v < n_dir / 2; v += blockDim.x) {
+            const float2 x = s2[v];
+            d2[v] = (uint32_t)f32_to_bf16_rne(x.x * inv) | ((uint32_t)f32_to_bf16_rne(x.y * inv) << 16);
+        }
+    } else {
+        for (int v = threadIdx.x; v < n_dir; v += blockDim.x) dst[v] = f32_to_bf16_rne(src[v] * inv);
+    }
     if (w == n_win - 1) {
         const int64_t K = (int64_t)n_win * n_dir;
         for (int64_t c = K + threadIdx.x; c < Kp; c += blockDim.x) out[(size_t)row * Kp + c] = 0;
