@@ -827,17 +827,19 @@ ar_status index_orientations_ex(ar_context *ctx, const float *images, int64_t n_
     // and spill to scratch, so cand = 32 takes 128 x 256 (8 waves of 2 x 2):
     // 6.8 against 8.4 ms at 2000 x 20000 x 40968, identical results.  With 64
     // the lists are wave-wide, two registers per row a wave owns: 128 x 256
-    // keeps that at 16 rows per wave.  Large 16-candidate calls (at least 16
-    // rounds of 256 x 256 tiles on the device) take the same tile on 4 waves
-    // of 4 x 4 MFMA tiles (one wave per SIMD, 512 registers each): 159.9-160.3
-    // against 166.1-167.7 ms at 20000 x 100000, and 4.46 against 4.40 ms at
-    // 2000 x 20000 (2.5 rounds), where the 8-wave tile stays.
+    // keeps that at 16 rows per wave.  A 16-candidate call whose segments
+    // (planned below, the same for both 256 x 256 forms) walk at least 6
+    // tiles takes the same tile on 4 waves of 4 x 4 MFMA tiles (one wave per
+    // SIMD, 512 registers each): its K loop is faster, its epilogue (one
+    // thread per row) slower, and long segments keep the lists' insertions
+    // rare.  Measured (ms per call, 8 waves / 4 waves): 20000 x 100000 (25
+    // tiles per segment) 166.1-167.7 / 159.9-160.3; 2500 x 100000 (16)
+    // 20.5-20.6 / 18.7; 5000 x 20000 (7) 10.5 / 9.8; 10000 x 40000 (5)
+    // 33.7-33.8 / 34.2; 20000 x 12500 (2) 27.6-27.8 / 28.0.
     const int64_t m_pad = idx::round_up(n_roi, idx::kPadM);
-    const int64_t big_tiles = (m_pad / 256) * (lib->n_pad / 256);
-    const idx::CorrCfg cfg = ctx->corr_tile_set ? idx::CorrCfg{ctx->corr_waves, ctx->corr_wtm, ctx->corr_wtn, ctx->corr_bk}
-                             : cand >= 32                           ? idx::CorrCfg{8, 2, 2, idx::kBK}
-                             : big_tiles >= 16 * (int64_t)ctx->cu_count ? idx::CorrCfg{4, 4, 4, idx::kBK}
-                                                                        : idx::CorrCfg{8, 4, 2, idx::kBK};
+    idx::CorrCfg cfg = ctx->corr_tile_set ? idx::CorrCfg{ctx->corr_waves, ctx->corr_wtm, ctx->corr_wtn, ctx->corr_bk}
+                       : cand >= 32       ? idx::CorrCfg{8, 2, 2, idx::kBK}
+                                          : idx::CorrCfg{8, 4, 2, idx::kBK};
     const int m_blocks = (int)(m_pad / cfg.bm());
     const int n_tiles = (int)(lib->n_pad / cfg.bn());
     // segments: a workgroup walks tiles_per_seg column tiles of one row block.
@@ -871,6 +873,7 @@ ar_status index_orientations_ex(ar_context *ctx, const float *images, int64_t n_
             }
         }
     }
+    if (!ctx->corr_tile_set && cand == 16 && tiles_per_seg >= 6) cfg = idx::CorrCfg{4, 4, 4, idx::kBK};
     // One-tile segments whose last round is partial (small calls): the whole
     // rounds run the main tile and the remaining columns a tile of the same
     // height and half the width (4 waves), all in one more round.  Every
