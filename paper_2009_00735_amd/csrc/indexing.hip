@@ -822,23 +822,24 @@ ar_status index_orientations_ex(ar_context *ctx, const float *images, int64_t n_
     AR_CHECK(lib->ctx == ctx, "library belongs to another context");
     AR_HIP(hipSetDevice(ctx->device));
     hipStream_t s = (hipStream_t)stream;
-    // Default tile: 256 x 256 (8 waves of 4 x 2 MFMA tiles).  With 32
-    // candidates the per-thread lists no longer fit beside its accumulators
-    // and spill to scratch, so cand = 32 takes 128 x 256 (8 waves of 2 x 2):
-    // 6.8 against 8.4 ms at 2000 x 20000 x 40968, identical results.  With 64
-    // the lists are wave-wide, two registers per row a wave owns: 128 x 256
-    // keeps that at 16 rows per wave.  A 16-candidate call whose segments
-    // (planned below, the same for both 256 x 256 forms) walk at least 6
-    // tiles takes the same tile on 4 waves of 4 x 4 MFMA tiles (one wave per
-    // SIMD, 512 registers each): its K loop is faster, its epilogue (one
-    // thread per row) slower, and long segments keep the lists' insertions
-    // rare.  Measured (ms per call, 8 waves / 4 waves): 20000 x 100000 (25
-    // tiles per segment) 166.1-167.7 / 159.9-160.3; 2500 x 100000 (16)
-    // 20.5-20.6 / 18.7; 5000 x 20000 (7) 10.5 / 9.8; 10000 x 40000 (5)
-    // 33.7-33.8 / 34.2; 20000 x 12500 (2) 27.6-27.8 / 28.0.
+    // Default tile: 256 x 256 (8 waves of 4 x 2 MFMA tiles).  Longer
+    // candidate lists (cand = 32 per thread, 64 per wave) do not fit beside
+    // the 8-wave tile's accumulators, so cand >= 32 takes the same 256 x 256
+    // tile on 4 waves of 4 x 4 MFMA tiles (one wave per SIMD, 512 registers
+    // each), with identical results.  Measured, ms per call (128 x 256 on 8
+    // waves / 256 x 256 on 4): k = 32: 6.5 / 5.4 at 2000 x 20000, 15.6 / 12.7
+    // at 5000 x 20000, 238 / 173 at 20000 x 100000; k = 64: 8.0 / 7.7, 19.0 /
+    // 18.0, 254 / 225.  A 16-candidate call whose segments (planned below,
+    // the same for both 256 x 256 forms) walk at least 6 tiles takes the
+    // 4-wave form too: its K loop is faster, its epilogue (one thread per
+    // row) slower, and long segments keep the lists' insertions rare.
+    // Measured (ms per call, 8 waves / 4 waves): 20000 x 100000 (25 tiles
+    // per segment) 166.1-167.7 / 159.9-160.3; 2500 x 100000 (16) 20.5-20.6
+    // / 18.7; 5000 x 20000 (7) 10.5 / 9.8; 10000 x 40000 (5) 33.7-33.8 /
+    // 34.2; 20000 x 12500 (2) 27.6-27.8 / 28.0.
     const int64_t m_pad = idx::round_up(n_roi, idx::kPadM);
     idx::CorrCfg cfg = ctx->corr_tile_set ? idx::CorrCfg{ctx->corr_waves, ctx->corr_wtm, ctx->corr_wtn, ctx->corr_bk}
-                       : cand >= 32       ? idx::CorrCfg{8, 2, 2, idx::kBK}
+                       : cand >= 32       ? idx::CorrCfg{4, 4, 4, idx::kBK}
                                           : idx::CorrCfg{8, 4, 2, idx::kBK};
     const int m_blocks = (int)(m_pad / cfg.bm());
     const int n_tiles = (int)(lib->n_pad / cfg.bn());
