@@ -5,10 +5,13 @@
 //
 // Look-up table (ar_sparse_lut_create), per phase c:
 //   1. k_ref_max        per window, the maximum of the raw reference image.
-//   2. k_strong_keys    every entry's key x / max in FP64 (+0 for -0); a
-//                       stable radix sort per phase (hipCUB, descending key,
-//                       so equal keys keep the lower flat index w * n_dir + v
-//                       first); k_strong_take keeps the first n_hat.
+//   2. k_strong_keys    every entry's key x / max in FP64 (+0 for -0); the
+//                       n_hat largest keys, equal keys by the lower flat
+//                       index w * n_dir + v, in that order: k_strong_threshold
+//                       finds the n_hat-th largest key bit by bit,
+//                       k_strong_compact keeps the keys above it and the
+//                       lowest-index ties at it, k_strong_rank places each
+//                       kept entry at its rank.
 //   3. k_window_count   strong entries per window; the host pads every
 //                       window's segment to a multiple of 4 rows.
 //   4. k_window_order   the strong entries regrouped by window (stable) into
@@ -39,7 +42,6 @@
 // (per-wave selection, then a merge in LDS).
 #include <math.h>
 
-#include <hipcub/hipcub.hpp>
 
 #include <algorithm>
 #include <new>
@@ -104,11 +106,10 @@ __global__ __launch_bounds__(256) void k_ref_max(const float *__restrict__ ref, 
 }
 
 // grid (ceil(K / 256), n_phase): key[c][e] = x / max of window e / n_dir in
-// FP64 (0 for an all-zero window), -0 made +0 so that equal keys compare
-// equal in the radix order; val[c][e] = e.
+// FP64 (0 for an all-zero window), -0 made +0 so that equal keys have equal
+// codes.
 __global__ __launch_bounds__(256) void k_strong_keys(const float *__restrict__ ref, const float *__restrict__ ref_max,
-                                                     int n_win, int n_dir, double *__restrict__ key,
-                                                     int32_t *__restrict__ val)
+                                                     int n_win, int n_dir, double *__restrict__ key)
 {
     const int c = blockIdx.y;
     const int64_t K = (int64_t)n_win * n_dir;
@@ -116,19 +117,124 @@ __global__ __launch_bounds__(256) void k_strong_keys(const float *__restrict__ r
     if (e >= K) return;
     const float m = ref_max[(size_t)c * n_win + e / n_dir];
     key[(size_t)c * K + e] = (m > 0.0f ? (double)ref[(size_t)c * K + e] / (double)m : 0.0) + 0.0;
-    val[(size_t)c * K + e] = (int32_t)e;
 }
 
-// grid (ceil(n_hat / 256), n_phase): the first n_hat of each phase's sorted run
-__global__ __launch_bounds__(256) void k_strong_take(const double *__restrict__ key, const int32_t *__restrict__ val,
-                                                     int64_t K, int n_hat, int32_t *__restrict__ strong_idx,
-                                                     float *__restrict__ strong_val)
+// Order-preserving code of a double: a larger value has a larger code.
+__device__ __forceinline__ uint64_t key_code(double x)
+{
+    const uint64_t b = (uint64_t)__double_as_longlong(x);
+    return (b >> 63) ? ~b : (b | 0x8000000000000000ull);
+}
+
+constexpr int kSelThreads = 1024;
+
+// Sum of one int over the workgroup (kSelThreads threads), returned to all.
+__device__ __forceinline__ int select_sum(int v, int *red)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    int t = 0;
+#pragma unroll
+    for (int w = 0; w < kSelThreads / 64; ++w) t += red[w];
+    __syncthreads();
+    return t;
+}
+
+// One workgroup per phase: thr[c] = the n_hat-th largest key code T (the
+// largest T with at least n_hat codes >= T, built from the top bit down) and
+// n_gt[c] = the number of codes above it (fewer than n_hat).
+__global__ __launch_bounds__(kSelThreads) void k_strong_threshold(const double *__restrict__ key, int64_t K, int n_hat,
+                                                                  uint64_t *__restrict__ thr, int32_t *__restrict__ n_gt)
+{
+    __shared__ int red[kSelThreads / 64];
+    const double *k = key + (size_t)blockIdx.x * K;
+    uint64_t T = 0;
+    for (int bit = 63; bit >= 0; --bit) {
+        const uint64_t cand = T | (1ull << bit);
+        int cnt = 0;
+        for (int64_t e = threadIdx.x; e < K; e += kSelThreads) cnt += key_code(k[e]) >= cand;
+        if (select_sum(cnt, red) >= n_hat) T = cand;
+    }
+    int gt = 0;
+    for (int64_t e = threadIdx.x; e < K; e += kSelThreads) gt += key_code(k[e]) > T;
+    gt = select_sum(gt, red);
+    if (threadIdx.x == 0) {
+        thr[blockIdx.x] = T;
+        n_gt[blockIdx.x] = gt;
+    }
+}
+
+// One workgroup per phase, entries in index order: keep every code above T
+// and the first n_hat - n_gt codes equal to it; the kept entries go, in
+// index order, to sel_key / sel_idx [c][0 .. n_hat).
+__global__ __launch_bounds__(kSelThreads) void k_strong_compact(const double *__restrict__ key, int64_t K, int n_hat,
+                                                                const uint64_t *__restrict__ thr,
+                                                                const int32_t *__restrict__ n_gt,
+                                                                double *__restrict__ sel_key, int32_t *__restrict__ sel_idx)
+{
+    __shared__ int wsel[kSelThreads / 64], weq[kSelThreads / 64];
+    const int c = blockIdx.x;
+    const double *k = key + (size_t)c * K;
+    const uint64_t T = thr[c];
+    const int ties = n_hat - n_gt[c];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const uint64_t lt = (1ull << lane) - 1;
+    int eq_base = 0, sel_base = 0;   // ties and kept entries before this chunk
+    for (int64_t c0 = 0; c0 < K; c0 += kSelThreads) {
+        const int64_t e = c0 + threadIdx.x;
+        const double x = e < K ? k[e] : 0.0;
+        const uint64_t code = e < K ? key_code(x) : 0;
+        const bool eq = e < K && code == T;
+        // tie rank in index order: ties in earlier waves of the chunk, then lanes below
+        const uint64_t beq = __ballot(eq);
+        if (lane == 0) weq[wave] = __popcll(beq);
+        __syncthreads();
+        int eq_before = eq_base + __popcll(beq & lt), eq_chunk = 0;
+        for (int w = 0; w < kSelThreads / 64; ++w) {
+            if (w < wave) eq_before += weq[w];
+            eq_chunk += weq[w];
+        }
+        const bool keep = e < K && (code > T || (eq && eq_before < ties));
+        const uint64_t bsel = __ballot(keep);
+        if (lane == 0) wsel[wave] = __popcll(bsel);
+        __syncthreads();
+        int pos = sel_base + __popcll(bsel & lt), sel_chunk = 0;
+        for (int w = 0; w < kSelThreads / 64; ++w) {
+            if (w < wave) pos += wsel[w];
+            sel_chunk += wsel[w];
+        }
+        if (keep) {
+            sel_key[(size_t)c * n_hat + pos] = x;
+            sel_idx[(size_t)c * n_hat + pos] = (int32_t)e;
+        }
+        eq_base += eq_chunk;
+        sel_base += sel_chunk;
+        __syncthreads();   // wsel / weq are rewritten by the next chunk
+    }
+}
+
+// grid (ceil(n_hat / 256), n_phase): kept entry i goes to its rank among the
+// kept ones (larger key first, equal keys by lower index).
+__global__ __launch_bounds__(256) void k_strong_rank(const double *__restrict__ sel_key,
+                                                     const int32_t *__restrict__ sel_idx, int n_hat,
+                                                     int32_t *__restrict__ strong_idx, float *__restrict__ strong_val)
 {
     const int c = blockIdx.y;
     const int i = blockIdx.x * 256 + threadIdx.x;
     if (i >= n_hat) return;
-    strong_idx[(size_t)c * n_hat + i] = val[(size_t)c * K + i];
-    strong_val[(size_t)c * n_hat + i] = (float)key[(size_t)c * K + i];
+    const double *sk = sel_key + (size_t)c * n_hat;
+    const int32_t *si = sel_idx + (size_t)c * n_hat;
+    const uint64_t ki = key_code(sk[i]);
+    const int32_t ii = si[i];
+    int rank = 0;
+    for (int j = 0; j < n_hat; ++j) {
+        const uint64_t kj = key_code(sk[j]);
+        rank += kj > ki || (kj == ki && si[j] < ii);
+    }
+    strong_idx[(size_t)c * n_hat + rank] = ii;
+    strong_val[(size_t)c * n_hat + rank] = (float)sk[i];
 }
 
 // grid (ceil(n_hat / 256), n_phase): strong entries per window (count is zeroed)
@@ -1011,37 +1117,34 @@ ar_status ar_sparse_lut_create(ar_context *ctx, const float *reference, int32_t 
         sparse::k_ref_max<<<(unsigned)(n_phase * n_win), 256, 0, s>>>(reference, n_dir, ref_max.as<float>());
         launched("k_ref_max");
     }
-    // strong lists: keys, one stable descending radix sort per phase, the first n_hat
-    ar::DeviceBuffer keys, keys_out, vals, vals_out, sort_temp;
-    size_t sort_bytes = 0;
-    if (st == AR_OK)
-        hip(hipcub::DeviceRadixSort::SortPairsDescending(nullptr, sort_bytes, (const double *)nullptr,
-                                                         (double *)nullptr, (const int32_t *)nullptr,
-                                                         (int32_t *)nullptr, (int)K, 0, 64, s),
-            "strong-entry sort");
+    // strong lists: keys, then the n_hat largest (ties by lower index) in order
+    ar::DeviceBuffer keys, sel_key, sel_idx, thr, n_gt;
     step(keys.reserve(sizeof(double) * (size_t)n_phase * K));
-    step(keys_out.reserve(sizeof(double) * (size_t)n_phase * K));
-    step(vals.reserve(sizeof(int32_t) * (size_t)n_phase * K));
-    step(vals_out.reserve(sizeof(int32_t) * (size_t)n_phase * K));
-    step(sort_temp.reserve(std::max<size_t>(sort_bytes, 256)));   // non-null: a null pointer is a size query
+    step(sel_key.reserve(sizeof(double) * nh));
+    step(sel_idx.reserve(sizeof(int32_t) * nh));
+    step(thr.reserve(sizeof(uint64_t) * n_phase));
+    step(n_gt.reserve(sizeof(int32_t) * n_phase));
     if (st == AR_OK) {
         sparse::k_strong_keys<<<dim3((unsigned)((K + 255) / 256), (unsigned)n_phase), 256, 0, s>>>(
-            reference, ref_max.as<float>(), n_win, n_dir, keys.as<double>(), vals.as<int32_t>());
+            reference, ref_max.as<float>(), n_win, n_dir, keys.as<double>());
         launched("k_strong_keys");
     }
-    for (int c = 0; c < n_phase && st == AR_OK; ++c) {
-        size_t tb = sort_bytes;
-        hip(hipcub::DeviceRadixSort::SortPairsDescending(sort_temp.ptr, tb, keys.as<double>() + (size_t)c * K,
-                                                         keys_out.as<double>() + (size_t)c * K,
-                                                         vals.as<int32_t>() + (size_t)c * K,
-                                                         vals_out.as<int32_t>() + (size_t)c * K, (int)K, 0, 64, s),
-            "strong-entry sort");
+    if (st == AR_OK) {
+        sparse::k_strong_threshold<<<(unsigned)n_phase, sparse::kSelThreads, 0, s>>>(
+            keys.as<double>(), K, n_hat, thr.as<uint64_t>(), n_gt.as<int32_t>());
+        launched("k_strong_threshold");
     }
     if (st == AR_OK) {
-        sparse::k_strong_take<<<dim3((unsigned)((n_hat + 255) / 256), (unsigned)n_phase), 256, 0, s>>>(
-            keys_out.as<double>(), vals_out.as<int32_t>(), K, n_hat, lut->strong_idx.as<int32_t>(),
+        sparse::k_strong_compact<<<(unsigned)n_phase, sparse::kSelThreads, 0, s>>>(
+            keys.as<double>(), K, n_hat, thr.as<uint64_t>(), n_gt.as<int32_t>(), sel_key.as<double>(),
+            sel_idx.as<int32_t>());
+        launched("k_strong_compact");
+    }
+    if (st == AR_OK) {
+        sparse::k_strong_rank<<<dim3((unsigned)((n_hat + 255) / 256), (unsigned)n_phase), 256, 0, s>>>(
+            sel_key.as<double>(), sel_idx.as<int32_t>(), n_hat, lut->strong_idx.as<int32_t>(),
             lut->strong_val.as<float>());
-        launched("k_strong_take");
+        launched("k_strong_rank");
     }
     if (st == AR_OK) {
         sparse::k_window_count<<<dim3((unsigned)((n_hat + 255) / 256), (unsigned)n_phase), 256, 0, s>>>(
