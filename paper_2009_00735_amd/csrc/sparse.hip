@@ -128,41 +128,42 @@ __device__ __forceinline__ uint64_t key_code(double x)
 
 constexpr int kSelThreads = 1024;
 
-// Sum of one int over the workgroup (kSelThreads threads), returned to all.
-__device__ __forceinline__ int select_sum(int v, int *red)
-{
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
-    __syncthreads();
-    int t = 0;
-#pragma unroll
-    for (int w = 0; w < kSelThreads / 64; ++w) t += red[w];
-    __syncthreads();
-    return t;
-}
-
-// One workgroup per phase: thr[c] = the n_hat-th largest key code T (the
-// largest T with at least n_hat codes >= T, built from the top bit down) and
-// n_gt[c] = the number of codes above it (fewer than n_hat).
+// One workgroup per phase: thr[c] = the n_hat-th largest key code T and
+// n_gt[c] = the number of codes above it (fewer than n_hat).  T is found one
+// 8-bit digit at a time from the top: a histogram of the digit over the codes
+// that match the digits found so far, then the digit at which the count from
+// the top reaches the number still to place.
 __global__ __launch_bounds__(kSelThreads) void k_strong_threshold(const double *__restrict__ key, int64_t K, int n_hat,
                                                                   uint64_t *__restrict__ thr, int32_t *__restrict__ n_gt)
 {
-    __shared__ int red[kSelThreads / 64];
+    __shared__ int hist[256];
+    __shared__ int pick[2];   // digit, count above it
     const double *k = key + (size_t)blockIdx.x * K;
-    uint64_t T = 0;
-    for (int bit = 63; bit >= 0; --bit) {
-        const uint64_t cand = T | (1ull << bit);
-        int cnt = 0;
-        for (int64_t e = threadIdx.x; e < K; e += kSelThreads) cnt += key_code(k[e]) >= cand;
-        if (select_sum(cnt, red) >= n_hat) T = cand;
+    uint64_t prefix = 0, mask = 0;
+    int need = n_hat;         // codes still to place at or below the prefix
+    for (int d = 7; d >= 0; --d) {
+        for (int i = threadIdx.x; i < 256; i += kSelThreads) hist[i] = 0;
+        __syncthreads();
+        for (int64_t e = threadIdx.x; e < K; e += kSelThreads) {
+            const uint64_t code = key_code(k[e]);
+            if ((code & mask) == prefix) atomicAdd(&hist[(int)((code >> (8 * d)) & 255u)], 1);
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            int above = 0, b = 255;
+            for (; b > 0 && above + hist[b] < need; --b) above += hist[b];
+            pick[0] = b;
+            pick[1] = above;
+        }
+        __syncthreads();
+        prefix |= (uint64_t)pick[0] << (8 * d);
+        mask |= (uint64_t)255u << (8 * d);
+        need -= pick[1];
+        __syncthreads();   // pick and hist are rewritten by the next digit
     }
-    int gt = 0;
-    for (int64_t e = threadIdx.x; e < K; e += kSelThreads) gt += key_code(k[e]) > T;
-    gt = select_sum(gt, red);
     if (threadIdx.x == 0) {
-        thr[blockIdx.x] = T;
-        n_gt[blockIdx.x] = gt;
+        thr[blockIdx.x] = prefix;
+        n_gt[blockIdx.x] = n_hat - need;
     }
 }
 
