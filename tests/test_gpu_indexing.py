@@ -218,6 +218,29 @@ def test_index_invalid_arguments(nat, ctx):
         lib.lookup(torch.zeros(3, dtype=torch.int32, device="cuda"))
 
 
+def test_index_unaligned_image_arrays(nat, ctx):
+    """Image arrays that start 4 bytes off an 8-byte boundary (a view one
+    float into its buffer) take the single-value path of the normalise-and-
+    cast kernel; the top-k and scores equal those from aligned arrays."""
+    S, L, truth = synth.planted_images(50, 300, 4, 64, seed=5)   # even n_dir: the paired path when aligned
+
+    def shifted(a):
+        t = dev(a)
+        buf = torch.empty(t.numel() + 1, device="cuda")
+        v = buf[1:].view(t.shape)
+        v.copy_(t)
+        assert v.data_ptr() % 8 == 4
+        return v
+
+    lib = nat.Library(ctx, dev(L))
+    lib_u = nat.Library(ctx, shifted(L))
+    a_idx, a_sc = nat.index_orientations(ctx, dev(S), lib, 16)
+    for images, library in ((shifted(S), lib), (dev(S), lib_u), (shifted(S), lib_u)):
+        b_idx, b_sc = nat.index_orientations(ctx, images, library, 16)
+        assert torch.equal(a_idx, b_idx) and torch.equal(a_sc, b_sc)
+    assert np.array_equal(a_idx[:, 0].cpu().numpy(), truth)
+
+
 def test_library_rejects_rows_beyond_the_panel_offsets(nat, ctx):
     """The correlation addresses 256-row panels of BF16 rows with 32-bit
     byte offsets, so n_win * n_dir above 4194240 is refused before any device
