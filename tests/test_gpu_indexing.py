@@ -277,6 +277,31 @@ def test_every_correlation_tile_gives_identical_results(nat, ctx, tile):
         nat.ar_index_set_tile(ctx, 0, 0, 0, 0)
 
 
+@pytest.mark.parametrize("n_win,n_dir", [(1, 40), (2, 32), (1, 64)])
+def test_short_k_every_tile_against_oracle(nat, ctx, orc, n_win, n_dir):
+    """K padded to 64 or 128 (two to four K steps, fewer than the LDS ring
+    holds): every tile, with 16, 32 and 64 candidates, returns the oracle's
+    top-k (or ties) and bit-identical results across tiles."""
+    S, L, truth = synth.planted_images(40, 700, n_win, n_dir, seed=n_dir + n_win)
+    lib = nat.Library(ctx, dev(L))
+    tiles = [(4, 2, 2, 32), (4, 2, 4, 32), (4, 4, 2, 32), (4, 4, 4, 32), (8, 2, 2, 32), (8, 4, 2, 32)]
+    try:
+        for cand in (16, 32, 64):
+            ref = None
+            for tile in tiles:
+                nat.ar_index_set_tile(ctx, *tile)
+                got = nat.index_orientations_ex(ctx, dev(S), lib, cand, cand)
+                if ref is None:
+                    ref = got
+                    rep = {}
+                    check_topk(orc, S, L, got[0].cpu().numpy(), got[1].cpu().numpy(), cand, rep)
+                else:
+                    for a, b in zip(ref, got):
+                        assert torch.equal(a, b), (cand, tile)
+    finally:
+        nat.ar_index_set_tile(ctx, 0, 0, 0, 0)
+
+
 def test_index_set_tile_rejects_unsupported(nat, ctx):
     for tile in [(8, 4, 4, 32), (4, 2, 2, 16), (2, 2, 2, 32), (0, 0, 0, 32)]:
         with pytest.raises(nat.AraulloError):
