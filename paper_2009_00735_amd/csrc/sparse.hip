@@ -10,7 +10,7 @@
 //                       index w * n_dir + v, in that order: k_strong_threshold
 //                       finds the n_hat-th largest key bit by bit,
 //                       k_strong_compact keeps the keys above it and the
-//                       lowest-index ties at it, k_strong_rank places each
+//                       lowest-index ties at it, k_strong_place puts each
 //                       kept entry at its rank.
 //   3. k_window_count   strong entries per window; the host pads every
 //                       window's segment to a multiple of 4 rows.
@@ -218,7 +218,7 @@ __global__ __launch_bounds__(kSelThreads) void k_strong_compact(const double *__
 
 // grid (ceil(n_hat / 256), n_phase): kept entry i goes to its rank among the
 // kept ones (larger key first, equal keys by lower index).
-__global__ __launch_bounds__(256) void k_strong_rank(const double *__restrict__ sel_key,
+__global__ __launch_bounds__(256) void k_strong_place(const double *__restrict__ sel_key,
                                                      const int32_t *__restrict__ sel_idx, int n_hat,
                                                      int32_t *__restrict__ strong_idx, float *__restrict__ strong_val)
 {
@@ -1142,10 +1142,10 @@ ar_status ar_sparse_lut_create(ar_context *ctx, const float *reference, int32_t 
         launched("k_strong_compact");
     }
     if (st == AR_OK) {
-        sparse::k_strong_rank<<<dim3((unsigned)((n_hat + 255) / 256), (unsigned)n_phase), 256, 0, s>>>(
+        sparse::k_strong_place<<<dim3((unsigned)((n_hat + 255) / 256), (unsigned)n_phase), 256, 0, s>>>(
             sel_key.as<double>(), sel_idx.as<int32_t>(), n_hat, lut->strong_idx.as<int32_t>(),
             lut->strong_val.as<float>());
-        launched("k_strong_rank");
+        launched("k_strong_place");
     }
     if (st == AR_OK) {
         sparse::k_window_count<<<dim3((unsigned)((n_hat + 255) / 256), (unsigned)n_phase), 256, 0, s>>>(
