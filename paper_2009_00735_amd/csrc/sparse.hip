@@ -8,7 +8,7 @@
 //   2. k_strong_keys    every entry's key x / max in FP64 (+0 for -0); the
 //                       n_hat largest keys, equal keys by the lower flat
 //                       index w * n_dir + v, in that order: k_strong_threshold
-//                       finds the n_hat-th largest key bit by bit,
+//                       finds the n_hat-th largest key a digit at a time,
 //                       k_strong_compact keeps the keys above it and the
 //                       lowest-index ties at it, k_strong_place puts each
 //                       kept entry at its rank.
