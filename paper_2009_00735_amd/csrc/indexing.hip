@@ -193,10 +193,10 @@ __device__ __forceinline__ void barrier_only()
     asm volatile("" ::: "memory");
 }
 
-// One K step of MFMAs from a stage.  Per slice of 16 along K a wave needs WTM
+// One slice of MFMAs from a stage.  Per slice of 16 along K a wave needs WTM
 // A and WTN B fragments (8 bf16 per lane: row lane % 32, chunk
-// 2 * slice + lane / 32); the second slice's fragments are read while the
-// first slice's MFMAs run.
+// 2 * slice + lane / 32); a K step reads both slices' fragments first and
+// then runs both slices' MFMAs (fill_schedule orders the step).
 template <int WTM, int WTN>
 __device__ __forceinline__ void mfma_frags(const bf16x8 (&fa)[WTM], const bf16x8 (&fb)[WTN], f32x16 (&acc)[WTM][WTN])
 {
